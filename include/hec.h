@@ -1,0 +1,189 @@
+/*
+ * hec.h -- C ABI of the MI355X (gfx950) HEC / ILU(k) / level-schedule Krylov library.
+ *
+ * The operations follow Yang, Liu, Chen, "Development of Krylov and AMG linear
+ * solvers for large-scale sparse matrices on GPUs": the HEC matrix format
+ * (Sec. 2.1), SpMV (Sec. 2.2, Alg. 1, Eq. (2)), ILU(k) (Sec. 2.4, Eq. (7)-(10),
+ * Alg. 2), the level-schedule triangular solver (Sec. 2.6, Eq. (11), Alg. 3) and
+ * the Krylov solvers (Sec. 2.7, Alg. 4 for BiCGSTAB; restarted GMRES).
+ *
+ * Conventions for every entry point:
+ *  - Host CSR input: Ap[n+1] row starts (Ap[0] == 0, non-decreasing), Aj[nnz]
+ *    column indices strictly ascending within each row and in [0, n), Ax[nnz]
+ *    values (double). These host arrays are borrowed for the duration of the
+ *    call only. Indices are 0-based int32.
+ *  - Vectors (x, b, y) are caller-owned DEVICE pointers of n elements of the
+ *    stated dtype (for example torch tensors' data_ptr()). `stream` is a
+ *    hipStream_t (NULL = the default stream).
+ *  - Handles own their device memory until the matching *_destroy call.
+ *  - Every call returns an hec_status; on failure a message for the calling
+ *    thread is available from hec_last_error(). No C++ exception crosses the
+ *    ABI. Arguments are validated on the host before any device work.
+ *  - hec_spmv and trsv_levels are asynchronous on `stream`. Setup calls and the
+ *    solvers synchronise `stream` before they return.
+ *  - Distinct handles may be used from different threads. One handle must not be
+ *    used concurrently on two streams.
+ */
+#ifndef HEC_H
+#define HEC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HEC_OK = 0,
+    HEC_ERR_INVALID_ARG = 1,   /* bad size, pointer, CSR structure, missing diagonal, ... */
+    HEC_ERR_NOMEM = 2,         /* device or host allocation failed */
+    HEC_ERR_ZERO_PIVOT = 3,    /* ILU met an exactly zero pivot */
+    HEC_ERR_BREAKDOWN = 4,     /* BiCGSTAB rho or (r0,v) became 0 (or non-finite) */
+    HEC_ERR_NOT_CONVERGED = 5, /* maxit reached; x holds the last iterate */
+    HEC_ERR_HIP = 6            /* a HIP runtime call failed */
+} hec_status;
+
+typedef enum { HEC_F64 = 0, HEC_F32 = 1 } hec_dtype;
+
+/* hec_from_csr / ilu_factor flag: also keep an FP32 copy of the values
+ * (rounded to nearest even from the FP64 values) for mixed precision. */
+#define HEC_KEEP_F32 1u
+
+/* trsv_levels `which` */
+#define HEC_LOWER 1u
+#define HEC_UPPER 2u
+#define HEC_LU 3u
+
+typedef struct hec_matrix_s *hec_matrix; /* device HEC matrix A */
+typedef struct hec_ilu_s *hec_ilu;       /* device in-place L\U factor on pattern S_k */
+typedef struct hec_levels_s *hec_levels; /* lower + upper level schedules and level-ordered factor copies */
+
+typedef struct {
+    int32_t restart;    /* GMRES restart length m (ignored by BiCGSTAB); >= 1 */
+    int32_t maxit;      /* max Arnoldi steps (GMRES) or loop passes (BiCGSTAB); >= 0 */
+    int32_t precision;  /* 0: all FP64. 1: mixed -- FP32 matrix/factor/basis storage in the
+                           inner solve, FP64 residual, dots, rotations and refinement */
+    int32_t x0_zero;    /* 1: start from x = 0 (x's contents ignored); 0: x holds x0 */
+    double rtol;        /* stop when ||b - A x|| / ||b|| <= rtol (FP64 true residual) */
+    double ir_rtol;     /* mixed: outer refinement target (<= 0: use rtol) */
+    double inner_rtol;  /* mixed: relative residual reduction asked of each inner solve */
+} hec_solve_opts;
+
+typedef struct {
+    int32_t status;      /* same value as returned */
+    int32_t iterations;  /* Arnoldi steps (GMRES, summed over refinement steps) or loop passes */
+    int32_t restarts;    /* GMRES cycles started after the first; BiCGSTAB restarts */
+    int32_t ir_steps;    /* mixed: outer refinement steps */
+    double rel_res_true; /* ||b - A x|| / ||b|| in FP64 at return */
+    double rel_res_est;  /* the solver's own recurrence estimate at its last step */
+    double seconds;      /* wall time of the call */
+} hec_solve_info;
+
+/* ---------------------------------------------------------------- HEC matrix */
+
+/* Sec. 2.1: build the HEC form of A on the device -- an ELL slab of width K
+ * stored column-major with leading dimension ld = n rounded up to 256 (entry s
+ * of row i at s*ld + i), plus the rest of every longer row in CSR (rem_ptr[n+1],
+ * rem_col, rem_val). K = ell_width if ell_width >= 0, else min(20, longest row)
+ * (the paper's recommended boundary), never above the longest row; the first K
+ * entries of each row go to the slab. Empty slab slots of row i hold (col i,
+ * value 0); rows n..ld-1 hold (col 0, value 0). ell_width = 0 gives plain CSR.
+ * flags: HEC_KEEP_F32. Errors: INVALID_ARG for n < 0, null pointers or a
+ * malformed CSR (unsorted or duplicate columns, out-of-range index). */
+hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax,
+                        int32_t ell_width, uint32_t flags, void *stream, hec_matrix *out);
+
+/* Sizes of a HEC matrix (any output pointer may be NULL). */
+hec_status hec_info(hec_matrix A, int32_t *n, int32_t *K, int32_t *ld, int64_t *nnz,
+                    int64_t *nnz_rem);
+
+/* Copy the HEC arrays to caller host buffers of sizes K*ld, K*ld, n+1, nnz_rem,
+ * nnz_rem (for bit-exact checks). ell_val32/rem_val32 may be NULL; when given,
+ * the matrix must have been built with HEC_KEEP_F32. */
+hec_status hec_export(hec_matrix A, int32_t *ell_col, double *ell_val, int32_t *rem_ptr,
+                      int32_t *rem_col, double *rem_val, float *ell_val32, float *rem_val32);
+
+/* Eq. (2) with Alg. 1's order (ELL part, then the CSR remainder):
+ * y = alpha*A*x + beta*y. vals selects the FP64 values or the FP32 copy; xt and
+ * yt the vector dtypes. Accumulation is in FP64 when the values are FP64, in
+ * FP32 otherwise. beta == 0 does not read y. x and y must not overlap. */
+hec_status hec_spmv(hec_matrix A, hec_dtype vals, double alpha, const void *x, hec_dtype xt,
+                    double beta, void *y, hec_dtype yt, void *stream);
+
+hec_status hec_destroy(hec_matrix A);
+
+/* ---------------------------------------------------------------- ILU(k) */
+
+/* Sec. 2.4, Eq. (7)-(10), Alg. 2: incomplete LU with level of fill k. The
+ * pattern S_k = {(i,j): level <= k} is built on the host (Eq. (9)-(10)); the
+ * numeric elimination (for each row i and each p < i in S_k ascending:
+ * a_ip /= a_pp; a_ij -= a_ip a_pj for (i,j) in S_k) runs on the device, rows
+ * grouped by the Eq. (11) levels of L. L (unit diagonal implied) and U share one
+ * array, as in the paper. Every row must store its diagonal (INVALID_ARG
+ * otherwise); an exactly zero pivot gives ZERO_PIVOT. flags: HEC_KEEP_F32. */
+hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k,
+                      uint32_t flags, void *stream, hec_ilu *out);
+
+hec_status ilu_info(hec_ilu M, int32_t *n, int64_t *nnz);
+
+/* Copy the factor to host CSR buffers (n+1, nnz, nnz): L strictly below the
+ * diagonal, U on and above it, columns ascending. */
+hec_status ilu_export(hec_ilu M, int32_t *LUp, int32_t *LUj, double *LUx);
+
+hec_status ilu_destroy(hec_ilu M);
+
+/* ---------------------------------------------------------------- level schedule */
+
+/* Sec. 2.6, Eq. (11), Alg. 3: levels of L (l(i) = 1 + max l(j) over stored
+ * j < i, starting from 0) and, mirrored, of U (j > i, rows from n-1 down),
+ * stored 0-based; rows grouped by level in ascending row order (level_ptr +
+ * perm). Also builds the level-ordered device copies of L and U used by
+ * trsv_levels. The schedule refers to M's pattern and values at call time. */
+hec_status level_schedule(hec_ilu M, hec_levels *out);
+
+hec_status levels_info(hec_levels lv, int32_t *n, int32_t *nlev_lower, int32_t *nlev_upper);
+
+/* Copy the schedules to host buffers: ptr arrays of nlev+1, perm arrays of n. */
+hec_status levels_export(hec_levels lv, int32_t *lower_ptr, int32_t *lower_perm,
+                         int32_t *upper_ptr, int32_t *upper_perm);
+
+hec_status levels_destroy(hec_levels lv);
+
+/* Alg. 3: solve with the factor level by level. which = HEC_LOWER: x = L^{-1} b
+ * (unit diagonal); HEC_UPPER: x = U^{-1} b; HEC_LU: x = U^{-1} L^{-1} b (the
+ * preconditioner solve M x = b of Eq. (7)-(8)). prec selects FP64 factor and
+ * vectors, or the FP32 factor copy (ilu_factor with HEC_KEEP_F32) with FP32
+ * vectors. b and x are device vectors of n elements and must not overlap.
+ * Every level's rows are solved in parallel; a row starts as soon as the rows it
+ * depends on are done. */
+hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec, const void *b,
+                       void *x, void *stream);
+
+/* ---------------------------------------------------------------- Krylov solvers */
+
+/* Restarted GMRES(m) (Sec. 2.7), right-preconditioned with M = LU:
+ * x = x0 + M^{-1} V y minimising ||b - A x|| over each cycle; classical
+ * Gram-Schmidt applied twice, Givens rotations, convergence decided by the FP64
+ * true residual. precision = 1: iterative refinement in FP64 around inner
+ * GMRES solves that use the FP32 copies of A and of the factor (both handles
+ * built with HEC_KEEP_F32) and an FP32 Krylov basis. b, x: device FP64.
+ * ||b|| == 0 gives x = 0, OK, 0 iterations. On NOT_CONVERGED x holds the last
+ * iterate. `info` may be NULL. */
+hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                       const hec_solve_opts *opts, hec_solve_info *info, void *stream);
+
+/* Preconditioned BiCGSTAB exactly as Alg. 4 (shadow residual r0 = b - A x0),
+ * "||s|| / ||r|| satisfied" read as <= rtol * ||b||; rho == 0 or (r0, v) == 0 is
+ * a breakdown, after which the method restarts once from the current x before
+ * reporting BREAKDOWN. FP64 only (precision must be 0). */
+hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                          const hec_solve_opts *opts, hec_solve_info *info, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEC_H */

@@ -123,8 +123,8 @@ void orc_hec_fill(int n, const int *Ap, const int *Aj, const double *Ax, int K, 
  * Output: the factored rows in CSR (LUp, LUj, LUx, and each kept entry's level
  * in LUlev), allocated here and released with orc_free. L is the strict lower
  * part (unit diagonal implied), U the upper part with the diagonal.
- * Zero pivot (a_pp == 0 exactly) returns ORC_ZERO_PIVOT; a missing diagonal
- * returns ORC_INVALID. */
+ * A zero pivot (u_ii == 0 exactly, whether or not a later row uses it)
+ * returns ORC_ZERO_PIVOT; a missing diagonal returns ORC_INVALID. */
 int orc_iluk(int n, const int *Ap, const int *Aj, const double *Ax, int k,
              int **LUp_out, int **LUj_out, double **LUx_out, int **LUlev_out)
 {
@@ -206,6 +206,9 @@ int orc_iluk(int n, const int *Ap, const int *Aj, const double *Ax, int k,
             ++nz;
         }
         LUp[i + 1] = (int)nz;
+        /* U_ii is the divisor of the backward substitution: a zero pivot is an
+         * error even in a row that no later row eliminates with */
+        if (status == ORC_OK && LUx[diag[i]] == 0.0) status = ORC_ZERO_PIVOT;
     }
     free(w); free(lev); free(next); free(diag);
     if (status != ORC_OK) {

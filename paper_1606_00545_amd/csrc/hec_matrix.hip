@@ -1,0 +1,380 @@
+// HEC matrix: conversion from CSR (Sec. 2.1) and SpMV (Sec. 2.2, Alg. 1, Eq. (2)).
+//
+// Layout in HBM: the ELL slab is column-major (entry s of row i at s*ld + i,
+// ld = n rounded up to 256), so a wavefront's load of slot s touches 64
+// consecutive values: one 512-byte (FP64) or 256-byte (FP32/int32) segment.
+// The remainder is plain CSR plus a list of the rows that have one.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "hec_internal.hpp"
+
+namespace hec {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax) {
+    if (n < 0) fail(HEC_ERR_INVALID_ARG, "n < 0");
+    if (!Ap) fail(HEC_ERR_INVALID_ARG, "Ap is NULL");
+    if (Ap[0] != 0) fail(HEC_ERR_INVALID_ARG, "Ap[0] != 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (Ap[i + 1] < Ap[i]) fail(HEC_ERR_INVALID_ARG, "Ap is not non-decreasing at row " + std::to_string(i));
+    if (Ap[n] > 0 && (!Aj || !Ax)) fail(HEC_ERR_INVALID_ARG, "Aj or Ax is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+            int32_t j = Aj[e];
+            if (j < 0 || j >= n)
+                fail(HEC_ERR_INVALID_ARG, "column index out of range in row " + std::to_string(i));
+            if (e > Ap[i] && j <= Aj[e - 1])
+                fail(HEC_ERR_INVALID_ARG, "columns not strictly ascending in row " + std::to_string(i));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ conversion kernels
+
+// One thread per slab row i < ld: writes the K slots of row i (coalesced across i).
+__global__ __launch_bounds__(256) void k_hec_fill_ell(int32_t n, int32_t K, int32_t ld,
+                                                      const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj,
+                                                      const double *__restrict__ Ax,
+                                                      int32_t *__restrict__ ell_col,
+                                                      double *__restrict__ ell_val,
+                                                      float *__restrict__ ell_val32) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld) return;
+    int32_t a = 0, len = 0;
+    if (i < n) {
+        a = Ap[i];
+        len = Ap[i + 1] - a;
+    }
+    for (int32_t s = 0; s < K; ++s) {
+        size_t slot = (size_t)s * ld + i;
+        int32_t c;
+        double v;
+        if (s < len) {
+            c = Aj[a + s];
+            v = Ax[a + s];
+        } else {
+            c = i < n ? i : 0;
+            v = 0.0;
+        }
+        ell_col[slot] = c;
+        ell_val[slot] = v;
+        if (ell_val32) ell_val32[slot] = (float)v;  // round to nearest even
+    }
+}
+
+// One thread per row: copies entries K.. of row i to the remainder CSR.
+__global__ __launch_bounds__(256) void k_hec_fill_rem(int32_t n, int32_t K,
+                                                      const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj,
+                                                      const double *__restrict__ Ax,
+                                                      const int32_t *__restrict__ rem_ptr,
+                                                      int32_t *__restrict__ rem_col,
+                                                      double *__restrict__ rem_val,
+                                                      float *__restrict__ rem_val32) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t src = Ap[i] + K, end = Ap[i + 1], dst = rem_ptr[i];
+    for (; src < end; ++src, ++dst) {
+        rem_col[dst] = Aj[src];
+        double v = Ax[src];
+        rem_val[dst] = v;
+        if (rem_val32) rem_val32[dst] = (float)v;
+    }
+}
+
+// ------------------------------------------------------------------ SpMV kernels
+
+// ELL part (Alg. 1, first loop): one thread per row, slab loads are
+// non-temporal (streamed once), x is gathered through the caches.
+// y[i] = alpha * sum_s val[s*ld+i] * x[col[s*ld+i]] + beta * z[i].
+template <class VT, class XT, class YT, class AT>
+__global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t K, int32_t ld,
+                                                  const int32_t *__restrict__ col,
+                                                  const VT *__restrict__ val, AT alpha,
+                                                  const XT *__restrict__ x, AT beta,
+                                                  const YT *z, YT *y, const int32_t *skip) {
+    if (skip && *skip) return;
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t *c = col + i;
+    const VT *v = val + i;
+    AT acc = 0;
+    int32_t s = 0;
+    for (; s + 4 <= K; s += 4) {
+        int32_t j0 = __builtin_nontemporal_load(c + (size_t)(s + 0) * ld);
+        int32_t j1 = __builtin_nontemporal_load(c + (size_t)(s + 1) * ld);
+        int32_t j2 = __builtin_nontemporal_load(c + (size_t)(s + 2) * ld);
+        int32_t j3 = __builtin_nontemporal_load(c + (size_t)(s + 3) * ld);
+        VT a0 = __builtin_nontemporal_load(v + (size_t)(s + 0) * ld);
+        VT a1 = __builtin_nontemporal_load(v + (size_t)(s + 1) * ld);
+        VT a2 = __builtin_nontemporal_load(v + (size_t)(s + 2) * ld);
+        VT a3 = __builtin_nontemporal_load(v + (size_t)(s + 3) * ld);
+        XT x0 = x[j0], x1 = x[j1], x2 = x[j2], x3 = x[j3];
+        acc += (AT)a0 * (AT)x0;
+        acc += (AT)a1 * (AT)x1;
+        acc += (AT)a2 * (AT)x2;
+        acc += (AT)a3 * (AT)x3;
+    }
+    for (; s < K; ++s) {
+        int32_t j = __builtin_nontemporal_load(c + (size_t)s * ld);
+        VT a = __builtin_nontemporal_load(v + (size_t)s * ld);
+        acc += (AT)a * (AT)x[j];
+    }
+    AT r = alpha * acc;
+    if (beta != (AT)0) r += beta * (AT)z[i];
+    y[i] = (YT)r;
+}
+
+// CSR remainder (Alg. 1, second loop): LANES lanes per row (a sub-wavefront),
+// lanes stride the row, then a butterfly reduction inside the group.
+// first == true (no ELL part): y = alpha*t + beta*z; otherwise y += alpha*t.
+template <class VT, class XT, class YT, class AT, int LANES>
+__global__ __launch_bounds__(256) void k_spmv_rem(int32_t nrows, const int32_t *__restrict__ rows,
+                                                  const int32_t *__restrict__ rptr,
+                                                  const int32_t *__restrict__ rcol,
+                                                  const VT *__restrict__ rval, AT alpha,
+                                                  const XT *__restrict__ x, AT beta, const YT *z,
+                                                  YT *y, bool first, const int32_t *skip) {
+    if (skip && *skip) return;
+    int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t grp = gid / LANES;  // uniform over the LANES lanes of the group
+    int32_t lane = threadIdx.x % LANES;
+    if (grp >= nrows) return;
+    int32_t r = rows[grp];
+    int32_t e0 = rptr[r], e1 = rptr[r + 1];
+    AT acc = 0;
+    for (int32_t e = e0 + lane; e < e1; e += LANES)
+        acc += (AT)__builtin_nontemporal_load(rval + e) * (AT)x[__builtin_nontemporal_load(rcol + e)];
+#pragma unroll
+    for (int off = LANES / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LANES);
+    if (lane == 0) {
+        if (first) {
+            AT t = alpha * acc;
+            if (beta != (AT)0) t += beta * (AT)z[r];
+            y[r] = (YT)t;
+        } else {
+            y[r] = (YT)((AT)y[r] + alpha * acc);
+        }
+    }
+}
+
+template <class VT, class XT, class YT, class AT, int LANES>
+static void launch_rem(const hec_matrix_s &A, const VT *rval, AT alpha, const XT *x, AT beta,
+                       const YT *z, YT *y, bool first, hipStream_t s, const int32_t *skip) {
+    size_t threads = (size_t)A.n_rem_rows * LANES;
+    k_spmv_rem<VT, XT, YT, AT, LANES><<<ceil_div(threads, 256), 256, 0, s>>>(
+        A.n_rem_rows, A.rem_rows.get(), A.rem_ptr.get(), A.rem_col.get(), rval, alpha, x, beta, z, y,
+        first, skip);
+}
+
+template <class VT, class XT, class YT>
+void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta_d, const YT *z, YT *y,
+                 hipStream_t s, const int32_t *skip) {
+    using AT = VT;  // accumulate in the value precision
+    AT alpha = (AT)alpha_d, beta = (AT)beta_d;
+    if (A.n == 0) return;
+    const VT *ev, *rv;
+    if constexpr (sizeof(VT) == 8) {
+        ev = (const VT *)A.ell_val.get();
+        rv = (const VT *)A.rem_val.get();
+    } else {
+        ev = (const VT *)A.ell_val32.get();
+        rv = (const VT *)A.rem_val32.get();
+    }
+    bool first = A.K == 0;
+    if (!first) {
+        k_spmv_ell<VT, XT, YT, AT><<<ceil_div(A.n, 256), 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev,
+                                                                     alpha, x, beta, z, y, skip);
+        HEC_CHECK_LAUNCH();
+    }
+    if (A.n_rem_rows > 0) {
+        switch (A.rem_lanes) {
+            case 2: launch_rem<VT, XT, YT, AT, 2>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+            case 4: launch_rem<VT, XT, YT, AT, 4>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+            case 8: launch_rem<VT, XT, YT, AT, 8>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+            case 16: launch_rem<VT, XT, YT, AT, 16>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+            case 32: launch_rem<VT, XT, YT, AT, 32>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+            default: launch_rem<VT, XT, YT, AT, 64>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
+        }
+        HEC_CHECK_LAUNCH();
+    }
+}
+
+template void spmv_launch<double, double, double>(const hec_matrix_s &, double, const double *, double,
+                                                  const double *, double *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<double, float, double>(const hec_matrix_s &, double, const float *, double,
+                                                  const double *, double *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<double, double, float>(const hec_matrix_s &, double, const double *, double,
+                                                  const float *, float *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<double, float, float>(const hec_matrix_s &, double, const float *, double,
+                                                  const float *, float *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<float, float, float>(const hec_matrix_s &, double, const float *, double,
+                                                  const float *, float *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<float, double, double>(const hec_matrix_s &, double, const double *, double,
+                                                  const double *, double *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<float, float, double>(const hec_matrix_s &, double, const float *, double,
+                                                  const double *, double *, hipStream_t,
+                                                  const int32_t *);
+template void spmv_launch<float, double, float>(const hec_matrix_s &, double, const double *, double,
+                                                  const float *, float *, hipStream_t,
+                                                  const int32_t *);
+
+}  // namespace hec
+
+using namespace hec;
+
+extern "C" {
+
+const char *hec_last_error(void) { return g_last_error.c_str(); }
+
+hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax,
+                        int32_t ell_width, uint32_t flags, void *stream, hec_matrix *out) {
+    return guarded([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        validate_csr(n, Ap, Aj, Ax);
+        if (flags & ~HEC_KEEP_F32) fail(HEC_ERR_INVALID_ARG, "unknown flags");
+        hipStream_t s = as_stream(stream);
+        auto A = std::make_unique<hec_matrix_s>();
+        A->n = n;
+        A->nnz = Ap[n];
+        int32_t maxrow = 0;
+        for (int32_t i = 0; i < n; ++i) maxrow = std::max(maxrow, Ap[i + 1] - Ap[i]);
+        int32_t K = ell_width >= 0 ? ell_width : 20;
+        A->K = std::min(K, maxrow);
+        A->ld = (int32_t)(((int64_t)n + 255) / 256 * 256);
+        A->has_f32 = (flags & HEC_KEEP_F32) != 0;
+        // remainder row pointer and row list (host prefix sum)
+        std::vector<int32_t> rptr(n + 1);
+        std::vector<int32_t> rrows;
+        int64_t r = 0;
+        rptr[0] = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t len = Ap[i + 1] - Ap[i];
+            int32_t extra = len > A->K ? len - A->K : 0;
+            if (A->K == 0 || extra > 0) rrows.push_back(i);
+            r += extra;
+            rptr[i + 1] = (int32_t)r;
+        }
+        A->nnz_rem = r;
+        A->n_rem_rows = (int32_t)rrows.size();
+        {
+            // lanes per remainder row: the power of two nearest the mean remainder length
+            double mean = rrows.empty() ? 0.0 : (double)r / rrows.size();
+            int lanes = 2;
+            while (lanes < 64 && lanes * 1.5 < mean) lanes *= 2;
+            A->rem_lanes = lanes;
+        }
+        size_t slab = (size_t)A->K * A->ld;
+        A->ell_col.alloc(slab);
+        A->ell_val.alloc(slab);
+        if (A->has_f32) A->ell_val32.alloc(slab);
+        A->rem_ptr.alloc(n + 1);
+        A->rem_col.alloc(r);
+        A->rem_val.alloc(r);
+        if (A->has_f32) A->rem_val32.alloc(r);
+        A->rem_rows.alloc(rrows.size());
+        A->rem_ptr.upload(rptr.data(), n + 1, s);
+        A->rem_rows.upload(rrows.data(), rrows.size(), s);
+        // stage the CSR on the device and scatter it into the two parts
+        DevBuf<int32_t> dAp(n + 1), dAj(A->nnz);
+        DevBuf<double> dAx(A->nnz);
+        dAp.upload(Ap, n + 1, s);
+        dAj.upload(Aj, A->nnz, s);
+        dAx.upload(Ax, A->nnz, s);
+        if (slab) {
+            k_hec_fill_ell<<<ceil_div(A->ld, 256), 256, 0, s>>>(n, A->K, A->ld, dAp.get(), dAj.get(),
+                                                                dAx.get(), A->ell_col.get(), A->ell_val.get(),
+                                                                A->ell_val32.get());
+            HEC_CHECK_LAUNCH();
+        }
+        if (r && n) {
+            k_hec_fill_rem<<<ceil_div(n, 256), 256, 0, s>>>(n, A->K, dAp.get(), dAj.get(), dAx.get(),
+                                                            A->rem_ptr.get(), A->rem_col.get(),
+                                                            A->rem_val.get(), A->rem_val32.get());
+            HEC_CHECK_LAUNCH();
+        }
+        HEC_HIP(hipStreamSynchronize(s));
+        *out = A.release();
+    });
+}
+
+hec_status hec_info(hec_matrix A, int32_t *n, int32_t *K, int32_t *ld, int64_t *nnz, int64_t *nnz_rem) {
+    return guarded([&] {
+        if (!A) fail(HEC_ERR_INVALID_ARG, "null matrix");
+        if (n) *n = A->n;
+        if (K) *K = A->K;
+        if (ld) *ld = A->ld;
+        if (nnz) *nnz = A->nnz;
+        if (nnz_rem) *nnz_rem = A->nnz_rem;
+    });
+}
+
+hec_status hec_export(hec_matrix A, int32_t *ell_col, double *ell_val, int32_t *rem_ptr, int32_t *rem_col,
+                      double *rem_val, float *ell_val32, float *rem_val32) {
+    return guarded([&] {
+        if (!A) fail(HEC_ERR_INVALID_ARG, "null matrix");
+        if ((ell_val32 || rem_val32) && !A->has_f32) fail(HEC_ERR_INVALID_ARG, "matrix has no FP32 copy");
+        size_t slab = (size_t)A->K * A->ld;
+        hipStream_t s = nullptr;
+        if (ell_col) A->ell_col.download(ell_col, slab, s);
+        if (ell_val) A->ell_val.download(ell_val, slab, s);
+        if (ell_val32) A->ell_val32.download(ell_val32, slab, s);
+        if (rem_ptr) A->rem_ptr.download(rem_ptr, A->n + 1, s);
+        if (rem_col) A->rem_col.download(rem_col, A->nnz_rem, s);
+        if (rem_val) A->rem_val.download(rem_val, A->nnz_rem, s);
+        if (rem_val32) A->rem_val32.download(rem_val32, A->nnz_rem, s);
+        HEC_HIP(hipStreamSynchronize(s));
+    });
+}
+
+hec_status hec_spmv(hec_matrix A, hec_dtype vals, double alpha, const void *x, hec_dtype xt, double beta,
+                    void *y, hec_dtype yt, void *stream) {
+    return guarded([&] {
+        if (!A) fail(HEC_ERR_INVALID_ARG, "null matrix");
+        if (A->n > 0 && (!x || !y)) fail(HEC_ERR_INVALID_ARG, "x or y is NULL");
+        if (vals == HEC_F32 && !A->has_f32) fail(HEC_ERR_INVALID_ARG, "matrix has no FP32 copy (HEC_KEEP_F32)");
+        if ((vals != HEC_F64 && vals != HEC_F32) || (xt != HEC_F64 && xt != HEC_F32) ||
+            (yt != HEC_F64 && yt != HEC_F32))
+            fail(HEC_ERR_INVALID_ARG, "bad dtype");
+        if (!std::isfinite(alpha) || !std::isfinite(beta)) fail(HEC_ERR_INVALID_ARG, "alpha/beta not finite");
+        hipStream_t s = as_stream(stream);
+        int key = (vals << 2) | (xt << 1) | yt;
+        switch (key) {
+#define CASE(V, X, Y, TV, TX, TY)                                                                       \
+    case ((V << 2) | (X << 1) | Y):                                                                     \
+        spmv_launch<TV, TX, TY>(*A, alpha, (const TX *)x, beta, (const TY *)y, (TY *)y, s);             \
+        break;
+            CASE(0, 0, 0, double, double, double)
+            CASE(0, 1, 0, double, float, double)
+            CASE(0, 0, 1, double, double, float)
+            CASE(0, 1, 1, double, float, float)
+            CASE(1, 1, 1, float, float, float)
+            CASE(1, 0, 0, float, double, double)
+            CASE(1, 1, 0, float, float, double)
+            CASE(1, 0, 1, float, double, float)
+#undef CASE
+        }
+    });
+}
+
+hec_status hec_destroy(hec_matrix A) {
+    delete A;
+    return HEC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,815 @@
+// Krylov solvers (Sec. 2.7): restarted right-preconditioned GMRES(m) and
+// BiCGSTAB (Alg. 4), built from the vector operations of Sec. 2.3 (Eq. (2)-(6)),
+// the HEC SpMV and the level-scheduled preconditioner solve.
+//
+// Every scalar of the methods (rho, alpha, omega, the Hessenberg matrix, the
+// Givens rotations, the residual estimate, the convergence flags) lives in
+// device memory and is produced by the last workgroup of the reduction that
+// needs it, so an iteration is a fixed sequence of stream-ordered launches with
+// no host round trip. Once the device sets the "done" flag, the remaining
+// launches of the sequence return at entry. The host looks at the flag through
+// mapped pinned memory one iteration behind the device.
+//
+// Reductions are deterministic: the grid size depends only on n, each
+// workgroup sums a fixed set of rows in a fixed order, and the last workgroup
+// combines the per-workgroup partial sums in a fixed order.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <type_traits>
+
+#include "hec_internal.hpp"
+
+namespace hec {
+
+namespace {
+
+constexpr int RB = 256;          // threads per reduction workgroup
+constexpr int kMaxRedBlocks = 1024;
+constexpr int kMaxRestart = 32;  // the orthogonalisation keeps up to 32 basis coefficients in registers
+
+inline int red_blocks(int64_t n) {
+    int64_t b = (n + RB * 4 - 1) / (RB * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxRedBlocks));
+}
+
+// ------------------------------------------------------------------ device state layout
+
+// Integer flags (device + mapped host mirror).
+enum : int { SI_DONE = 0, SI_JDONE = 1, SI_BREAK = 2, SI_STOP_S = 3, SI_ITERS = 4, SI_COUNT = 8 };
+// Double scalars.
+enum : int {
+    SD_BNORM = 0, SD_TOL = 1, SD_BETA = 2, SD_HNEXT = 3, SD_RES = 4,  // GMRES
+    SD_RHO = 5, SD_RHO_PREV = 6, SD_ALPHA = 7, SD_OMEGA = 8,       // BiCGSTAB
+    SD_SNORM2 = 9, SD_RNORM2 = 10,
+    SD_SCALARS = 16
+};
+
+struct GLayout {
+    int m;
+    int H, cs, sn, g, y, h1, h2, total;
+    explicit GLayout(int m_ = 0) : m(m_) {
+        H = SD_SCALARS;
+        cs = H + (m + 1) * m;
+        sn = cs + m;
+        g = sn + m;
+        y = g + m + 1;
+        h1 = y + m;
+        h2 = h1 + kMaxRestart;
+        total = h2 + kMaxRestart;
+    }
+    __host__ __device__ int Hij(int i, int j) const { return H + j * (m + 1) + i; }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum acc[0..nv) over the workgroup; the totals land in tot[0..nv) (shared).
+template <int NV>
+__device__ __forceinline__ void block_sum(const double (&acc)[NV], int nv, double *red, double *tot) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        if (k < nv) {
+            double v = wave_sum(acc[k]);
+            if (lane == 0) red[wid * NV + k] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        int k = threadIdx.x;
+        tot[k] = ((red[k] + red[NV + k]) + red[2 * NV + k]) + red[3 * NV + k];
+    }
+    __syncthreads();
+}
+
+// Generic fused pass: every row i runs op.row(i, acc) (which may also update
+// vectors), the NV sums are reduced deterministically and the last workgroup
+// calls op.finish(totals) on one thread.
+template <int NV, class Op>
+__global__ __launch_bounds__(RB) void k_pass(int64_t n, Op op, int nv, double *part, uint32_t *counter,
+                                             const int32_t *skip) {
+    if (skip && *skip) return;
+    __shared__ double red[4 * NV];
+    __shared__ double tot[NV];
+    __shared__ double sh[kMaxRestart + 1];
+    __shared__ bool last;
+    op.init(sh);
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RB;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) op.row(i, acc, sh);
+    block_sum<NV>(acc, nv, red, tot);
+    if (threadIdx.x < nv) {
+        part[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
+        __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) acc[k] += part[(size_t)b * NV + k];
+    }
+    block_sum<NV>(acc, nv, red, tot);
+    if (threadIdx.x == 0) {
+        op.finish(tot);
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ void mirror(int32_t *hostflags, int idx, int32_t v) {
+    if (hostflags) __hip_atomic_store(hostflags + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+struct NoInit {
+    __device__ void init(double *) const {}
+};
+
+// ---------------------------------------------------------------- ops
+
+// *out = ||a||_2 (Eq. (6))
+template <class T>
+struct OpNorm : NoInit {
+    const T *a;
+    double *out;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const {
+        double v = a[i];
+        acc[0] += v * v;
+    }
+    __device__ void finish(const double *t) const { *out = sqrt(t[0]); }
+};
+
+// GMRES cycle start: beta = ||r||, g = beta e1, flags cleared; done if beta <= tol.
+struct OpCycleStart : NoInit {
+    const double *r;
+    double *sd;
+    int32_t *si, *hf;
+    GLayout L;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const { acc[0] += r[i] * r[i]; }
+    __device__ void finish(const double *t) const {
+        double beta = sqrt(t[0]);
+        sd[SD_BETA] = beta;
+        sd[SD_RES] = beta;
+        sd[L.g] = beta;
+        for (int k = 1; k <= L.m; ++k) sd[L.g + k] = 0.0;
+        int done = !(beta > sd[SD_TOL]);
+        si[SI_DONE] = done;
+        si[SI_JDONE] = 0;
+        mirror(hf, SI_DONE, done);
+        mirror(hf, SI_JDONE, 0);
+    }
+};
+
+// CGS pass 1: h1[k] = <V_k, w>, k < nv
+template <class VT, int NV>
+struct OpCgs1 : NoInit {
+    const VT *V;
+    int64_t ldv;
+    const VT *w;
+    int nv;
+    double *h1;
+    __device__ void row(int64_t i, double (&acc)[NV], double *) const {
+        double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) acc[k] += (double)V[k * ldv + i] * wi;
+    }
+    __device__ void finish(const double *t) const {
+        for (int k = 0; k < nv; ++k) h1[k] = t[k];
+    }
+};
+
+// CGS pass 2: w -= V h1, h2[k] = <V_k, w>
+template <class VT, int NV>
+struct OpCgs2 {
+    const VT *V;
+    int64_t ldv;
+    VT *w;
+    int nv;
+    const double *h1;
+    double *h2;
+    __device__ void init(double *sh) const {
+        if ((int)threadIdx.x < nv) sh[threadIdx.x] = h1[threadIdx.x];
+    }
+    __device__ void row(int64_t i, double (&acc)[NV], double *sh) const {
+        double vk[NV];
+        double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            if (k < nv) {
+                vk[k] = V[k * ldv + i];
+                wi -= sh[k] * vk[k];
+            }
+        }
+        VT ws = (VT)wi;
+        w[i] = ws;
+        double wr = ws;
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) acc[k] += vk[k] * wr;
+    }
+    __device__ void finish(const double *t) const {
+        for (int k = 0; k < nv; ++k) h2[k] = t[k];
+    }
+};
+
+// CGS pass 3: w -= V h2, ||w||^2; then column j of H (h1 + h2, ||w||), the
+// previous Givens rotations, a new rotation, g, and the convergence test.
+template <class VT, int NV>
+struct OpCgs3 {
+    const VT *V;
+    int64_t ldv;
+    VT *w;
+    int nv;  // = j + 1
+    double *sd;
+    int32_t *si, *hf;
+    GLayout L;
+    __device__ void init(double *sh) const {
+        if ((int)threadIdx.x < nv) sh[threadIdx.x] = sd[L.h2 + threadIdx.x];
+    }
+    __device__ void row(int64_t i, double (&acc)[1], double *sh) const {
+        double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) wi -= sh[k] * (double)V[k * ldv + i];
+        VT ws = (VT)wi;
+        w[i] = ws;
+        double wr = ws;
+        acc[0] += wr * wr;
+    }
+    __device__ void finish(const double *t) const {
+        const int j = nv - 1;
+        double hn = sqrt(t[0]);
+        for (int k = 0; k <= j; ++k) sd[L.Hij(k, j)] = sd[L.h1 + k] + sd[L.h2 + k];
+        sd[SD_HNEXT] = hn;
+        for (int k = 0; k < j; ++k) {
+            double a = sd[L.Hij(k, j)], c = sd[L.Hij(k + 1, j)];
+            double cs = sd[L.cs + k], sn = sd[L.sn + k];
+            sd[L.Hij(k, j)] = cs * a + sn * c;
+            sd[L.Hij(k + 1, j)] = -sn * a + cs * c;
+        }
+        double a = sd[L.Hij(j, j)], c = hn;
+        double rr = hypot(a, c);
+        double cs = 1.0, sn = 0.0;
+        if (c != 0.0) {
+            cs = a / rr;
+            sn = c / rr;
+        }
+        sd[L.cs + j] = cs;
+        sd[L.sn + j] = sn;
+        sd[L.Hij(j, j)] = cs * a + sn * c;
+        double gj = sd[L.g + j];
+        sd[L.g + j + 1] = -sn * gj;
+        sd[L.g + j] = cs * gj;
+        double res = fabs(sd[L.g + j + 1]);
+        sd[SD_RES] = res;
+        si[SI_JDONE] = j + 1;
+        mirror(hf, SI_JDONE, j + 1);
+        if (!(res > sd[SD_TOL]) || hn == 0.0 || !isfinite(res)) {
+            si[SI_DONE] = 1;
+            mirror(hf, SI_DONE, 1);
+        }
+    }
+};
+
+// v = r / beta (start of a cycle)
+template <class VT, class RT>
+__global__ __launch_bounds__(256) void k_scale_start(int64_t n, const RT *r, VT *v, const double *sd) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v[i] = (VT)((double)r[i] / sd[SD_BETA]);
+}
+
+// v_{j+1} = w / h_{j+1,j}
+template <class VT>
+__global__ __launch_bounds__(256) void k_scale_next(int64_t n, const VT *w, VT *v, const double *sd,
+                                                    const int32_t *skip) {
+    if (*skip) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v[i] = (VT)((double)w[i] / sd[SD_HNEXT]);
+}
+
+// H y = g back substitution on the jdone x jdone upper triangle (one thread).
+__global__ void k_backsolve(double *sd, const int32_t *si, GLayout L) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int jd = si[SI_JDONE];
+    for (int i = jd - 1; i >= 0; --i) {
+        double t = sd[L.g + i];
+        for (int q = i + 1; q < jd; ++q) t -= sd[L.Hij(i, q)] * sd[L.y + q];
+        sd[L.y + i] = t / sd[L.Hij(i, i)];
+    }
+}
+
+// x += Z y (first jdone columns)
+template <class VT>
+__global__ __launch_bounds__(256) void k_update_x(int64_t n, const VT *Z, int64_t ldz, double *x,
+                                                  const double *sd, const int32_t *si, GLayout L) {
+    __shared__ double y[kMaxRestart];
+    int jd = si[SI_JDONE];
+    if ((int)threadIdx.x < jd) y[threadIdx.x] = sd[L.y + threadIdx.x];
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = x[i];
+    for (int k = 0; k < jd; ++k) acc += y[k] * (double)Z[k * ldz + i];
+    x[i] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(int64_t n, T *a, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+template <class S, class D>
+__global__ __launch_bounds__(256) void k_copy(int64_t n, const S *a, D *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (D)a[i];
+}
+
+// ---------------------------------------------------------------- BiCGSTAB ops (Alg. 4)
+
+// r0 = r (shadow), rho = (r0, r) = ||r||^2, flags reset: start / restart.
+struct OpBiStart : NoInit {
+    const double *r;
+    double *r0;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const {
+        double v = r[i];
+        r0[i] = v;
+        acc[0] += v * v;
+    }
+    __device__ void finish(const double *t) const {
+        sd[SD_RHO] = t[0];
+        sd[SD_RNORM2] = t[0];
+        int done = !(sqrt(t[0]) > sd[SD_TOL]);
+        si[SI_DONE] = done;
+        si[SI_STOP_S] = 0;
+        si[SI_BREAK] = 0;
+        si[SI_JDONE] = 0;  // loop passes in this run
+        mirror(hf, SI_DONE, done);
+        mirror(hf, SI_BREAK, 0);
+        mirror(hf, SI_JDONE, 0);
+        if (!done && (t[0] == 0.0 || !isfinite(t[0]))) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+        }
+    }
+};
+
+// k == 1: p = r; else p = r + beta (p - omega v), beta = (rho/rho_prev)(alpha/omega)
+__global__ __launch_bounds__(256) void k_bi_p(int64_t n, const double *r, double *p, const double *v,
+                                              const double *sd, const int32_t *si, int first) {
+    if (si[SI_DONE]) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (first) {
+        p[i] = r[i];
+    } else {
+        double beta = (sd[SD_RHO] / sd[SD_RHO_PREV]) * (sd[SD_ALPHA] / sd[SD_OMEGA]);
+        p[i] = r[i] + beta * (p[i] - sd[SD_OMEGA] * v[i]);
+    }
+}
+
+// alpha = rho / (r0, v); breakdown if (r0, v) == 0
+struct OpBiAlpha : NoInit {
+    const double *r0, *v;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const { acc[0] += r0[i] * v[i]; }
+    __device__ void finish(const double *t) const {
+        if (t[0] == 0.0 || !isfinite(t[0])) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+            return;
+        }
+        sd[SD_ALPHA] = sd[SD_RHO] / t[0];
+    }
+};
+
+// s = r - alpha v, ||s||; if ||s|| is small: x += alpha p*, stop.
+struct OpBiS : NoInit {
+    const double *r, *v, *ps;
+    double *s, *x;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const {
+        double si_ = r[i] - sd[SD_ALPHA] * v[i];
+        s[i] = si_;
+        acc[0] += si_ * si_;
+    }
+    __device__ void finish(const double *t) const {
+        sd[SD_SNORM2] = t[0];
+        si[SI_JDONE] += 1;
+        mirror(hf, SI_JDONE, si[SI_JDONE]);
+        if (!(sqrt(t[0]) > sd[SD_TOL])) si[SI_STOP_S] = 1;
+    }
+};
+
+// once ||s|| was small enough the rest of the pass is skipped
+__global__ void k_fold_stop(int32_t *si, int32_t *hf) {
+    if (si[SI_STOP_S] && !si[SI_DONE]) {
+        si[SI_DONE] = 1;
+        mirror(hf, SI_DONE, 1);
+    }
+}
+
+// early exit of Alg. 4: x += alpha p* when ||s|| was small enough
+__global__ __launch_bounds__(256) void k_bi_xs(int64_t n, double *x, const double *ps, double *sd, int32_t *si,
+                                               int32_t *hf) {
+    if (si[SI_DONE] || !si[SI_STOP_S]) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += sd[SD_ALPHA] * ps[i];
+}
+
+// (t, s) and (t, t) -> omega
+struct OpBiOmega : NoInit {
+    const double *t_, *s;
+    double *sd;
+    __device__ void row(int64_t i, double (&acc)[2], double *) const {
+        double tv = t_[i];
+        acc[0] += tv * s[i];
+        acc[1] += tv * tv;
+    }
+    __device__ void finish(const double *t) const { sd[SD_OMEGA] = t[1] == 0.0 ? 0.0 : t[0] / t[1]; }
+};
+
+// x += alpha p* + omega s*; r = s - omega t; ||r||^2 and (r0, r) -> next rho
+struct OpBiXR : NoInit {
+    double *x, *r;
+    const double *ps, *ss, *s, *t_, *r0;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[2], double *) const {
+        double al = sd[SD_ALPHA], om = sd[SD_OMEGA];
+        x[i] = x[i] + al * ps[i] + om * ss[i];
+        double ri = s[i] - om * t_[i];
+        r[i] = ri;
+        acc[0] += ri * ri;
+        acc[1] += r0[i] * ri;
+    }
+    __device__ void finish(const double *t) const {
+        sd[SD_RNORM2] = t[0];
+        sd[SD_RHO_PREV] = sd[SD_RHO];
+        sd[SD_RHO] = t[1];
+        if (!(sqrt(t[0]) > sd[SD_TOL]) || sd[SD_OMEGA] == 0.0) {
+            si[SI_DONE] = 1;
+            mirror(hf, SI_DONE, 1);
+        } else if (t[1] == 0.0 || !isfinite(t[1])) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+        }
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- workspace
+
+struct KrylovWS {
+    int64_t n = 0, ldv = 0;
+    int m = 0;
+    int nred = 1;
+    bool mixed = false, bicg = false;
+    DevBuf<double> V, Z;         // FP64 basis (m+1) x ldv, preconditioned basis m x ldv
+    DevBuf<float> V32, Z32;      // mixed inner basis
+    DevBuf<double> w, r, v6;     // w, r, and 6 more vectors for BiCGSTAB
+    DevBuf<float> w32;
+    DevBuf<double> sd;           // scalars + Hessenberg
+    DevBuf<int32_t> si;
+    DevBuf<double> part;         // partial sums, nred x kMaxRestart
+    DevBuf<uint32_t> counter;
+    int32_t *hflags = nullptr;   // mapped pinned mirror of si
+    int32_t *dflags = nullptr;   // its device address
+    std::vector<hipEvent_t> ev;
+    ~KrylovWS() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        if (hflags) (void)hipHostFree(hflags);
+    }
+};
+
+void KrylovWSDeleter::operator()(KrylovWS *w) const { delete w; }
+
+static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream_t s) {
+    auto *w = A.ws.get();
+    bool ok = w && w->m >= m && (!mixed || w->mixed) && (!bicg || w->bicg);
+    if (ok) return *w;
+    int mm = std::max(m, w ? w->m : 0);
+    bool mx = mixed || (w && w->mixed);
+    bool bc = bicg || (w && w->bicg);
+    A.ws.reset();
+    auto nw = std::unique_ptr<KrylovWS, KrylovWSDeleter>(new KrylovWS());
+    nw->n = A.n;
+    nw->ldv = ((int64_t)A.n + 63) / 64 * 64;
+    nw->m = mm;
+    nw->mixed = mx;
+    nw->bicg = bc;
+    nw->nred = red_blocks(A.n);
+    size_t ldv = nw->ldv;
+    if (mm > 0) {
+        nw->V.alloc((mm + 1) * ldv);
+        nw->Z.alloc(mm * ldv);
+        if (mx) {
+            nw->V32.alloc((mm + 1) * ldv);
+            nw->Z32.alloc(mm * ldv);
+        }
+    }
+    nw->w.alloc(ldv);
+    nw->r.alloc(ldv);
+    if (mx) nw->w32.alloc(ldv);
+    if (bc) nw->v6.alloc(6 * ldv);
+    GLayout L(std::max(mm, 1));
+    nw->sd.alloc(std::max(L.total, SD_SCALARS + 8));
+    nw->si.alloc(SI_COUNT);
+    nw->part.alloc((size_t)nw->nred * kMaxRestart);
+    nw->counter.alloc(1);
+    HEC_HIP(hipMemsetAsync(nw->counter.get(), 0, sizeof(uint32_t), s));
+    HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
+    HEC_HIP(hipHostMalloc((void **)&nw->hflags, SI_COUNT * sizeof(int32_t), hipHostMallocMapped));
+    std::memset(nw->hflags, 0, SI_COUNT * sizeof(int32_t));
+    HEC_HIP(hipHostGetDevicePointer((void **)&nw->dflags, nw->hflags, 0));
+    nw->ev.resize(kMaxRestart + 2);
+    for (auto &e : nw->ev) HEC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HEC_HIP(hipStreamSynchronize(s));
+    A.ws = std::move(nw);
+    return *A.ws;
+}
+
+template <int NV, class Op>
+static void launch_pass(KrylovWS &ws, int64_t n, const Op &op, int nv, hipStream_t s, const int32_t *skip) {
+    k_pass<NV, Op><<<ws.nred, RB, 0, s>>>(n, op, nv, ws.part.get(), ws.counter.get(), skip);
+    HEC_CHECK_LAUNCH();
+}
+
+static inline volatile int32_t *hf(KrylovWS &ws) { return (volatile int32_t *)ws.hflags; }
+
+// One GMRES cycle on the basis of type VT (double, or float for the mixed
+// inner solve), with r (FP64) holding the cycle's starting residual and
+// sd[SD_TOL] the absolute target. Returns the Arnoldi steps taken; x += Z y.
+template <class VT>
+static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc, int m, double *x,
+                       hipStream_t s) {
+    const int64_t n = A.n, ldv = ws.ldv;
+    VT *V, *Z, *w;
+    if constexpr (sizeof(VT) == 8) {
+        V = (VT *)ws.V.get();
+        Z = (VT *)ws.Z.get();
+        w = (VT *)ws.w.get();
+    } else {
+        V = (VT *)ws.V32.get();
+        Z = (VT *)ws.Z32.get();
+        w = (VT *)ws.w32.get();
+    }
+    GLayout L(m);
+    double *sd = ws.sd.get();
+    int32_t *si = ws.si.get();
+    const int32_t *done = si + SI_DONE;
+    // beta = ||r||, g = beta e1
+    OpCycleStart st{{}, ws.r.get(), sd, si, ws.dflags, L};
+    launch_pass<1>(ws, n, st, 1, s, nullptr);
+    HEC_HIP(hipEventRecord(ws.ev[0], s));
+    k_scale_start<VT, double><<<ceil_div(n, 256), 256, 0, s>>>(n, ws.r.get(), V, sd);
+    HEC_CHECK_LAUNCH();
+    HEC_HIP(hipEventSynchronize(ws.ev[0]));
+    if (hf(ws)[SI_DONE]) return 0;
+    for (int j = 0; j < mcyc; ++j) {
+        // look one iteration behind: stop issuing work once the device is done
+        if (j >= 2) {
+            HEC_HIP(hipEventSynchronize(ws.ev[j - 1]));
+            if (hf(ws)[SI_DONE]) break;
+        }
+        VT *vj = V + j * ldv, *zj = Z + j * ldv;
+        trsv_launch<VT>(lv, HEC_LU, vj, zj, s, done);
+        spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
+        const int nv = j + 1;
+        auto run = [&](auto nvtag) {
+            constexpr int NV = decltype(nvtag)::value;
+            OpCgs1<VT, NV> p1{{}, V, ldv, w, nv, sd + L.h1};
+            launch_pass<NV>(ws, n, p1, nv, s, done);
+            OpCgs2<VT, NV> p2{V, ldv, w, nv, sd + L.h1, sd + L.h2};
+            launch_pass<NV>(ws, n, p2, nv, s, done);
+            OpCgs3<VT, NV> p3{V, ldv, w, nv, sd, si, ws.dflags, L};
+            launch_pass<1>(ws, n, p3, 1, s, done);
+        };
+        if (nv <= 8) run(std::integral_constant<int, 8>());
+        else if (nv <= 16) run(std::integral_constant<int, 16>());
+        else run(std::integral_constant<int, 32>());
+        if (j + 1 < mcyc) {
+            k_scale_next<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, w, V + (j + 1) * ldv, sd, done);
+            HEC_CHECK_LAUNCH();
+        }
+        HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
+    }
+    k_backsolve<<<1, 64, 0, s>>>(sd, si, L);
+    HEC_CHECK_LAUNCH();
+    k_update_x<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, Z, ldv, x, sd, si, L);
+    HEC_CHECK_LAUNCH();
+    HEC_HIP(hipStreamSynchronize(s));
+    return hf(ws)[SI_JDONE];
+}
+
+static double read_scalar(KrylovWS &ws, int idx, hipStream_t s) {
+    double v = 0.0;
+    HEC_HIP(hipMemcpyAsync(&v, ws.sd.get() + idx, sizeof(double), hipMemcpyDeviceToHost, s));
+    HEC_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+static void set_scalar(KrylovWS &ws, int idx, double v, hipStream_t s) {
+    HEC_HIP(hipMemcpyAsync(ws.sd.get() + idx, &v, sizeof(double), hipMemcpyHostToDevice, s));
+    HEC_HIP(hipStreamSynchronize(s));
+}
+
+// ||b - A x|| for the FP64 matrix into ws.r; returns the norm
+static double true_residual(hec_matrix_s &A, KrylovWS &ws, const double *b, const double *x, hipStream_t s) {
+    spmv_launch<double, double, double>(A, -1.0, x, 1.0, b, ws.r.get(), s);
+    OpNorm<double> op{{}, ws.r.get(), ws.sd.get() + SD_RES};
+    launch_pass<1>(ws, A.n, op, 1, s, nullptr);
+    return read_scalar(ws, SD_RES, s);
+}
+
+static double vec_norm(KrylovWS &ws, int64_t n, const double *v, hipStream_t s) {
+    OpNorm<double> op{{}, v, ws.sd.get() + SD_BNORM};
+    launch_pass<1>(ws, n, op, 1, s, nullptr);
+    return read_scalar(ws, SD_BNORM, s);
+}
+
+static void check_solve_args(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                             const hec_solve_opts *o) {
+    if (!A || !M || !lv || !o) fail(HEC_ERR_INVALID_ARG, "null handle or options");
+    if (A->n != M->n || A->n != lv->n) fail(HEC_ERR_INVALID_ARG, "matrix, factor and levels differ in size");
+    if (A->n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
+    if (o->maxit < 0) fail(HEC_ERR_INVALID_ARG, "maxit < 0");
+    if (!(o->rtol > 0.0)) fail(HEC_ERR_INVALID_ARG, "rtol must be > 0");
+    if (o->precision != 0 && o->precision != 1) fail(HEC_ERR_INVALID_ARG, "precision must be 0 or 1");
+}
+
+}  // namespace hec
+
+using namespace hec;
+
+extern "C" {
+
+hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                       const hec_solve_opts *o, hec_solve_info *info, void *stream) {
+    hec_solve_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+    hec_status st = guarded([&] {
+        check_solve_args(A, M, lv, b, x, o);
+        if (o->restart < 1 || o->restart > kMaxRestart)
+            fail(HEC_ERR_INVALID_ARG, "restart must be in [1, 32]");
+        const bool mixed = o->precision == 1;
+        if (mixed && (!A->has_f32 || !M->has_f32))
+            fail(HEC_ERR_INVALID_ARG, "mixed precision needs HEC_KEEP_F32 on the matrix and the factor");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = A->n;
+        inf.status = HEC_OK;
+        if (n == 0) return;
+        KrylovWS &ws = get_ws(*A, o->restart, mixed, false, s);
+        const double bnorm = vec_norm(ws, n, b, s);
+        if (bnorm == 0.0) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+            HEC_HIP(hipStreamSynchronize(s));
+            return;
+        }
+        if (o->x0_zero) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+        }
+        const double target = mixed && o->ir_rtol > 0.0 ? std::min(o->ir_rtol, o->rtol) : o->rtol;
+        double res = true_residual(*A, ws, b, x, s);
+        int it = 0, cycles = 0;
+        while (res / bnorm > target && it < o->maxit) {
+            int mcyc = std::min(o->restart, o->maxit - it);
+            int jd;
+            if (!mixed) {
+                set_scalar(ws, SD_TOL, target * bnorm, s);
+                jd = gmres_cycle<double>(*A, *lv, ws, mcyc, o->restart, x, s);
+            } else {
+                // inner solve of A d = r in FP32 storage, one cycle, to inner_rtol
+                double inner = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-4;
+                set_scalar(ws, SD_TOL, std::max(inner * res, 0.5 * target * bnorm), s);
+                jd = gmres_cycle<float>(*A, *lv, ws, mcyc, o->restart, x, s);
+                inf.ir_steps++;
+            }
+            inf.rel_res_est = read_scalar(ws, SD_RES, s) / bnorm;
+            it += jd;
+            cycles++;
+            res = true_residual(*A, ws, b, x, s);
+            if (jd == 0) break;  // no progress possible (breakdown at the start of a cycle)
+        }
+        inf.iterations = it;
+        inf.restarts = std::max(0, cycles - 1);
+        inf.rel_res_true = res / bnorm;
+        if (!(res / bnorm <= target)) fail(HEC_ERR_NOT_CONVERGED, "GMRES did not reach the tolerance");
+    });
+    inf.status = st;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
+}
+
+hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                          const hec_solve_opts *o, hec_solve_info *info, void *stream) {
+    hec_solve_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+    hec_status st = guarded([&] {
+        check_solve_args(A, M, lv, b, x, o);
+        if (o->precision != 0) fail(HEC_ERR_INVALID_ARG, "BiCGSTAB runs in FP64 only");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = A->n;
+        if (n == 0) return;
+        KrylovWS &ws = get_ws(*A, 0, false, true, s);
+        const int64_t ldv = ws.ldv;
+        double *r = ws.r.get(), *r0 = ws.v6.get(), *p = r0 + ldv, *ps = p + ldv, *v = ps + ldv, *sv = v + ldv,
+               *ss = sv + ldv, *t = ws.w.get();
+        double *sd = ws.sd.get();
+        int32_t *si = ws.si.get();
+        const double bnorm = vec_norm(ws, n, b, s);
+        if (bnorm == 0.0) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+            HEC_HIP(hipStreamSynchronize(s));
+            return;
+        }
+        if (o->x0_zero) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+        }
+        set_scalar(ws, SD_TOL, o->rtol * bnorm, s);
+        double res = true_residual(*A, ws, b, x, s);
+        int it = 0, restarts = 0;
+        bool broke = false;
+        const unsigned g = ceil_div(n, 256);
+        while (res / bnorm > o->rtol && it < o->maxit && restarts <= 3) {
+            OpBiStart bs{{}, r, r0, sd, si, ws.dflags};
+            launch_pass<1>(ws, n, bs, 1, s, nullptr);
+            HEC_HIP(hipStreamSynchronize(s));
+            broke = false;
+            if (!hf(ws)[SI_DONE]) {
+                int k = 0;
+                for (; it + k < o->maxit; ++k) {
+                    if (k >= 2) {  // wait for pass k-2, keep pass k-1 queued
+                        HEC_HIP(hipEventSynchronize(ws.ev[k % 2]));
+                        if (hf(ws)[SI_DONE]) break;
+                    }
+                    const int32_t *done = si + SI_DONE;
+                    k_bi_p<<<g, 256, 0, s>>>(n, r, p, v, sd, si, k == 0);
+                    HEC_CHECK_LAUNCH();
+                    trsv_launch<double>(*lv, HEC_LU, p, ps, s, done);
+                    spmv_launch<double, double, double>(*A, 1.0, ps, 0.0, v, v, s, done);
+                    launch_pass<1>(ws, n, OpBiAlpha{{}, r0, v, sd, si, ws.dflags}, 1, s, done);
+                    launch_pass<1>(ws, n, OpBiS{{}, r, v, ps, sv, x, sd, si, ws.dflags}, 1, s, done);
+                    k_bi_xs<<<g, 256, 0, s>>>(n, x, ps, sd, si, ws.dflags);
+                    HEC_CHECK_LAUNCH();
+                    k_fold_stop<<<1, 1, 0, s>>>(si, ws.dflags);
+                    HEC_CHECK_LAUNCH();
+                    trsv_launch<double>(*lv, HEC_LU, sv, ss, s, done);
+                    spmv_launch<double, double, double>(*A, 1.0, ss, 0.0, t, t, s, done);
+                    launch_pass<2>(ws, n, OpBiOmega{{}, t, sv, sd}, 2, s, done);
+                    launch_pass<2>(ws, n, OpBiXR{{}, x, r, ps, ss, sv, t, r0, sd, si, ws.dflags}, 2, s, done);
+                    HEC_HIP(hipEventRecord(ws.ev[k % 2], s));
+                }
+                HEC_HIP(hipStreamSynchronize(s));
+                it += hf(ws)[SI_JDONE];
+                broke = hf(ws)[SI_BREAK] != 0;
+            }
+            inf.rel_res_est = std::sqrt(std::min(read_scalar(ws, SD_RNORM2, s), read_scalar(ws, SD_SNORM2, s))) / bnorm;
+            res = true_residual(*A, ws, b, x, s);
+            if (res / bnorm > o->rtol) ++restarts;
+        }
+        inf.iterations = it;
+        inf.restarts = restarts;
+        inf.rel_res_true = res / bnorm;
+        if (!(res / bnorm <= o->rtol)) {
+            if (broke) fail(HEC_ERR_BREAKDOWN, "BiCGSTAB breakdown (rho or (r0,v) == 0)");
+            fail(HEC_ERR_NOT_CONVERGED, "BiCGSTAB did not reach the tolerance");
+        }
+    });
+    inf.status = st;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
+}
+
+}  // extern "C"

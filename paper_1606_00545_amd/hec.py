@@ -1,0 +1,292 @@
+"""Python binding of the HEC / ILU(k) / level-schedule Krylov library (``libhec.so``).
+
+Argument marshalling only: every call goes straight to the C ABI declared in
+``include/hec.h``, with the same names. Host CSR arrays are numpy arrays;
+vectors are torch CUDA tensors (device memory and streams come from PyTorch).
+There is no fallback: if ``libhec.so`` is missing or cannot be loaded, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhec.so")
+
+OK, INVALID_ARG, NOMEM, ZERO_PIVOT, BREAKDOWN, NOT_CONVERGED, HIP_ERROR = range(7)
+F64, F32 = 0, 1
+KEEP_F32 = 1
+LOWER, UPPER, LU = 1, 2, 3
+
+EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
+            "ilu_factor", "ilu_info", "ilu_export", "ilu_destroy",
+            "level_schedule", "levels_info", "levels_export", "levels_destroy",
+            "trsv_levels", "gmres_solve", "bicgstab_solve", "hec_last_error")
+
+
+class HecError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("precision", C.c_int32),
+                ("x0_zero", C.c_int32), ("rtol", C.c_double), ("ir_rtol", C.c_double),
+                ("inner_rtol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("ir_steps", C.c_int32), ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+
+
+def load(path: str = LIB_PATH):
+    """Load libhec.so (raises OSError if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with `python -m paper_1606_00545_amd.build`")
+    L = C.CDLL(path)
+    L.hec_last_error.restype = C.c_char_p
+    L.hec_from_csr.argtypes = [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_uint32, _vp, C.POINTER(_vp)]
+    L.hec_info.argtypes = [_vp, _i32p, _i32p, _i32p, _i64p, _i64p]
+    L.hec_export.argtypes = [_vp] + [_vp] * 7
+    L.hec_spmv.argtypes = [_vp, C.c_int, C.c_double, _vp, C.c_int, C.c_double, _vp, C.c_int, _vp]
+    L.hec_destroy.argtypes = [_vp]
+    L.ilu_factor.argtypes = [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_uint32, _vp, C.POINTER(_vp)]
+    L.ilu_info.argtypes = [_vp, _i32p, _i64p]
+    L.ilu_export.argtypes = [_vp, _vp, _vp, _vp]
+    L.ilu_destroy.argtypes = [_vp]
+    L.level_schedule.argtypes = [_vp, C.POINTER(_vp)]
+    L.levels_info.argtypes = [_vp, _i32p, _i32p, _i32p]
+    L.levels_export.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.levels_destroy.argtypes = [_vp]
+    L.trsv_levels.argtypes = [_vp, _vp, C.c_uint32, C.c_int, _vp, _vp, _vp]
+    L.gmres_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _vp]
+    L.bicgstab_solve.argtypes = L.gmres_solve.argtypes
+    for name in EXPORTED:
+        if name != "hec_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise HecError(code, where, load().hec_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _dev(t, dtype=None):
+    """Device pointer of a contiguous torch CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous CUDA tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+def _csr(A):
+    n = int(A.n)
+    Ap = np.ascontiguousarray(A.Ap, dtype=np.int32)
+    Aj = np.ascontiguousarray(A.Aj, dtype=np.int32)
+    Ax = np.ascontiguousarray(A.Ax, dtype=np.float64)
+    return n, Ap, Aj, Ax
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def close(self):
+        if self.ptr:
+            getattr(load(), self._destroy)(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix(_Handle):
+    _destroy = "hec_destroy"
+
+
+class Factor(_Handle):
+    _destroy = "ilu_destroy"
+
+
+class Levels(_Handle):
+    _destroy = "levels_destroy"
+
+
+# ---------------------------------------------------------------- HEC matrix
+
+def hec_from_csr(A, ell_width: int = -1, keep_f32: bool = False, stream=None) -> Matrix:
+    n, Ap, Aj, Ax = _csr(A)
+    out = _vp()
+    _check(load().hec_from_csr(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, ell_width,
+                               KEEP_F32 if keep_f32 else 0, _stream_or_null(stream), C.byref(out)),
+           "hec_from_csr")
+    return Matrix(out.value)
+
+
+def _stream_or_null(stream):
+    """Setup calls accept a stream; None means the legacy default stream (no torch needed)."""
+    if stream is None:
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+def hec_info(M: Matrix) -> dict:
+    n, K, ld = C.c_int32(), C.c_int32(), C.c_int32()
+    nnz, nr = C.c_int64(), C.c_int64()
+    _check(load().hec_info(M.ptr, C.byref(n), C.byref(K), C.byref(ld), C.byref(nnz), C.byref(nr)), "hec_info")
+    return {"n": n.value, "K": K.value, "ld": ld.value, "nnz": nnz.value, "nnz_rem": nr.value}
+
+
+def hec_export(M: Matrix, f32: bool = False) -> dict:
+    d = hec_info(M)
+    slab = d["K"] * d["ld"]
+    out = {"ell_col": np.empty(slab, np.int32), "ell_val": np.empty(slab, np.float64),
+           "rem_ptr": np.empty(d["n"] + 1, np.int32), "rem_col": np.empty(d["nnz_rem"], np.int32),
+           "rem_val": np.empty(d["nnz_rem"], np.float64)}
+    if f32:
+        out["ell_val32"] = np.empty(slab, np.float32)
+        out["rem_val32"] = np.empty(d["nnz_rem"], np.float32)
+    p = lambda k: out[k].ctypes.data if k in out else None
+    _check(load().hec_export(M.ptr, p("ell_col"), p("ell_val"), p("rem_ptr"), p("rem_col"), p("rem_val"),
+                             p("ell_val32"), p("rem_val32")), "hec_export")
+    out.update(d)
+    return out
+
+
+def hec_spmv(M: Matrix, x, y, alpha: float = 1.0, beta: float = 0.0, vals: int = F64, stream=None):
+    """y = alpha*A*x + beta*y on the device (asynchronous on the stream)."""
+    _check(load().hec_spmv(M.ptr, vals, alpha, _dev(x), _dtype_code(x), beta, _dev(y), _dtype_code(y),
+                           _stream(stream)), "hec_spmv")
+    return y
+
+
+# ---------------------------------------------------------------- ILU(k) + levels
+
+def ilu_factor(A, k: int = 0, keep_f32: bool = False, stream=None) -> Factor:
+    n, Ap, Aj, Ax = _csr(A)
+    out = _vp()
+    _check(load().ilu_factor(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, k, KEEP_F32 if keep_f32 else 0,
+                             _stream_or_null(stream), C.byref(out)), "ilu_factor")
+    return Factor(out.value)
+
+
+def ilu_info(M: Factor) -> dict:
+    n, nnz = C.c_int32(), C.c_int64()
+    _check(load().ilu_info(M.ptr, C.byref(n), C.byref(nnz)), "ilu_info")
+    return {"n": n.value, "nnz": nnz.value}
+
+
+def ilu_export(M: Factor):
+    d = ilu_info(M)
+    LUp = np.empty(d["n"] + 1, np.int32)
+    LUj = np.empty(d["nnz"], np.int32)
+    LUx = np.empty(d["nnz"], np.float64)
+    _check(load().ilu_export(M.ptr, LUp.ctypes.data, LUj.ctypes.data, LUx.ctypes.data), "ilu_export")
+    return LUp, LUj, LUx
+
+
+def level_schedule(M: Factor) -> Levels:
+    out = _vp()
+    _check(load().level_schedule(M.ptr, C.byref(out)), "level_schedule")
+    return Levels(out.value)
+
+
+def levels_info(lv: Levels) -> dict:
+    n, a, b = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().levels_info(lv.ptr, C.byref(n), C.byref(a), C.byref(b)), "levels_info")
+    return {"n": n.value, "nlev_lower": a.value, "nlev_upper": b.value}
+
+
+def levels_export(lv: Levels) -> dict:
+    d = levels_info(lv)
+    out = {"lower_ptr": np.empty(d["nlev_lower"] + 1, np.int32), "lower_perm": np.empty(d["n"], np.int32),
+           "upper_ptr": np.empty(d["nlev_upper"] + 1, np.int32), "upper_perm": np.empty(d["n"], np.int32)}
+    _check(load().levels_export(lv.ptr, out["lower_ptr"].ctypes.data, out["lower_perm"].ctypes.data,
+                                out["upper_ptr"].ctypes.data, out["upper_perm"].ctypes.data), "levels_export")
+    out.update(d)
+    return out
+
+
+def trsv_levels(M: Factor, lv: Levels, b, x, which: int = LU, stream=None):
+    """x = L^{-1} b, U^{-1} b or U^{-1} L^{-1} b on the device (asynchronous)."""
+    prec = _dtype_code(b)
+    if _dtype_code(x) != prec:
+        raise ValueError("b and x must have the same dtype")
+    _check(load().trsv_levels(M.ptr, lv.ptr, which, prec, _dev(b), _dev(x), _stream(stream)), "trsv_levels")
+    return x
+
+
+# ---------------------------------------------------------------- solvers
+
+def _opts(restart, maxit, rtol, precision, x0_zero, ir_rtol, inner_rtol):
+    return SolveOpts(restart, maxit, precision, 1 if x0_zero else 0, rtol, ir_rtol, inner_rtol)
+
+
+def gmres_solve(A: Matrix, M: Factor, lv: Levels, b, x, restart: int = 30, maxit: int = 10000,
+                rtol: float = 1e-8, precision: int = 0, x0_zero: bool = True, ir_rtol: float = 0.0,
+                inner_rtol: float = 1e-4, stream=None, check: bool = True) -> dict:
+    import torch
+    o = _opts(restart, maxit, rtol, precision, x0_zero, ir_rtol, inner_rtol)
+    info = SolveInfo()
+    code = load().gmres_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+                              C.byref(o), C.byref(info), _stream(stream))
+    if check and code != OK:
+        _check(code, "gmres_solve")
+    return info.as_dict()
+
+
+def bicgstab_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, rtol: float = 1e-8,
+                   x0_zero: bool = True, stream=None, check: bool = True) -> dict:
+    import torch
+    o = _opts(1, maxit, rtol, 0, x0_zero, 0.0, 0.0)
+    info = SolveInfo()
+    code = load().bicgstab_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+                                 C.byref(o), C.byref(info), _stream(stream))
+    if check and code != OK:
+        _check(code, "bicgstab_solve")
+    return info.as_dict()

@@ -1,0 +1,141 @@
+"""GPU solvers: restarted GMRES and BiCGSTAB (FP64 and mixed precision) against the oracle.
+
+Krylov iterates are not unique across implementations (CGS2 on the device, MGS in the
+oracle; fused multiply-adds), so parity is judged by the FP64 true residual computed by
+the oracle's SpMV, the distance to the oracle's solution, and the iteration counts."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1606_00545_amd import hec, synth
+from tests._gpu import dev, empty, host
+from tests._mats import tridiag
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(kind):
+    if kind == "poisson2d_64":
+        A, xt = synth.workload_c1()
+    elif kind == "tpfa3d_24":
+        A, xt = synth.workload_diffusion3d(24, sigma=2.0, seed=21)
+    elif kind == "tpfa2d_aniso":
+        rng = np.random.default_rng(22)
+        A = synth.lognormal_tpfa((70, 45), 2.5, rng)
+        xt = rng.uniform(-1, 1, A.n)
+    b = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, xt)
+    return A, xt, b
+
+
+def _rel_res(A, x, b):
+    return np.linalg.norm(b - O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, x)) / np.linalg.norm(b)
+
+
+def _setup(A, k=0, f32=False):
+    Mh = hec.hec_from_csr(A, keep_f32=f32)
+    F = hec.ilu_factor(A, k=k, keep_f32=f32)
+    lv = hec.level_schedule(F)
+    return Mh, F, lv
+
+
+@pytest.mark.parametrize("kind", ["poisson2d_64", "tpfa3d_24", "tpfa2d_aniso"])
+@pytest.mark.parametrize("k", [0, 1])
+def test_gmres_fp64_matches_oracle(kind, k):
+    A, xt, b = _system(kind)
+    Fo = O.iluk(A.n, A.Ap, A.Aj, A.Ax, k)
+    ro = O.gmres(A, Fo, b, restart=30, rtol=1e-8)
+    Mh, F, lv = _setup(A, k)
+    x = empty(A.n)
+    info = hec.gmres_solve(Mh, F, lv, dev(b), x, restart=30, rtol=1e-8)
+    x = host(x)
+    rr = _rel_res(A, x, b)
+    assert info["status"] == hec.OK and rr <= 1e-8
+    assert abs(info["rel_res_true"] - rr) <= 1e-10
+    assert abs(info["iterations"] - ro.iterations) <= max(2, ro.iterations // 10)
+    # both are 1e-8-residual solutions of the same system
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-4
+    print(f"{kind} k={k}: gpu it={info['iterations']} oracle it={ro.iterations} res={rr:.2e} "
+          f"|x-x_o|/|x_o|={np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x):.2e}")
+
+
+@pytest.mark.parametrize("kind", ["poisson2d_64", "tpfa3d_24", "tpfa2d_aniso"])
+def test_bicgstab_fp64_matches_oracle(kind):
+    A, xt, b = _system(kind)
+    Fo = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    ro = O.bicgstab(A, Fo, b, rtol=1e-8)
+    Mh, F, lv = _setup(A, 0)
+    x = empty(A.n)
+    info = hec.bicgstab_solve(Mh, F, lv, dev(b), x, rtol=1e-8)
+    x = host(x)
+    rr = _rel_res(A, x, b)
+    assert info["status"] == hec.OK and rr <= 1e-8
+    assert abs(info["iterations"] - ro.iterations) <= max(3, ro.iterations // 5)
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-4
+    print(f"{kind}: gpu it={info['iterations']} oracle it={ro.iterations} res={rr:.2e}")
+
+
+@pytest.mark.parametrize("kind,k", [("tpfa3d_24", 0), ("tpfa3d_24", 1), ("tpfa2d_aniso", 0)])
+@pytest.mark.parametrize("target", [1e-8, 1e-10])
+def test_gmres_mixed_precision_reaches_fp64_tolerance(kind, k, target):
+    A, xt, b = _system(kind)
+    Mh, F, lv = _setup(A, k, f32=True)
+    x = empty(A.n)
+    info = hec.gmres_solve(Mh, F, lv, dev(b), x, restart=30, rtol=target, precision=1)
+    x = host(x)
+    rr = _rel_res(A, x, b)
+    assert info["status"] == hec.OK and rr <= target and info["ir_steps"] >= 1
+    Fo = O.iluk(A.n, A.Ap, A.Aj, A.Ax, k)
+    ro = O.gmres(A, Fo, b, restart=30, rtol=target)
+    err = np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x)
+    print(f"mixed {kind} k={k} target={target}: it={info['iterations']} ir={info['ir_steps']} "
+          f"res={rr:.2e} |x-x_o|/|x_o|={err:.2e}")
+    assert err < 1e-3
+
+
+def test_exact_preconditioner_one_iteration():
+    A = tridiag(5000, np.random.default_rng(1))
+    b = np.random.default_rng(2).uniform(-1, 1, A.n)
+    Mh, F, lv = _setup(A)
+    for solver in ("gmres", "bicgstab"):
+        x = empty(A.n)
+        f = hec.gmres_solve if solver == "gmres" else hec.bicgstab_solve
+        info = f(Mh, F, lv, dev(b), x, rtol=1e-12)
+        assert info["iterations"] == 1 and _rel_res(A, host(x), b) <= 1e-12
+
+
+def test_zero_rhs_and_initial_guess():
+    A, xt, b = _system("poisson2d_64")
+    Mh, F, lv = _setup(A)
+    x = dev(np.ones(A.n))
+    info = hec.gmres_solve(Mh, F, lv, dev(np.zeros(A.n)), x, x0_zero=False)
+    assert info["iterations"] == 0 and (host(x) == 0).all()
+    # a converged initial guess needs no iteration
+    x = dev(xt)
+    info = hec.gmres_solve(Mh, F, lv, dev(b), x, x0_zero=False, rtol=1e-6)
+    assert info["iterations"] == 0 and info["status"] == hec.OK
+    # restart from a partial solve (resume from a saved iterate)
+    x = empty(A.n)
+    i1 = hec.gmres_solve(Mh, F, lv, dev(b), x, maxit=10, check=False)
+    assert i1["status"] == hec.NOT_CONVERGED and i1["iterations"] == 10
+    i2 = hec.gmres_solve(Mh, F, lv, dev(b), x, x0_zero=False)
+    assert i2["status"] == hec.OK and _rel_res(A, host(x), b) <= 1e-8
+
+
+def test_not_converged_status_and_best_iterate():
+    A, xt, b = _system("tpfa3d_24")
+    Mh, F, lv = _setup(A)
+    x = empty(A.n)
+    info = hec.bicgstab_solve(Mh, F, lv, dev(b), x, maxit=3, check=False)
+    assert info["status"] == hec.NOT_CONVERGED and info["iterations"] == 3
+    assert abs(_rel_res(A, host(x), b) - info["rel_res_true"]) < 1e-12
+
+
+def test_solves_are_deterministic():
+    A, xt, b = _system("tpfa3d_24")
+    Mh, F, lv = _setup(A)
+    outs = []
+    for _ in range(2):
+        x = empty(A.n)
+        hec.gmres_solve(Mh, F, lv, dev(b), x)
+        outs.append(host(x))
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))

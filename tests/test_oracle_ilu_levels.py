@@ -229,3 +229,13 @@ def test_level_counts_at_workload_sizes():
     A = synth.poisson2d(64)
     lv = O.level_schedule(A.n, A.Ap, A.Aj, "lower")
     assert lv.nlev == 127
+
+
+def test_zero_pivot_in_last_row_is_reported():
+    """u_nn = 0 is never used to eliminate, but it is the divisor of the backward solve."""
+    from tests._mats import from_pattern
+    D = np.array([[1.0, 1.0], [1.0, 1.0]])  # u_11 = 1 - 1*1 = 0
+    A = from_pattern(np.ones((2, 2), bool), D)
+    with pytest.raises(O.OracleError) as e:
+        O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    assert e.value.code == O.ZERO_PIVOT
