@@ -62,6 +62,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} not found: build it with `python -m paper_1606_00545_amd.build`")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7. Loading
+    # torch first makes the dynamic linker bind libhec.so to that same runtime
+    # (same soname), so torch's device pointers and streams are valid here.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     L.hec_last_error.restype = C.c_char_p
     L.hec_from_csr.argtypes = [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_uint32, _vp, C.POINTER(_vp)]
