@@ -129,6 +129,7 @@ struct hec_matrix_s {
 
 struct hec_ilu_s {
     int32_t n = 0, k = 0;
+    int32_t gnx = 0, gny = 0, gnz = 0;  // natural-order grid of A's stencil, if recognised (0: none)
     int64_t nnz = 0;
     bool has_f32 = false;
     std::vector<int32_t> hLUp, hLUj;  // host copy of the pattern S_k (used by level_schedule)
@@ -138,26 +139,39 @@ struct hec_ilu_s {
     hec::DevBuf<float> LUx32;
 };
 
-// One triangle in level order, stored as a column-major ELL slab over the
-// level-ordered positions q = 0..n-1 (entry s of position q at s*ldq + q).
+// One triangle of the factor with its level schedule (Eq. (11), Alg. 3) and
+// the blocked execution plan of the triangular solve: rows are cut into parts
+// (contiguous row ranges in the order the triangle is solved), each part's rows
+// are laid out at consecutive positions sorted by (level, row), and each part is
+// cut into sub-segments of at most 64 rows of one level. Entry s of position q
+// is stored at s*ldq + q.
 struct hec_tri {
-    int32_t nlev = 0, K = 0, ldq = 0, nchunks = 0;
-    std::vector<int32_t> hlevel_ptr, hperm;
-    hec::DevBuf<int32_t> perm;         // position -> row
-    hec::DevBuf<int32_t> chunk_ptr;    // nchunks+1 positions; chunks never straddle a level
-    hec::DevBuf<int32_t> col;          // dependency row, -1 for padding
+    int32_t nlev = 0;
+    std::vector<int32_t> hlevel_ptr, hperm;  // Alg. 3: level start pointers, rows by (level, row)
+    int32_t K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 0, S = 0;  // KC: K padded to 4/8/16/32
+    int32_t D64 = 0, D32 = 0;                // ring depths for the FP64 / FP32 solve
+    bool blocked = true;                     // false: rows too long for LDS slots, per-row polling kernel
+    int32_t nchunks = 0;                     // fallback plan: 64-row chunks of one level
+    hec::DevBuf<int32_t> chunk_ptr;
+    size_t lds64 = 0, lds32 = 0;             // dynamic LDS bytes of the solve kernels
+    hec::DevBuf<int32_t> part_ss;   // nparts+1: sub-segment range of each part
+    hec::DevBuf<int32_t> part_pos;  // nparts+1: first position of each part
+    hec::DevBuf<int32_t> ss_pos;    // nss+1: first position of each sub-segment
+    hec::DevBuf<int32_t> grow;      // position -> row
+    hec::DevBuf<int32_t> other;     // lower only: the row's position in the upper plan
+    hec::DevBuf<int32_t> enc;       // K*ldq: -(local position+1) inside the part, row outside, INT_MIN pad
     hec::DevBuf<double> val;
     hec::DevBuf<float> val32;
-    hec::DevBuf<double> dinv_src;      // U only: the pivot u_ii per position
-    hec::DevBuf<float> d32;
+    hec::DevBuf<double> piv;        // upper only: u_ii per position
+    hec::DevBuf<float> piv32;
 };
 
 struct hec_levels_s {
     int32_t n = 0;
     hec_tri lower, upper;
-    hec::DevBuf<uint32_t> sync;       // ticket + done counters for the solve kernels
-    hec::DevBuf<double> tmp64;        // intermediate y of an LU solve
-    hec::DevBuf<float> tmp32;
+    hec::DevBuf<uint32_t> sync;            // part tickets + finished-workgroup counters
+    hec::DevBuf<double> y64, bp64, yp64;   // y = L^{-1} b (by row), b in lower order, y in upper order
+    hec::DevBuf<float> y32, bp32, yp32;
 };
 
 namespace hec {
@@ -173,5 +187,16 @@ void spmv_launch(const hec_matrix_s &A, double alpha, const XT *x, double beta, 
 template <class T>
 void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s,
                  const int32_t *skip = nullptr);
+
+// Eq. (11) levels of the strict lower (upper == false) or strict upper triangle
+// of a pattern with known diagonal positions; fills level_ptr and perm (Alg. 3)
+// and, if lev != nullptr, each row's level. Returns the number of levels.
+int32_t compute_levels(int32_t n, const std::vector<int32_t> &LUp, const std::vector<int32_t> &LUj,
+                       const std::vector<int32_t> &diag, bool upper, std::vector<int32_t> &level_ptr,
+                       std::vector<int32_t> &perm, std::vector<int32_t> *lev = nullptr);
+
+// Builds the level schedule and blocked solve plan of one triangle of M (the
+// upper plan must be built first: the lower plan records positions in it).
+void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *upper_plan, hipStream_t s);
 
 }  // namespace hec

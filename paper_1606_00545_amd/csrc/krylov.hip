@@ -29,7 +29,7 @@ constexpr int kMaxRedBlocks = 1024;
 constexpr int kMaxRestart = 32;  // the orthogonalisation keeps up to 32 basis coefficients in registers
 
 inline int red_blocks(int64_t n) {
-    int64_t b = (n + RB * 4 - 1) / (RB * 4);
+    int64_t b = (n + RB * 2 - 1) / (RB * 2);
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxRedBlocks));
 }
 
@@ -171,117 +171,143 @@ struct OpCycleStart : NoInit {
     }
 };
 
-// CGS pass 1: h1[k] = <V_k, w>, k < nv
-template <class VT, int NV>
-struct OpCgs1 : NoInit {
-    const VT *V;
-    int64_t ldv;
-    const VT *w;
-    int nv;
-    double *h1;
-    __device__ void row(int64_t i, double (&acc)[NV], double *) const {
-        double wi = w[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) acc[k] += (double)V[k * ldv + i] * wi;
+// Givens step of column j (one thread): H(:, j) = h1 + h2, h_{j+1,j} = hn, the
+// earlier rotations applied to the column, a new rotation zeroing h_{j+1,j},
+// g updated, and the convergence test |g_{j+1}| <= tol (or hn == 0).
+__device__ void givens_finish(int j, double hn, double *sd, int32_t *si, int32_t *hf, const GLayout &L) {
+    for (int k = 0; k <= j; ++k) sd[L.Hij(k, j)] = sd[L.h1 + k] + sd[L.h2 + k];
+    sd[SD_HNEXT] = hn;
+    for (int k = 0; k < j; ++k) {
+        double a = sd[L.Hij(k, j)], c = sd[L.Hij(k + 1, j)];
+        double cs = sd[L.cs + k], sn = sd[L.sn + k];
+        sd[L.Hij(k, j)] = cs * a + sn * c;
+        sd[L.Hij(k + 1, j)] = -sn * a + cs * c;
     }
-    __device__ void finish(const double *t) const {
-        for (int k = 0; k < nv; ++k) h1[k] = t[k];
+    double a = sd[L.Hij(j, j)], c = hn;
+    double rr = hypot(a, c);
+    double cs = 1.0, sn = 0.0;
+    if (c != 0.0) {
+        cs = a / rr;
+        sn = c / rr;
     }
-};
+    sd[L.cs + j] = cs;
+    sd[L.sn + j] = sn;
+    sd[L.Hij(j, j)] = cs * a + sn * c;
+    double gj = sd[L.g + j];
+    sd[L.g + j + 1] = -sn * gj;
+    sd[L.g + j] = cs * gj;
+    double res = fabs(sd[L.g + j + 1]);
+    sd[SD_RES] = res;
+    si[SI_JDONE] = j + 1;
+    mirror(hf, SI_JDONE, j + 1);
+    if (!(res > sd[SD_TOL]) || hn == 0.0 || !isfinite(res)) {
+        si[SI_DONE] = 1;
+        mirror(hf, SI_DONE, 1);
+    }
+}
 
-// CGS pass 2: w -= V h1, h2[k] = <V_k, w>
-template <class VT, int NV>
-struct OpCgs2 {
-    const VT *V;
-    int64_t ldv;
-    VT *w;
-    int nv;
-    const double *h1;
-    double *h2;
-    __device__ void init(double *sh) const {
-        if ((int)threadIdx.x < nv) sh[threadIdx.x] = h1[threadIdx.x];
-    }
-    __device__ void row(int64_t i, double (&acc)[NV], double *sh) const {
-        double vk[NV];
-        double wi = w[i];
+// Classical Gram-Schmidt passes over the basis V (vectors of type VT, FP64 sums):
+//   MODE 1: hout[k] = <V_k, w>                                  k < nv
+//   MODE 2: w -= V hin;  hout[k] = <V_k, w>
+//   MODE 3: w -= V hin;  ||w||^2, then the Givens step of column nv-1
+// A workgroup's 4 wavefronts take the same 64 rows at a time; wavefront q owns
+// the vectors k = q, q+4, q+8, ... (8 sums per thread for up to 32 vectors).
+// The update w -= V hin adds the 4 wavefronts' partial sums in a fixed order
+// through LDS; every sum is reduced in a fixed order (deterministic).
+template <class VT, int MODE>
+__global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V, int64_t ldv, VT *w, int nv,
+                                            const double *__restrict__ hin, double *hout, double *part,
+                                            uint32_t *counter, const int32_t *skip, double *sd, int32_t *si,
+                                            int32_t *hf, GLayout L) {
+    constexpr int KW = kMaxRestart / 4;  // vectors per wavefront
+    constexpr int NS = kMaxRestart + 1;  // sums per workgroup: nv dots (+ the norm)
+    if (skip && *skip) return;
+    __shared__ double sh[kMaxRestart];
+    __shared__ double px[4][64];
+    __shared__ double red[NS];
+    __shared__ double wred[4][NS];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    if (MODE != 1 && (int)threadIdx.x < nv) sh[threadIdx.x] = hin[threadIdx.x];
+    __syncthreads();
+    double acc[KW];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            if (k < nv) {
-                vk[k] = V[k * ldv + i];
-                wi -= sh[k] * vk[k];
+    for (int u = 0; u < KW; ++u) acc[u] = 0.0;
+    double nrm = 0.0;
+    const int64_t ntiles = (n + 63) / 64;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t i = t * 64 + lane;
+        const bool in = i < n;
+        double vk[KW];
+#pragma unroll
+        for (int u = 0; u < KW; ++u) {
+            const int k = q + 4 * u;
+            vk[u] = (in && k < nv) ? (double)V[k * ldv + i] : 0.0;
+        }
+        double wi = in ? (double)w[i] : 0.0;
+        if constexpr (MODE != 1) {
+            double ps = 0.0;
+#pragma unroll
+            for (int u = 0; u < KW; ++u) {
+                const int k = q + 4 * u;
+                if (k < nv) ps += sh[k] * vk[u];
             }
+            px[q][lane] = ps;
+            __syncthreads();
+            wi -= ((px[0][lane] + px[1][lane]) + px[2][lane]) + px[3][lane];
+            const VT ws = (VT)wi;
+            wi = (double)ws;
+            if (q == 0 && in) w[i] = ws;
+            __syncthreads();
         }
-        VT ws = (VT)wi;
-        w[i] = ws;
-        double wr = ws;
+        if constexpr (MODE == 3) {
+            if (q == 0) nrm += wi * wi;
+        } else {
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) acc[k] += vk[k] * wr;
+            for (int u = 0; u < KW; ++u) acc[u] += vk[u] * wi;
+        }
     }
-    __device__ void finish(const double *t) const {
-        for (int k = 0; k < nv; ++k) h2[k] = t[k];
-    }
-};
-
-// CGS pass 3: w -= V h2, ||w||^2; then column j of H (h1 + h2, ||w||), the
-// previous Givens rotations, a new rotation, g, and the convergence test.
-template <class VT, int NV>
-struct OpCgs3 {
-    const VT *V;
-    int64_t ldv;
-    VT *w;
-    int nv;  // = j + 1
-    double *sd;
-    int32_t *si, *hf;
-    GLayout L;
-    __device__ void init(double *sh) const {
-        if ((int)threadIdx.x < nv) sh[threadIdx.x] = sd[L.h2 + threadIdx.x];
-    }
-    __device__ void row(int64_t i, double (&acc)[1], double *sh) const {
-        double wi = w[i];
+    // per-workgroup sums: wavefront q reduces its own vectors; the norm lives in slot kMaxRestart
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) wi -= sh[k] * (double)V[k * ldv + i];
-        VT ws = (VT)wi;
-        w[i] = ws;
-        double wr = ws;
-        acc[0] += wr * wr;
-    }
-    __device__ void finish(const double *t) const {
-        const int j = nv - 1;
-        double hn = sqrt(t[0]);
-        for (int k = 0; k <= j; ++k) sd[L.Hij(k, j)] = sd[L.h1 + k] + sd[L.h2 + k];
-        sd[SD_HNEXT] = hn;
-        for (int k = 0; k < j; ++k) {
-            double a = sd[L.Hij(k, j)], c = sd[L.Hij(k + 1, j)];
-            double cs = sd[L.cs + k], sn = sd[L.sn + k];
-            sd[L.Hij(k, j)] = cs * a + sn * c;
-            sd[L.Hij(k + 1, j)] = -sn * a + cs * c;
-        }
-        double a = sd[L.Hij(j, j)], c = hn;
-        double rr = hypot(a, c);
-        double cs = 1.0, sn = 0.0;
-        if (c != 0.0) {
-            cs = a / rr;
-            sn = c / rr;
-        }
-        sd[L.cs + j] = cs;
-        sd[L.sn + j] = sn;
-        sd[L.Hij(j, j)] = cs * a + sn * c;
-        double gj = sd[L.g + j];
-        sd[L.g + j + 1] = -sn * gj;
-        sd[L.g + j] = cs * gj;
-        double res = fabs(sd[L.g + j + 1]);
-        sd[SD_RES] = res;
-        si[SI_JDONE] = j + 1;
-        mirror(hf, SI_JDONE, j + 1);
-        if (!(res > sd[SD_TOL]) || hn == 0.0 || !isfinite(res)) {
-            si[SI_DONE] = 1;
-            mirror(hf, SI_DONE, 1);
+    for (int u = 0; u < KW; ++u) {
+        const int k = q + 4 * u;
+        if (MODE != 3 && k < nv) {
+            double v = wave_sum(acc[u]);
+            if (lane == 0) red[k] = v;
         }
     }
-};
+    if (MODE == 3 && q == 0) {
+        double v = wave_sum(nrm);
+        if (lane == 0) red[kMaxRestart] = v;
+    }
+    __syncthreads();
+    const int lo = MODE == 3 ? kMaxRestart : 0, hi = MODE == 3 ? kMaxRestart + 1 : nv;
+    if ((int)threadIdx.x >= lo && (int)threadIdx.x < hi) {
+        part[(size_t)blockIdx.x * NS + threadIdx.x] = red[threadIdx.x];
+        __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // the last workgroup: sum the partial sums over workgroups in a fixed order
+    for (int k = lo + q; k < hi; k += 4) {
+        double s = 0.0;
+        for (int b = lane; b < (int)gridDim.x; b += 64) s += part[(size_t)b * NS + k];
+        s = wave_sum(s);
+        if (lane == 0) wred[0][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if constexpr (MODE == 3) {
+            givens_finish(nv - 1, sqrt(wred[0][kMaxRestart]), sd, si, hf, L);
+        } else {
+            for (int k = 0; k < nv; ++k) hout[k] = wred[0][k];
+        }
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // v = r / beta (start of a cycle)
 template <class VT, class RT>
@@ -540,7 +566,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     GLayout L(std::max(mm, 1));
     nw->sd.alloc(std::max(L.total, SD_SCALARS + 8));
     nw->si.alloc(SI_COUNT);
-    nw->part.alloc((size_t)nw->nred * kMaxRestart);
+    nw->part.alloc((size_t)nw->nred * (kMaxRestart + 1));
     nw->counter.alloc(1);
     HEC_HIP(hipMemsetAsync(nw->counter.get(), 0, sizeof(uint32_t), s));
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
@@ -601,18 +627,16 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
         trsv_launch<VT>(lv, HEC_LU, vj, zj, s, done);
         spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
         const int nv = j + 1;
-        auto run = [&](auto nvtag) {
-            constexpr int NV = decltype(nvtag)::value;
-            OpCgs1<VT, NV> p1{{}, V, ldv, w, nv, sd + L.h1};
-            launch_pass<NV>(ws, n, p1, nv, s, done);
-            OpCgs2<VT, NV> p2{V, ldv, w, nv, sd + L.h1, sd + L.h2};
-            launch_pass<NV>(ws, n, p2, nv, s, done);
-            OpCgs3<VT, NV> p3{V, ldv, w, nv, sd, si, ws.dflags, L};
-            launch_pass<1>(ws, n, p3, 1, s, done);
-        };
-        if (nv <= 8) run(std::integral_constant<int, 8>());
-        else if (nv <= 16) run(std::integral_constant<int, 16>());
-        else run(std::integral_constant<int, 32>());
+        const unsigned g = ws.nred;
+        k_cgs<VT, 1><<<g, RB, 0, s>>>(n, V, ldv, w, nv, nullptr, sd + L.h1, ws.part.get(), ws.counter.get(),
+                                      done, sd, si, ws.dflags, L);
+        HEC_CHECK_LAUNCH();
+        k_cgs<VT, 2><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h1, sd + L.h2, ws.part.get(), ws.counter.get(),
+                                      done, sd, si, ws.dflags, L);
+        HEC_CHECK_LAUNCH();
+        k_cgs<VT, 3><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h2, nullptr, ws.part.get(), ws.counter.get(),
+                                      done, sd, si, ws.dflags, L);
+        HEC_CHECK_LAUNCH();
         if (j + 1 < mcyc) {
             k_scale_next<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, w, V + (j + 1) * ldv, sd, done);
             HEC_CHECK_LAUNCH();

@@ -1,0 +1,680 @@
+// Level-scheduled triangular solves (Sec. 2.6, Alg. 3), as one persistent
+// launch per triangle in which rows of successive levels are solved inside a
+// workgroup with their dependencies held in LDS.
+//
+// Plan (built once per factor on the host, see build_tri):
+//  * the rows are cut into parts: contiguous row ranges in the order the
+//    triangle is solved (ascending rows for L, descending for U). Every
+//    dependency of a row lies in its own part or in an earlier part, so the
+//    parts form a chain that can be claimed in order from a ticket counter:
+//    a part only ever waits for parts already claimed by running workgroups,
+//    hence no deadlock at any occupancy or grid size;
+//  * inside a part the rows are laid out by (level, row) (Alg. 3's order) and
+//    cut into sub-segments of at most 64 rows of one level.
+//
+// Execution (k_trsv_blk): one workgroup per part, 1 solver wavefront and 15
+// prefetching wavefronts.
+//  * Prefetchers stream the next sub-segments into a ring of LDS slots: the
+//    right-hand side (already gathered into position order), the row's
+//    entries, and the values of dependencies in earlier parts, polled from
+//    global memory until final;
+//  * the solver takes sub-segments in order, reads dependencies inside the part
+//    from a small LDS ring of recent results and dependencies outside it from
+//    the slot, and publishes each result to global memory. It never waits on
+//    global memory itself.
+//  * Readiness of a value across parts is the value itself: the output vector
+//    is pre-filled with a signalling-NaN bit pattern that arithmetic never
+//    produces; results are stored and polled with device-coherent (agent
+//    scope) accesses, so only single-location coherence is needed and no
+//    cache-wide fence is issued.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <type_traits>
+
+#include "hec_internal.hpp"
+
+namespace hec {
+
+namespace {
+
+constexpr int kPrefetchWaves = 15;
+constexpr int kBlkThreads = 64 * (1 + kPrefetchWaves);
+constexpr int kSub = 64;            // rows per sub-segment (one solver wavefront)
+constexpr int kPad = INT_MIN;       // padding entry of a row shorter than K
+constexpr int kBatch = 8;           // entries loaded per batch by a prefetcher lane
+
+#ifndef HEC_TRSV_TARGET_PARTS
+#define HEC_TRSV_TARGET_PARTS 64
+#endif
+#ifndef HEC_TRSV_MIN_PART_ROWS
+#define HEC_TRSV_MIN_PART_ROWS 4096
+#endif
+#ifndef HEC_TRSV_TILE_PARTS
+#define HEC_TRSV_TILE_PARTS 256
+#endif
+#ifndef HEC_TRSV_MAX_RING
+#define HEC_TRSV_MAX_RING 32
+#endif
+
+template <class T> struct Sentinel;
+template <> struct Sentinel<double> {
+    using U = unsigned long long;
+    static constexpr U bits = 0x7FF4DEADBEEF1234ull;  // signalling NaN: never produced by arithmetic
+    static constexpr U qnan = 0x7FF8000000000000ull;
+};
+template <> struct Sentinel<float> {
+    using U = unsigned int;
+    static constexpr U bits = 0x7FA0BEEFu;
+    static constexpr U qnan = 0x7FC00000u;
+};
+
+template <class T>
+__device__ __forceinline__ typename Sentinel<T>::U load_coherent(const T *p) {
+    using U = typename Sentinel<T>::U;
+    return __hip_atomic_load((U *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes a solved value. A right-hand side that carries the sentinel's own
+// bit pattern (and reaches the output untouched by arithmetic) is replaced by
+// a quiet NaN, so no waiting row can mistake a final value for "not ready".
+template <class T>
+__device__ __forceinline__ void store_coherent(T *p, T v) {
+    using U = typename Sentinel<T>::U;
+    U u;
+    __builtin_memcpy(&u, &v, sizeof(T));
+    if (u == Sentinel<T>::bits) u = Sentinel<T>::qnan;
+    __hip_atomic_store((U *)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T from_bits(typename Sentinel<T>::U u) {
+    T v;
+    __builtin_memcpy(&v, &u, sizeof(T));
+    return v;
+}
+
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
+// Byte offsets inside one LDS slot (64 rows of one sub-segment, KC entries per
+// row: the row's entries padded to a compile-time width).
+template <class T, bool UPPER>
+struct Slot {
+    int KC;
+    __host__ __device__ size_t b() const { return 0; }                                    // T[64]
+    __host__ __device__ size_t xe() const { return b() + kSub * sizeof(T); }              // T[KC][64]
+    __host__ __device__ size_t v() const { return xe() + (size_t)KC * kSub * sizeof(T); }  // T[KC][64]
+    __host__ __device__ size_t d() const { return v() + (size_t)KC * kSub * sizeof(T); }   // T[64] (U)
+    __host__ __device__ size_t gi() const { return d() + (UPPER ? kSub * sizeof(T) : 0); }  // int[64]
+    __host__ __device__ size_t po() const { return gi() + kSub * sizeof(int); }           // int[64]
+    __host__ __device__ size_t a() const { return po() + kSub * sizeof(int); }            // int[KC][64]
+    __host__ __device__ size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
+};
+
+// LDS: [filled[D] | consumed | part | zero (16 B)] [part's sub-segment
+//      starts, S+1] [ring of recent results, W] [D slots]
+__host__ __device__ inline size_t ctrl_head(int D) { return align16((size_t)(D + 2) * sizeof(int)) + 16; }
+__host__ __device__ inline size_t ctrl_bytes(int D, int S) {
+    return ctrl_head(D) + align16((size_t)(S + 1) * sizeof(int));
+}
+
+template <class T, bool UPPER>
+size_t lds_bytes(int KC, int W, int D, int S) {
+    return ctrl_bytes(D, S) + align16((size_t)W * sizeof(T)) + (size_t)D * Slot<T, UPPER>{KC}.bytes();
+}
+
+struct PlanArgs {
+    int32_t nparts, K, ldq, W, D, S;  // S: most sub-segments in one part
+    const int32_t *part_ss, *part_pos, *ss_pos, *grow, *other, *enc;
+};
+
+// A value that is never the sentinel: the target of the polls of entries that
+// need none, so that every lane issues its loads together.
+__device__ double g_zero64 = 0.0;
+__device__ float g_zero32 = 0.0f;
+template <class T> __device__ __forceinline__ const T *zero_addr();
+template <> __device__ __forceinline__ const double *zero_addr<double>() { return &g_zero64; }
+template <> __device__ __forceinline__ const float *zero_addr<float>() { return &g_zero32; }
+
+template <class T, bool UPPER, int KC>
+__global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *__restrict__ val,
+                                                          const T *__restrict__ piv, const T *__restrict__ bperm,
+                                                          T *x, T *yother, uint32_t *sync, const int32_t *skip) {
+    using U = typename Sentinel<T>::U;
+    constexpr U SENT = Sentinel<T>::bits;
+    if (skip && *skip) return;  // uniform: no workgroup touches the counters
+    extern __shared__ __align__(16) char smem[];
+    const int D = P.D, K = P.K, W = P.W;
+    int *filled = (int *)smem;
+    int *consumed = filled + D;
+    int *s_part = consumed + 1;
+    const uint32_t zero_off = (uint32_t)(ctrl_head(D) - 16);
+    int *sspos = (int *)(smem + ctrl_head(D));
+    const uint32_t sx_off = (uint32_t)ctrl_bytes(D, P.S);
+    T *sx = (T *)(smem + sx_off);
+    const uint32_t slots_off = sx_off + (uint32_t)align16((size_t)W * sizeof(T));
+    const Slot<T, UPPER> L{KC};
+    const uint32_t sb = (uint32_t)L.bytes();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < 4) ((int *)(smem + zero_off))[threadIdx.x] = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            *s_part = (int)atomicAdd(&sync[0], 1u);
+            *consumed = 0;
+        }
+        if ((int)threadIdx.x < D) filled[threadIdx.x] = -1;
+        __syncthreads();
+        const int p = *s_part;
+        if (p >= P.nparts) break;
+        const int kb = P.part_ss[p], nss = P.part_ss[p + 1] - kb, pos0 = P.part_pos[p];
+        for (int t = threadIdx.x; t <= nss; t += blockDim.x) sspos[t] = P.ss_pos[kb + t];
+        __syncthreads();
+
+        if (wave == 0) {
+            // ---------------- solver: two LDS round trips and KC fused multiply-adds per row
+            __builtin_amdgcn_s_setprio(3);
+            int slot = 0;
+            for (int rel = 0; rel < nss; ++rel) {
+                while (__hip_atomic_load(&filled[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != rel)
+                    __builtin_amdgcn_s_sleep(1);
+                const int q0 = sspos[rel], cnt = sspos[rel + 1] - q0;  // rows and first position
+                const char *sl = smem + slots_off + slot * sb;
+                T acc = ((const T *)(sl + L.b()))[lane];
+                const int gi = ((const int *)(sl + L.gi()))[lane];
+                const int po = ((const int *)(sl + L.po()))[lane];
+                T dd = (T)1;
+                if constexpr (UPPER) dd = ((const T *)(sl + L.d()))[lane];
+                uint32_t ad[KC];
+                T av[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) {
+                    ad[u] = ((const uint32_t *)(sl + L.a()))[u * kSub + lane];
+                    av[u] = ((const T *)(sl + L.v()))[u * kSub + lane];
+                }
+                T xv[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) xv[u] = *(const T *)(smem + ad[u]);
+#pragma unroll
+                for (int u = 0; u < KC; ++u) acc -= av[u] * xv[u];
+                if constexpr (UPPER) acc = acc / dd;
+                if (lane < cnt) {
+                    sx[(q0 - pos0 + lane) & (W - 1)] = acc;
+                    store_coherent(x + gi, acc);
+                    if (yother) yother[po] = acc;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0) __hip_atomic_store(consumed, rel + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                slot = slot + 1 == D ? 0 : slot + 1;
+            }
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            // ---------------- prefetchers: every lane of a slot is written (idle lanes get padding)
+            const int w = wave - 1;
+            for (int rel = w; rel < nss; rel += kPrefetchWaves) {
+                const int slot = rel % D;
+                while (__hip_atomic_load(consumed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < rel - D + 1)
+                    __builtin_amdgcn_s_sleep(4);
+                const int q0 = sspos[rel], cnt = sspos[rel + 1] - q0;
+                const uint32_t so = slots_off + slot * sb;
+                char *sl = smem + so;
+                const bool live = lane < cnt;
+                const int q = q0 + (live ? lane : 0);
+                T bb = live ? bperm[q] : (T)0;
+                int gi = live ? P.grow[q] : 0;
+                int po = live && P.other ? P.other[q] : 0;
+                T dd = (T)1;
+                if constexpr (UPPER) dd = live ? piv[q] : (T)1;
+                constexpr int B = KC < kBatch ? KC : kBatch;
+                for (int s0 = 0; s0 < KC; s0 += B) {
+                    int es[B];
+                    T vs[B];
+                    U xs[B];
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        es[u] = kPad;
+                        vs[u] = (T)0;
+                        if (live && s0 + u < K) {
+                            es[u] = P.enc[(size_t)(s0 + u) * P.ldq + q];
+                            vs[u] = val[(size_t)(s0 + u) * P.ldq + q];
+                        }
+                    }
+                    // every lane polls all its entries at once; entries without an
+                    // outside dependency read a constant zero
+#pragma unroll
+                    for (int u = 0; u < B; ++u) xs[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
+                    bool pend = false;
+#pragma unroll
+                    for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
+                    while (pend) {
+                        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                        for (int u = 0; u < B; ++u)
+                            if (xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
+                        pend = false;
+#pragma unroll
+                        for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
+                    }
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        const int s = s0 + u;
+                        {
+                            const uint32_t xe_at = so + (uint32_t)(L.xe() + (size_t)(s * kSub + lane) * sizeof(T));
+                            uint32_t at = zero_off;  // padding: value 0 times a zero
+                            if (es[u] >= 0) at = xe_at;
+                            else if (es[u] != kPad) at = sx_off + (uint32_t)(((-1 - es[u]) & (W - 1)) * sizeof(T));
+                            ((uint32_t *)(sl + L.a()))[s * kSub + lane] = at;
+                            ((T *)(sl + L.v()))[s * kSub + lane] = vs[u];
+                            ((T *)(sl + L.xe()))[s * kSub + lane] = from_bits<T>(xs[u]);
+                        }
+                    }
+                }
+                ((T *)(sl + L.b()))[lane] = bb;
+                ((int *)(sl + L.gi()))[lane] = gi;
+                ((int *)(sl + L.po()))[lane] = po;
+                if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = dd;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0) __hip_atomic_store(&filled[slot], rel, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        uint32_t d = atomicAdd(&sync[1], 1u);
+        if (d == gridDim.x - 1) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Fallback for triangles whose rows are too long for the LDS slots: rows in
+// level order cut into 64-row chunks inside a level, wavefronts take chunks in
+// increasing order from a ticket counter and poll every dependency in global
+// memory (a chunk only waits for chunks taken by running wavefronts).
+template <class T, bool UPPER>
+__global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t *__restrict__ chunk_ptr, int32_t K,
+                                                 int32_t ldq, const int32_t *__restrict__ grow,
+                                                 const int32_t *__restrict__ other, const int32_t *__restrict__ enc,
+                                                 const T *__restrict__ val, const T *__restrict__ piv,
+                                                 const T *__restrict__ bperm, T *x, T *yother, uint32_t *sync,
+                                                 const int32_t *skip) {
+    using U = typename Sentinel<T>::U;
+    constexpr U SENT = Sentinel<T>::bits;
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&sync[0], 1u);
+        t = __shfl(t, 0);
+        if (t >= (uint32_t)nchunks) break;
+        const int32_t q = chunk_ptr[t] + lane;
+        if (q < chunk_ptr[t + 1]) {
+            T acc = bperm[q];
+            for (int32_t s0 = 0; s0 < K; s0 += kBatch) {
+                const int nb = min(kBatch, K - s0);
+                int es[kBatch];
+                T vs[kBatch];
+                U xs[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    es[u] = kPad;
+                    vs[u] = (T)0;
+                    if (u < nb) {
+                        es[u] = enc[(size_t)(s0 + u) * ldq + q];
+                        vs[u] = val[(size_t)(s0 + u) * ldq + q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u)
+                    if (u < nb) xs[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
+                bool pend = false;
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) pend |= u < nb && xs[u] == SENT;
+                while (pend) {
+                    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u)
+                        if (u < nb && xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
+                    pend = false;
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u) pend |= u < nb && xs[u] == SENT;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u)
+                    if (u < nb && es[u] != kPad) acc -= vs[u] * from_bits<T>(xs[u]);
+            }
+            if constexpr (UPPER) acc = acc / piv[q];
+            store_coherent(x + grow[q], acc);
+            if (yother) yother[other[q]] = acc;
+        }
+    }
+    if (lane == 0) {
+        const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+        uint32_t d = atomicAdd(&sync[1], 1u);
+        if (d == nwaves - 1) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Before a solve: outputs filled with the sentinel, right-hand side gathered
+// into the plan's position order.
+template <class T>
+__global__ __launch_bounds__(256) void k_trsv_prep(int64_t n, const int32_t *__restrict__ grow,
+                                                   const T *__restrict__ b, T *__restrict__ bperm, T *x1, T *x2,
+                                                   const int32_t *skip) {
+    if (skip && *skip) return;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const T s = from_bits<T>(Sentinel<T>::bits);
+    bperm[q] = b[grow[q]];
+    x1[q] = s;
+    if (x2) x2[q] = s;
+}
+
+// dst[q] = src[map[q]] (0 where map[q] < 0), optional FP32 copy.
+__global__ __launch_bounds__(256) void k_gather(size_t n, const int32_t *__restrict__ map,
+                                                const double *__restrict__ src, double *__restrict__ dst,
+                                                float *__restrict__ dst32) {
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int32_t m = map[q];
+    double v = m >= 0 ? src[m] : 0.0;
+    dst[q] = v;
+    if (dst32) dst32[q] = (float)v;
+}
+
+int max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 64 * 1024;
+    return std::min(v, 160 * 1024);
+}
+
+template <class T, bool UPPER>
+void launch_blk(const hec_tri &tri, uint32_t *sync, const T *bperm, T *x, T *yother, hipStream_t s,
+                const int32_t *skip) {
+    if (tri.nparts == 0 && tri.nchunks == 0) return;
+    const bool f64 = sizeof(T) == 8;
+    if (!tri.blocked) {
+        const T *val = f64 ? (const T *)tri.val.get() : (const T *)tri.val32.get();
+        const T *piv = UPPER ? (f64 ? (const T *)tri.piv.get() : (const T *)tri.piv32.get()) : nullptr;
+        int waves = std::min(tri.nchunks, 1024);
+        k_trsv_sf<T, UPPER><<<(waves + 3) / 4, 256, 0, s>>>(tri.nchunks, tri.chunk_ptr.get(), tri.K, tri.ldq,
+                                                          tri.grow.get(), yother ? tri.other.get() : nullptr,
+                                                          tri.enc.get(), val, piv, bperm, x, yother, sync, skip);
+        HEC_CHECK_LAUNCH();
+        return;
+    }
+    const size_t lds = f64 ? tri.lds64 : tri.lds32;
+    PlanArgs P{tri.nparts, tri.K, tri.ldq, tri.W, f64 ? tri.D64 : tri.D32, tri.S,
+               tri.part_ss.get(), tri.part_pos.get(), tri.ss_pos.get(), tri.grow.get(),
+               yother ? tri.other.get() : nullptr, tri.enc.get()};
+    const T *val, *piv = nullptr;
+    if constexpr (sizeof(T) == 8) {
+        val = tri.val.get();
+        if (UPPER) piv = tri.piv.get();
+    } else {
+        val = tri.val32.get();
+        if (UPPER) piv = tri.piv32.get();
+    }
+    const int grid = std::min(tri.nparts, 256);
+    auto go = [&](auto kc) {
+        constexpr int KC = decltype(kc)::value;
+        static bool attr_set = false;  // one per instantiation
+        if (!attr_set) {
+            HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_blk<T, UPPER, KC>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_per_block()));
+            attr_set = true;
+        }
+        k_trsv_blk<T, UPPER, KC><<<grid, kBlkThreads, lds, s>>>(P, val, piv, bperm, x, yother, sync, skip);
+    };
+    switch (tri.KC) {
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 8: go(std::integral_constant<int, 8>()); break;
+        case 16: go(std::integral_constant<int, 16>()); break;
+        default: go(std::integral_constant<int, 32>()); break;
+    }
+    HEC_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+template <class T>
+void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s, const int32_t *skip) {
+    const int64_t n = lv.n;
+    if (n == 0) return;
+    T *y, *bp, *yp;
+    if constexpr (sizeof(T) == 8) {
+        y = lv.y64.get();
+        bp = lv.bp64.get();
+        yp = lv.yp64.get();
+    } else {
+        y = lv.y32.get();
+        bp = lv.bp32.get();
+        yp = lv.yp32.get();
+    }
+    uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
+    const unsigned g = ceil_div(n, 256);
+    if (which == HEC_LU) {
+        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.lower.grow.get(), b, bp, y, x, skip);
+        HEC_CHECK_LAUNCH();
+        launch_blk<T, false>(lv.lower, sync, bp, y, yp, s, skip);  // y = L^{-1} b, also into upper order
+        launch_blk<T, true>(lv.upper, sync + 2, yp, x, nullptr, s, skip);
+    } else if (which == HEC_LOWER) {
+        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.lower.grow.get(), b, bp, x, (T *)nullptr, skip);
+        HEC_CHECK_LAUNCH();
+        launch_blk<T, false>(lv.lower, sync, bp, x, nullptr, s, skip);
+    } else {
+        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.upper.grow.get(), b, bp, x, (T *)nullptr, skip);
+        HEC_CHECK_LAUNCH();
+        launch_blk<T, true>(lv.upper, sync + 2, bp, x, nullptr, s, skip);
+    }
+}
+
+template void trsv_launch<double>(const hec_levels_s &, uint32_t, const double *, double *, hipStream_t,
+                                  const int32_t *);
+template void trsv_launch<float>(const hec_levels_s &, uint32_t, const float *, float *, hipStream_t,
+                                 const int32_t *);
+
+void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *upper_plan, hipStream_t s) {
+    const int32_t n = M.n;
+    std::vector<int32_t> lev;
+    tri.nlev = compute_levels(n, M.hLUp, M.hLUj, M.hdiag, upper, tri.hlevel_ptr, tri.hperm, &lev);
+    int32_t K = 0;
+    for (int32_t i = 0; i < n; ++i)
+        K = std::max(K, upper ? M.hLUp[i + 1] - M.hdiag[i] - 1 : M.hdiag[i] - M.hLUp[i]);
+    tri.K = K;
+    tri.KC = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32;
+    tri.ldq = (int32_t)(((int64_t)n + 63) / 64 * 64);
+    if (n == 0) return;
+    const int lds_max = max_lds_per_block() - 256;
+
+    // Parts. With a recognised grid (natural-order 5/7-point stencil, see
+    // detect_grid) the rows are cut into x-y tiles spanning all z, numbered in
+    // the order the triangle is solved, when that keeps every dependency in the
+    // same or an earlier part; otherwise into contiguous row ranges.
+    int64_t R = std::max<int64_t>(HEC_TRSV_MIN_PART_ROWS, (n + HEC_TRSV_TARGET_PARTS - 1) / HEC_TRSV_TARGET_PARTS);
+    R = std::min<int64_t>(R, n);
+    std::vector<int32_t> part_of(n), pos(n), grow(n), part_pos, part_ss, ss_pos;
+    bool tiled = false;
+    int32_t ntiles = 0;
+    if (M.gnx > 0 && (int64_t)M.gnx * M.gny * M.gnz == n && n >= 2 * HEC_TRSV_MIN_PART_ROWS) {
+        const int64_t target = std::min<int64_t>(HEC_TRSV_TILE_PARTS, n / HEC_TRSV_MIN_PART_ROWS);
+        const int64_t plane = (int64_t)M.gnx * M.gny;
+        int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
+        const int32_t tx = (int32_t)std::min<int64_t>(T, M.gnx), ty = (int32_t)std::min<int64_t>(T, M.gny);
+        const int32_t PX = (M.gnx + tx - 1) / tx, PY = (M.gny + ty - 1) / ty;
+        ntiles = PX * PY;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t xx = i % M.gnx, yy = (i / M.gnx) % M.gny;
+            int32_t t = xx / tx + PX * (yy / ty);
+            part_of[i] = upper ? ntiles - 1 - t : t;
+        }
+        tiled = ntiles > 1;
+        for (int32_t i = 0; i < n && tiled; ++i) {  // every dependency in the same or an earlier part
+            int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
+            int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
+            for (int32_t e = a; e < b; ++e)
+                if (part_of[M.hLUj[e]] > part_of[i]) { tiled = false; break; }
+        }
+    }
+    int32_t W = 64, S = 0;
+    int D64 = 0, D32 = 0;
+    for (;;) {
+        int32_t nparts;
+        if (tiled) {
+            nparts = ntiles;
+        } else {
+            nparts = (int32_t)((n + R - 1) / R);
+            for (int32_t i = 0; i < n; ++i) part_of[i] = (int32_t)((upper ? (int64_t)(n - 1 - i) : (int64_t)i) / R);
+        }
+        part_pos.assign(nparts + 1, 0);
+        for (int32_t i = 0; i < n; ++i) part_pos[part_of[i] + 1]++;
+        for (int32_t p = 0; p < nparts; ++p) part_pos[p + 1] += part_pos[p];
+        // positions: each part's rows in (level, row) order, i.e. the global schedule restricted to the part
+        std::vector<int32_t> fillp(part_pos.begin(), part_pos.end() - 1);
+        for (int32_t t = 0; t < n; ++t) {
+            int32_t i = tri.hperm[t];
+            int32_t q = fillp[part_of[i]]++;
+            pos[i] = q;
+            grow[q] = i;
+        }
+        // sub-segments: runs of one level inside a part, at most 64 rows
+        part_ss.assign(nparts + 1, 0);
+        ss_pos.clear();
+        for (int32_t p = 0; p < nparts; ++p) {
+            part_ss[p] = (int32_t)ss_pos.size();
+            int32_t q = part_pos[p];
+            while (q < part_pos[p + 1]) {
+                ss_pos.push_back(q);
+                int32_t l = lev[grow[q]];
+                int32_t e = q + 1;
+                while (e < part_pos[p + 1] && e - q < kSub && lev[grow[e]] == l) ++e;
+                q = e;
+            }
+        }
+        part_ss[nparts] = (int32_t)ss_pos.size();
+        ss_pos.push_back(n);
+        // ring of recent results: must span the longest distance to an in-part dependency
+        int64_t maxd = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
+            int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
+            for (int32_t e = a; e < b; ++e) {
+                int32_t j = M.hLUj[e];
+                if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, pos[i] - pos[j]);
+            }
+        }
+        W = 64;
+        while (W < maxd + kSub) W *= 2;
+        S = 0;
+        for (int32_t p = 0; p < nparts; ++p) S = std::max(S, part_ss[p + 1] - part_ss[p]);
+        auto fit = [&](auto tag) {
+            using T = decltype(tag);
+            int best = 0;
+            for (int D = 4; D <= HEC_TRSV_MAX_RING; ++D) {
+                size_t b = upper ? lds_bytes<T, true>(tri.KC, W, D, S) : lds_bytes<T, false>(tri.KC, W, D, S);
+                if ((int64_t)b <= lds_max) best = D;
+            }
+            return best;
+        };
+        D64 = fit(double());
+        D32 = M.has_f32 ? fit(float()) : 4;
+        if ((D64 >= 4 && D32 >= 4) || R <= kSub || K > 32) break;
+        tiled = false;                       // fall back to (smaller) contiguous parts
+        R = std::max<int64_t>(kSub, R / 2);  // a smaller part keeps the ring of results smaller
+    }
+    tri.blocked = D64 >= 4 && D32 >= 4 && K <= 32;
+    if (!tri.blocked) {
+        // rows too long for the LDS slots: one part per row in level order, every
+        // dependency polled in global memory, 64-row chunks inside each level
+        for (int32_t t = 0; t < n; ++t) {
+            grow[t] = tri.hperm[t];
+            pos[tri.hperm[t]] = t;
+            part_of[tri.hperm[t]] = t;
+        }
+        part_pos.assign(2, 0);
+        part_pos[1] = n;
+        std::vector<int32_t> chunks{0};
+        for (int32_t l = 0; l < tri.nlev; ++l)
+            for (int32_t q = tri.hlevel_ptr[l]; q < tri.hlevel_ptr[l + 1]; q += kSub)
+                chunks.push_back(std::min(q + kSub, tri.hlevel_ptr[l + 1]));
+        tri.nchunks = (int32_t)chunks.size() - 1;
+        tri.chunk_ptr.alloc(chunks.size());
+        tri.chunk_ptr.upload(chunks.data(), chunks.size(), s);
+        part_ss.assign(2, 0);
+        ss_pos.assign(1, 0);
+    }
+    const int32_t nparts = tri.blocked ? (int32_t)part_pos.size() - 1 : 0;
+    tri.nparts = nparts;
+    tri.nss = (int32_t)ss_pos.size() - 1;
+    tri.W = W;
+    tri.S = S;
+    tri.D64 = D64;
+    tri.D32 = D32;
+    tri.lds64 = upper ? lds_bytes<double, true>(tri.KC, W, D64, S) : lds_bytes<double, false>(tri.KC, W, D64, S);
+    tri.lds32 = upper ? lds_bytes<float, true>(tri.KC, W, D32, S) : lds_bytes<float, false>(tri.KC, W, D32, S);
+
+    // entries per position: in-part dependencies by local position, others by row
+    const size_t slab = (size_t)K * tri.ldq;
+    std::vector<int32_t> enc(slab, kPad), src(slab, -1), psrc;
+    if (upper) psrc.assign(tri.ldq, -1);
+    for (int32_t q = 0; q < n; ++q) {
+        int32_t i = grow[q];
+        int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
+        int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
+        int32_t pstart = tri.blocked ? part_pos[part_of[i]] : 0;
+        for (int32_t e = a, s2 = 0; e < b; ++e, ++s2) {
+            int32_t j = M.hLUj[e];
+            enc[(size_t)s2 * tri.ldq + q] = tri.blocked && part_of[j] == part_of[i] ? -(pos[j] - pstart + 1) : j;
+            src[(size_t)s2 * tri.ldq + q] = e;
+        }
+        if (upper) psrc[q] = M.hdiag[i];
+    }
+    tri.part_ss.alloc(part_ss.size());
+    tri.part_ss.upload(part_ss.data(), part_ss.size(), s);
+    tri.part_pos.alloc(part_pos.size());
+    tri.part_pos.upload(part_pos.data(), part_pos.size(), s);
+    tri.ss_pos.alloc(ss_pos.size());
+    tri.ss_pos.upload(ss_pos.data(), ss_pos.size(), s);
+    tri.grow.alloc(n);
+    tri.grow.upload(grow.data(), n, s);
+    if (!upper && upper_plan) {
+        // position of each lower-plan row in the upper plan
+        std::vector<int32_t> up_pos(n), other(n);
+        std::vector<int32_t> ug(n);
+        upper_plan->grow.download(ug.data(), n, s);
+        HEC_HIP(hipStreamSynchronize(s));
+        for (int32_t q = 0; q < n; ++q) up_pos[ug[q]] = q;
+        for (int32_t q = 0; q < n; ++q) other[q] = up_pos[grow[q]];
+        tri.other.alloc(n);
+        tri.other.upload(other.data(), n, s);
+    }
+    tri.enc.alloc(slab);
+    tri.enc.upload(enc.data(), slab, s);
+    tri.val.alloc(slab);
+    if (M.has_f32) tri.val32.alloc(slab);
+    DevBuf<int32_t> dsrc(slab);
+    if (slab) {
+        dsrc.upload(src.data(), slab, s);
+        k_gather<<<ceil_div(slab, 256), 256, 0, s>>>(slab, dsrc.get(), M.LUx.get(), tri.val.get(), tri.val32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    DevBuf<int32_t> dp;
+    if (upper) {
+        tri.piv.alloc(tri.ldq);
+        if (M.has_f32) tri.piv32.alloc(tri.ldq);
+        dp.alloc(tri.ldq);
+        dp.upload(psrc.data(), tri.ldq, s);
+        k_gather<<<ceil_div(tri.ldq, 256), 256, 0, s>>>(tri.ldq, dp.get(), M.LUx.get(), tri.piv.get(),
+                                                        tri.piv32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    HEC_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace hec

@@ -21,6 +21,11 @@ def _cases():
     yield "tpfa3d_k2", synth.lognormal_tpfa((9, 8, 7), 1.0, np.random.default_rng(3)), 2
     yield "tpfa2d_k3", synth.lognormal_tpfa((31, 23), 2.0, np.random.default_rng(4)), 3
     yield "random_k1", random_sparse(500, 0.008, np.random.default_rng(5)), 1
+    # several parts in the blocked solve, ragged last part
+    yield "tpfa3d_41x37x23_k0", synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0
+    yield "tpfa3d_41x37x23_k1", synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 1
+    yield "tpfa2d_301x97_k2", synth.lognormal_tpfa((301, 97), 1.5, np.random.default_rng(7)), 2
+    yield "random_20000_k1", random_sparse(20000, 0.0004, np.random.default_rng(8)), 1
 
 
 CASES = {name: (A, k) for name, A, k in _cases()}
