@@ -40,6 +40,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-iters", type=int, default=30)
     p.add_argument("--spmv-reps", type=int, default=50)
+    p.add_argument("--workload", default="diffusion128",
+                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving"],
+                   help="diffusion128 is the benchmark line; the others print extra records")
+    p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
+    p.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     return p.parse_args()
 
 
@@ -64,6 +69,8 @@ def time_launches(fn, reps, stream):
 
 def main():
     args = parse()
+    if args.workload != "diffusion128":
+        return extra(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -164,7 +171,7 @@ def main():
     # share of the step spent in the triangular solves (2 triangles per Arnoldi step)
     trsv_share = t_trsv_lu * it_per_solve / (ms_per_step / 1e3)
 
-    roof = {"kernel": "k_trsv<double,false> (level-scheduled lower solve)",
+    roof = {"kernel": "k_trsv_blk<double,false,4> (level-scheduled lower solve)",
             "bound": "hbm", "achieved": round(trsv_l_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(trsv_l_gbs / HBM_PEAK_GBS, 5), "traffic": None,
             "note": f"latency-bound: {li['nlev_lower']} dependent levels per triangle; "
@@ -229,6 +236,160 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------- extra records
+
+def extra(args):
+    import torch
+
+    from paper_1606_00545_amd import hec, synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"workload": args.workload, "data": "synthetic"}
+    if args.workload == "poisson64":
+        A, xt = synth.workload_c1()
+        Mh = hec.hec_from_csr(A)
+        F = hec.ilu_factor(A, 0)
+        lv = hec.level_schedule(F)
+        xd = torch.from_numpy(xt).to(dev)
+        b = torch.empty_like(xd)
+        hec.hec_spmv(Mh, xd, b)
+        x = torch.empty_like(b)
+        for name, fn in (("gmres", lambda: hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-8)),
+                         ("bicgstab", lambda: hec.bicgstab_solve(Mh, F, lv, b, x, rtol=1e-8))):
+            fn()
+            lat = []
+            for _ in range(max(args.steps, 20)):
+                t = time.perf_counter()
+                inf = fn()
+                lat.append(time.perf_counter() - t)
+            lat = np.array(lat) * 1e3
+            out[name] = {"iterations": inf["iterations"], "rel_res": inf["rel_res_true"],
+                         "solves_per_s": round(1e3 / lat.mean(), 2), "p50_ms": round(float(np.median(lat)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        out["trsv_lu_us"] = round(time_launches(lambda: hec.trsv_levels(F, lv, b, x, hec.LU), 50, stream) * 1e6, 2)
+        out["n"] = A.n
+    elif args.workload == "powerlaw":
+        t0 = time.time()
+        A, xt = synth.workload_powerlaw()
+        log(f"[bench] power-law n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
+        n, nnz = A.n, A.nnz
+        rows = []
+        for width in (0, 8, 12, 16, 24):
+            Mh = hec.hec_from_csr(A, ell_width=width, keep_f32=True)
+            inf = hec.hec_info(Mh)
+            for prec in ("f64", "f32"):
+                dt = torch.float64 if prec == "f64" else torch.float32
+                xd = torch.from_numpy(xt).to(dev, dt)
+                yd = torch.empty(n, dtype=dt, device=dev)
+                vals = hec.F64 if prec == "f64" else hec.F32
+                t = time_launches(lambda: hec.hec_spmv(Mh, xd, yd, vals=vals), 20, stream)
+                vb = 8 if prec == "f64" else 4
+                alg = (vb + 4) * nnz + 2 * vb * n
+                stored = (vb + 4) * inf["K"] * inf["ld"] + (vb + 4) * inf["nnz_rem"] + 4 * n + 2 * vb * n
+                rows.append({"format": "CSR" if width == 0 else f"HEC K={inf['K']}", "values": prec,
+                             "us": round(t * 1e6, 1), "alg_GBps": round(alg / t / 1e9, 1),
+                             "stored_GBps": round(stored / t / 1e9, 1), "frac_hbm": round(alg / t / 1e9 / HBM_PEAK_GBS, 4),
+                             "ell_fill": round((nnz - inf["nnz_rem"]) / max(1, inf["K"] * n), 3)})
+                log(f"[bench] {rows[-1]}")
+            del Mh
+        out.update({"n": n, "nnz": nnz, "spmv": rows})
+    elif args.workload == "aniso192":
+        t0 = time.time()
+        A, xt = synth.workload_diffusion3d(192, sigma=2.0, seed=4, zscale=0.01)
+        log(f"[bench] aniso 192^3 n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
+        ts = time.time()
+        Mh = hec.hec_from_csr(A, keep_f32=True)
+        F = hec.ilu_factor(A, k=1, keep_f32=True)
+        lv = hec.level_schedule(F)
+        t_setup = time.time() - ts
+        li = hec.levels_info(lv)
+        xd = torch.from_numpy(xt).to(dev)
+        b = torch.empty_like(xd)
+        hec.hec_spmv(Mh, xd, b)
+        res = {}
+        for name, prec in (("fp64", 0), ("mixed", 1)):
+            x = torch.empty_like(b)
+            inf = hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-10, precision=prec, ir_rtol=1e-10,
+                                  maxit=20000, check=False)
+            r = b.clone()
+            hec.hec_spmv(Mh, x, r, -1.0, 1.0)
+            res[name] = {"status": inf["status"], "iterations": inf["iterations"], "ir_steps": inf["ir_steps"],
+                         "seconds": round(inf["seconds"], 4), "rel_res": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
+                         "err_vs_x_true": float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))}
+            log(f"[bench] {name}: {res[name]}")
+        res["mixed_vs_fp64_x"] = None
+        zb = torch.empty_like(b)
+        zf = torch.empty(A.n, dtype=torch.float32, device=dev)
+        bf = b.float()
+        out.update({"n": A.n, "nnz": A.nnz, "nnz_lu": hec.ilu_info(F)["nnz"], "levels": li, "setup_s": round(t_setup, 2),
+                    "solves": res,
+                    "trsv_lu_us_f64": round(time_launches(lambda: hec.trsv_levels(F, lv, b, zb, hec.LU), 10, stream) * 1e6, 1),
+                    "trsv_lu_us_f32": round(time_launches(lambda: hec.trsv_levels(F, lv, bf, zf, hec.LU), 10, stream) * 1e6, 1)})
+    elif args.workload == "serving":
+        out.update(serving(args))
+    print(json.dumps(out), flush=True)
+
+
+def serving(args):
+    """Serving: requests (2D or 3D lognormal diffusion, n log-uniform in [1e3, 1e6],
+    per-request seed) arrive as a Poisson process at 0.7x the measured sequential
+    FP64 throughput; FP64 and mixed precision runs replay the same trace."""
+    import threading
+    import queue
+    from paper_1606_00545_amd import serve, synth
+    import torch
+
+    reqs = synth.serving_requests(args.requests)
+
+    def build(spec, prec):
+        A, xt = synth.request_system(spec)
+        # b = A x_true through scipy on the host (client side, outside the measured latency)
+        b = A.to_scipy() @ xt
+        return serve.Request(spec.rid, A, b, precision=prec, rtol=1e-8)
+
+    # calibration: sequential FP64 service time on the first few requests
+    cal = [build(s, 0) for s in reqs[:12]]
+    srv = serve.Server(slots=1)
+    t = time.perf_counter()
+    srv.run(cal)
+    seq_rate = len(cal) / (time.perf_counter() - t)
+    rate = 0.7 * seq_rate
+    arrivals = synth.poisson_arrivals(len(reqs), rate)
+    out = {"requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 3),
+           "sequential_fp64_solves_per_s": round(seq_rate, 3)}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        q = queue.Queue(maxsize=16)
+
+        def producer():
+            for spec, t_arr in zip(reqs, arrivals):
+                r = build(spec, prec)
+                r.arrival = float(t_arr)
+                q.put(r)
+            q.put(None)
+
+        def source():
+            while True:
+                r = q.get()
+                if r is None:
+                    return
+                yield r
+
+        th = threading.Thread(target=producer, daemon=True)
+        th.start()
+        srv = serve.Server(slots=args.slots)
+        t = time.perf_counter()
+        res = srv.run(source(), t0=t)
+        span = max(r.done for r in res) if res else 0.0
+        st = serve.latency_stats(res)
+        ok = sum(1 for r in res if r.info["status"] == 0 and r.info["rel_res_true"] <= 1e-8)
+        out[name] = {"completed": len(res), "converged": ok, "errors": len(srv.errors),
+                     "solves_per_s": round(len(res) / span, 3) if span else None,
+                     "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                     "peak_inflight": srv.peak_inflight}
+        log(f"[bench] serving {name}: {out[name]}")
+    return out
 
 
 if __name__ == "__main__":

@@ -15,7 +15,10 @@
  *  - Vectors (x, b, y) are caller-owned DEVICE pointers of n elements of the
  *    stated dtype (for example torch tensors' data_ptr()). `stream` is a
  *    hipStream_t (NULL = the default stream).
- *  - Handles own their device memory until the matching *_destroy call.
+ *  - Handles own their device memory until the matching *_destroy call. It is
+ *    allocated and released in stream order (hipMallocAsync/hipFreeAsync) on
+ *    the stream of the call that created it; destroy a handle before that
+ *    stream.
  *  - Every call returns an hec_status; on failure a message for the calling
  *    thread is available from hec_last_error(). No C++ exception crosses the
  *    ABI. Arguments are validated on the host before any device work.
@@ -138,8 +141,9 @@ hec_status ilu_destroy(hec_ilu M);
  * j < i, starting from 0) and, mirrored, of U (j > i, rows from n-1 down),
  * stored 0-based; rows grouped by level in ascending row order (level_ptr +
  * perm). Also builds the level-ordered device copies of L and U used by
- * trsv_levels. The schedule refers to M's pattern and values at call time. */
-hec_status level_schedule(hec_ilu M, hec_levels *out);
+ * trsv_levels (allocated and filled on `stream`, which is synchronised). The
+ * schedule refers to M's pattern and values at call time. */
+hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out);
 
 hec_status levels_info(hec_levels lv, int32_t *n, int32_t *nlev_lower, int32_t *nlev_upper);
 

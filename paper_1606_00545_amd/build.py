@@ -1,7 +1,9 @@
 """Build step for the HIP library (gfx950) and, for the test suite, the CPU oracle.
 
 ``python -m paper_1606_00545_amd.build`` compiles every ``csrc/*.hip`` file into
-``libhec.so`` next to this file with hipcc for gfx950.
+``libhec.so`` next to this file with hipcc for gfx950, and the host-only build
+of the triangular-solve planner (``csrc/plan_cpu.cpp``) into ``libhecplan.so``,
+which lets the test suite check solve plans without a GPU.
 """
 from __future__ import annotations
 
@@ -13,6 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhec.so")
+PLAN_LIB = os.path.join(HERE, "libhecplan.so")
 ARCH = "gfx950"
 
 
@@ -28,13 +31,28 @@ def hipcc_command(out: str = LIB):
              "-o", out] + hip_sources())
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = hipcc_command(tmp)
+def plan_command(out: str = PLAN_LIB):
+    return ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", out,
+            os.path.join(CSRC, "plan_cpu.cpp")]
+
+
+def _run(cmd, out, verbose):
+    tmp = out + ".tmp"
+    cmd = [tmp if c == out else c for c in cmd]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build_plan(verbose: bool = False) -> str:
+    _run(plan_command(), PLAN_LIB, verbose)
+    return PLAN_LIB
+
+
+def build(verbose: bool = False) -> str:
+    _run(hipcc_command(), LIB, verbose)
+    build_plan(verbose)
     return LIB
 
 

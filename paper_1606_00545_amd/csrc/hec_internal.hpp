@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/hec.h"
+#include "plan.hpp"
 
 namespace hec {
 
@@ -56,28 +57,47 @@ hec_status guarded(F &&body) {
 
 // ------------------------------------------------------------------ device memory
 
-// Owning device buffer (hipMalloc/hipFree).
+// The stream on which the calling thread's current entry point allocates
+// (set by StreamScope). Allocation is stream-ordered (hipMallocAsync /
+// hipFreeAsync), so setting up or releasing one system never synchronises the
+// whole device while other systems run on other streams.
+hipStream_t &alloc_stream();
+void ensure_pool();
+
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(alloc_stream()) {
+        ensure_pool();
+        alloc_stream() = s;
+    }
+    ~StreamScope() { alloc_stream() = prev; }
+};
+
+// Owning device buffer, allocated and freed in order on the stream that was
+// current when it was allocated.
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    hipStream_t st = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), st(o.st) { o.p = nullptr; o.n = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; st = o.st; o.p = nullptr; o.n = 0; }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
         n = count;
-        if (count) HEC_HIP(hipMalloc(&p, count * sizeof(T)));
+        st = alloc_stream();
+        if (count) HEC_HIP(hipMallocAsync((void **)&p, count * sizeof(T), st));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, st);
         p = nullptr;
         n = 0;
     }
@@ -158,6 +178,7 @@ struct hec_tri {
     hec::DevBuf<int32_t> part_pos;  // nparts+1: first position of each part
     hec::DevBuf<int32_t> ss_pos;    // nss+1: first position of each sub-segment
     hec::DevBuf<int32_t> grow;      // position -> row
+    std::vector<int32_t> hgrow;     // host copy of grow
     hec::DevBuf<int32_t> other;     // lower only: the row's position in the upper plan
     hec::DevBuf<int32_t> enc;       // K*ldq: -(local position+1) inside the part, row outside, INT_MIN pad
     hec::DevBuf<double> val;
@@ -187,13 +208,6 @@ void spmv_launch(const hec_matrix_s &A, double alpha, const XT *x, double beta, 
 template <class T>
 void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s,
                  const int32_t *skip = nullptr);
-
-// Eq. (11) levels of the strict lower (upper == false) or strict upper triangle
-// of a pattern with known diagonal positions; fills level_ptr and perm (Alg. 3)
-// and, if lev != nullptr, each row's level. Returns the number of levels.
-int32_t compute_levels(int32_t n, const std::vector<int32_t> &LUp, const std::vector<int32_t> &LUj,
-                       const std::vector<int32_t> &diag, bool upper, std::vector<int32_t> &level_ptr,
-                       std::vector<int32_t> &perm, std::vector<int32_t> *lev = nullptr);
 
 // Builds the level schedule and blocked solve plan of one triangle of M (the
 // upper plan must be built first: the lower plan records positions in it).

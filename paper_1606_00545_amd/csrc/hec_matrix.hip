@@ -18,6 +18,25 @@ thread_local std::string g_last_error;
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
+hipStream_t &alloc_stream() {
+    thread_local hipStream_t s = nullptr;
+    return s;
+}
+
+// Keep freed stream-ordered memory in the device pool for reuse instead of
+// returning it to the driver at every synchronisation.
+void ensure_pool() {
+    thread_local int done_dev = -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev == done_dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done_dev = dev;
+}
+
 void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax) {
     if (n < 0) fail(HEC_ERR_INVALID_ARG, "n < 0");
     if (!Ap) fail(HEC_ERR_INVALID_ARG, "Ap is NULL");
@@ -102,7 +121,13 @@ __global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t K, int32_t 
                                                   const XT *__restrict__ x, AT beta,
                                                   const YT *z, YT *y, const int32_t *skip) {
     if (skip && *skip) return;
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+    // L2): give XCD k the k-th contiguous eighth of the rows, so that the x
+    // entries a row gathers from its neighbours (also those nx*ny rows away)
+    // are mostly cached in the same L2. The grid is a multiple of 8.
+    const uint32_t per = gridDim.x >> 3;
+    const uint32_t blk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    int32_t i = blk * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t *c = col + i;
     const VT *v = val + i;
@@ -191,7 +216,8 @@ void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta
     }
     bool first = A.K == 0;
     if (!first) {
-        k_spmv_ell<VT, XT, YT, AT><<<ceil_div(A.n, 256), 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev,
+        const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;  // a multiple of 8 (XCD mapping)
+        k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev,
                                                                      alpha, x, beta, z, y, skip);
         HEC_CHECK_LAUNCH();
     }
@@ -249,6 +275,7 @@ hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const d
         validate_csr(n, Ap, Aj, Ax);
         if (flags & ~HEC_KEEP_F32) fail(HEC_ERR_INVALID_ARG, "unknown flags");
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         auto A = std::make_unique<hec_matrix_s>();
         A->n = n;
         A->nnz = Ap[n];
@@ -330,7 +357,7 @@ hec_status hec_export(hec_matrix A, int32_t *ell_col, double *ell_val, int32_t *
         if (!A) fail(HEC_ERR_INVALID_ARG, "null matrix");
         if ((ell_val32 || rem_val32) && !A->has_f32) fail(HEC_ERR_INVALID_ARG, "matrix has no FP32 copy");
         size_t slab = (size_t)A->K * A->ld;
-        hipStream_t s = nullptr;
+        hipStream_t s = A->ell_col.st;
         if (ell_col) A->ell_col.download(ell_col, slab, s);
         if (ell_val) A->ell_val.download(ell_val, slab, s);
         if (ell_val32) A->ell_val32.download(ell_val32, slab, s);
@@ -353,6 +380,7 @@ hec_status hec_spmv(hec_matrix A, hec_dtype vals, double alpha, const void *x, h
             fail(HEC_ERR_INVALID_ARG, "bad dtype");
         if (!std::isfinite(alpha) || !std::isfinite(beta)) fail(HEC_ERR_INVALID_ARG, "alpha/beta not finite");
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         int key = (vals << 2) | (xt << 1) | yt;
         switch (key) {
 #define CASE(V, X, Y, TV, TX, TY)                                                                       \

@@ -64,77 +64,6 @@ static void symbolic_iluk(int32_t n, const int32_t *Ap, const int32_t *Aj, int32
     }
 }
 
-// Recognises a natural-order 5- or 7-point stencil (cell x + nx*(y + ny*z)):
-// the strictly lower entries of A have offsets i - j in {1, nx, nx*ny} only,
-// with exactly the counts such a grid gives. The result only steers how the
-// triangular solves are partitioned (a performance choice; any answer is correct).
-static void detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t &nx, int32_t &ny, int32_t &nz) {
-    nx = ny = nz = 0;
-    int64_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
-    int nd = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        for (int32_t e = Ap[i]; e < Ap[i + 1] && Aj[e] < i; ++e) {
-            int64_t d = i - Aj[e];
-            int k = 0;
-            while (k < nd && off[k] != d) ++k;
-            if (k == nd) {
-                if (nd == 3) return;
-                off[nd++] = d;
-            }
-            cnt[k]++;
-        }
-    }
-    // sort the (at most 3) offsets
-    for (int a = 0; a < nd; ++a)
-        for (int b = a + 1; b < nd; ++b)
-            if (off[b] < off[a]) { std::swap(off[a], off[b]); std::swap(cnt[a], cnt[b]); }
-    if (nd < 2 || off[0] != 1) return;
-    int64_t X = off[1], Y = nd == 3 ? off[2] / off[1] : (int64_t)n / off[1];
-    if (nd == 3 && off[2] % off[1] != 0) return;
-    int64_t plane = X * Y;
-    if (plane <= 0 || n % plane != 0) return;
-    int64_t Z = n / plane;
-    if (cnt[0] != (X - 1) * Y * Z || cnt[1] != X * (Y - 1) * Z) return;
-    if (nd == 3 && cnt[2] != X * Y * (Z - 1)) return;
-    if (nd == 2 && Z != 1) return;
-    nx = (int32_t)X;
-    ny = (int32_t)Y;
-    nz = (int32_t)Z;
-}
-
-// Eq. (11): level of each row, 0-based, for the strict lower (upper == false)
-// or strict upper triangle, then Alg. 3's grouping: level_ptr and perm with
-// rows ascending inside each level (stable counting sort).
-int32_t compute_levels(int32_t n, const std::vector<int32_t> &LUp, const std::vector<int32_t> &LUj,
-                       const std::vector<int32_t> &diag, bool upper, std::vector<int32_t> &level_ptr,
-                       std::vector<int32_t> &perm, std::vector<int32_t> *lev_out) {
-    std::vector<int32_t> lev(n);
-    int32_t nlev = 0;
-    if (!upper) {
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t l = 0;
-            for (int32_t e = LUp[i]; e < diag[i]; ++e) l = std::max(l, lev[LUj[e]] + 1);
-            lev[i] = l;
-            nlev = std::max(nlev, l + 1);
-        }
-    } else {
-        for (int32_t i = n - 1; i >= 0; --i) {
-            int32_t l = 0;
-            for (int32_t e = diag[i] + 1; e < LUp[i + 1]; ++e) l = std::max(l, lev[LUj[e]] + 1);
-            lev[i] = l;
-            nlev = std::max(nlev, l + 1);
-        }
-    }
-    level_ptr.assign(nlev + 1, 0);
-    for (int32_t i = 0; i < n; ++i) level_ptr[lev[i] + 1]++;
-    for (int32_t l = 0; l < nlev; ++l) level_ptr[l + 1] += level_ptr[l];
-    std::vector<int32_t> next(level_ptr.begin(), level_ptr.end() - 1);
-    perm.resize(n);
-    for (int32_t i = 0; i < n; ++i) perm[next[lev[i]]++] = i;
-    if (lev_out) lev_out->swap(lev);
-    return nlev;
-}
-
 // ------------------------------------------------------------------ numeric ILU kernel
 
 // Rows of one level of L, one thread per row (Alg. 2 restricted to S_k):
@@ -202,12 +131,13 @@ hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const dou
             if (!d) fail(HEC_ERR_INVALID_ARG, "row " + std::to_string(i) + " has no stored diagonal");
         }
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         auto M = std::make_unique<hec_ilu_s>();
         M->n = n;
         M->k = k;
         M->has_f32 = (flags & HEC_KEEP_F32) != 0;
         symbolic_iluk(n, Ap, Aj, k, M->hLUp, M->hLUj, M->hdiag);
-        detect_grid(n, Ap, Aj, M->gnx, M->gny, M->gnz);
+        plan::detect_grid(n, Ap, Aj, M->gnx, M->gny, M->gnz);
         M->nnz = M->hLUp[n];
         // A's values scattered into S_k, fill entries start at 0
         std::vector<double> x0(M->nnz, 0.0);
@@ -228,7 +158,7 @@ hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const dou
         M->LUx.upload(x0.data(), M->nnz, s);
         // numeric elimination, one launch per level of L
         std::vector<int32_t> lptr, perm;
-        int32_t nlev = compute_levels(n, M->hLUp, M->hLUj, M->hdiag, false, lptr, perm);
+        int32_t nlev = plan::compute_levels(n, M->hLUp.data(), M->hLUj.data(), M->hdiag.data(), false, lptr, perm);
         DevBuf<int32_t> dperm(n), dflag(1);
         dperm.upload(perm.data(), n, s);
         HEC_HIP(hipMemsetAsync(dflag.get(), 0, sizeof(int32_t), s));
@@ -277,8 +207,8 @@ hec_status ilu_export(hec_ilu M, int32_t *LUp, int32_t *LUj, double *LUx) {
         if (LUp) std::copy(M->hLUp.begin(), M->hLUp.end(), LUp);
         if (LUj) std::copy(M->hLUj.begin(), M->hLUj.end(), LUj);
         if (LUx) {
-            M->LUx.download(LUx, M->nnz, nullptr);
-            HEC_HIP(hipStreamSynchronize(nullptr));
+            M->LUx.download(LUx, M->nnz, M->LUx.st);
+            HEC_HIP(hipStreamSynchronize(M->LUx.st));
         }
     });
 }
@@ -288,12 +218,13 @@ hec_status ilu_destroy(hec_ilu M) {
     return HEC_OK;
 }
 
-hec_status level_schedule(hec_ilu M, hec_levels *out) {
+hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
     return guarded([&] {
         if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
         if (!M) fail(HEC_ERR_INVALID_ARG, "null factor");
-        hipStream_t s = nullptr;
+        hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         auto lv = std::make_unique<hec_levels_s>();
         lv->n = M->n;
         build_tri(*M, true, lv->upper, nullptr, s);
@@ -347,6 +278,7 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
         if (lv->n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
         if (b == x && lv->n > 0) fail(HEC_ERR_INVALID_ARG, "b and x must not overlap");
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         if (prec == HEC_F64) {
             trsv_launch<double>(*lv, which, (const double *)b, (double *)x, s);
         } else if (prec == HEC_F32) {

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "hec_internal.hpp"
@@ -511,6 +512,30 @@ struct OpBiXR : NoInit {
 
 // ---------------------------------------------------------------- workspace
 
+// Mapped pinned flag blocks are recycled: freeing pinned host memory can
+// synchronise the whole device, which would stall other streams' solves.
+static std::mutex g_flag_mu;
+static std::vector<int32_t *> g_flag_pool;
+
+static int32_t *take_flags() {
+    {
+        std::lock_guard<std::mutex> lk(g_flag_mu);
+        if (!g_flag_pool.empty()) {
+            int32_t *p = g_flag_pool.back();
+            g_flag_pool.pop_back();
+            return p;
+        }
+    }
+    int32_t *p = nullptr;
+    HEC_HIP(hipHostMalloc((void **)&p, SI_COUNT * sizeof(int32_t), hipHostMallocMapped));
+    return p;
+}
+
+static void give_flags(int32_t *p) {
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    g_flag_pool.push_back(p);
+}
+
 struct KrylovWS {
     int64_t n = 0, ldv = 0;
     int m = 0;
@@ -529,7 +554,7 @@ struct KrylovWS {
     std::vector<hipEvent_t> ev;
     ~KrylovWS() {
         for (auto e : ev) (void)hipEventDestroy(e);
-        if (hflags) (void)hipHostFree(hflags);
+        if (hflags) give_flags(hflags);
     }
 };
 
@@ -570,7 +595,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     nw->counter.alloc(1);
     HEC_HIP(hipMemsetAsync(nw->counter.get(), 0, sizeof(uint32_t), s));
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
-    HEC_HIP(hipHostMalloc((void **)&nw->hflags, SI_COUNT * sizeof(int32_t), hipHostMallocMapped));
+    nw->hflags = take_flags();
     std::memset(nw->hflags, 0, SI_COUNT * sizeof(int32_t));
     HEC_HIP(hipHostGetDevicePointer((void **)&nw->dflags, nw->hflags, 0));
     nw->ev.resize(kMaxRestart + 2);
@@ -705,6 +730,7 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
         if (mixed && (!A->has_f32 || !M->has_f32))
             fail(HEC_ERR_INVALID_ARG, "mixed precision needs HEC_KEEP_F32 on the matrix and the factor");
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         const int64_t n = A->n;
         inf.status = HEC_OK;
         if (n == 0) return;
@@ -761,6 +787,7 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
         check_solve_args(A, M, lv, b, x, o);
         if (o->precision != 0) fail(HEC_ERR_INVALID_ARG, "BiCGSTAB runs in FP64 only");
         hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
         const int64_t n = A->n;
         if (n == 0) return;
         KrylovWS &ws = get_ws(*A, 0, false, true, s);

@@ -1,0 +1,316 @@
+// Host-side planning of the level-scheduled triangular solves (Sec. 2.6,
+// Eq. (11), Alg. 3): levels, grid recognition, and the blocked execution plan.
+// Pure C++ (no HIP): the GPU library builds its plans with it, and a CPU-only
+// checker library built from the same header lets the plan be verified without
+// a GPU.
+#pragma once
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#if defined(__HIPCC__)
+#define HEC_HD __host__ __device__
+#else
+#define HEC_HD
+#endif
+
+namespace hec {
+namespace plan {
+
+constexpr int kSub = 64;          // rows per sub-segment (one solver wavefront)
+constexpr int kPad = INT_MIN;     // padding entry of a row shorter than K
+// Partitioning parameters (overridable at compile time for tuning sweeps).
+#ifndef HEC_TRSV_TARGET_PARTS
+#define HEC_TRSV_TARGET_PARTS 64
+#endif
+#ifndef HEC_TRSV_MIN_PART_ROWS
+#define HEC_TRSV_MIN_PART_ROWS 4096
+#endif
+#ifndef HEC_TRSV_TILE_PARTS
+#define HEC_TRSV_TILE_PARTS 256
+#endif
+#ifndef HEC_TRSV_MAX_RING
+#define HEC_TRSV_MAX_RING 32
+#endif
+constexpr int kTargetParts = HEC_TRSV_TARGET_PARTS;  // contiguous parts: about this many ...
+constexpr int kMinPartRows = HEC_TRSV_MIN_PART_ROWS;  // ... of at least this many rows
+constexpr int kTileParts = HEC_TRSV_TILE_PARTS;      // grid tiles: about one per compute unit
+constexpr int kMaxRing = HEC_TRSV_MAX_RING;          // most LDS slots in the ring
+
+HEC_HD constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
+// Byte offsets inside one LDS slot (64 rows of one sub-segment, KC entries per
+// row: the row's entries padded to a compile-time width).
+template <class T, bool UPPER>
+struct Slot {
+    int KC;
+    HEC_HD size_t b() const { return 0; }                                       // T[64]
+    HEC_HD size_t xe() const { return b() + kSub * sizeof(T); }                 // T[KC][64]
+    HEC_HD size_t v() const { return xe() + (size_t)KC * kSub * sizeof(T); }    // T[KC][64]
+    HEC_HD size_t d() const { return v() + (size_t)KC * kSub * sizeof(T); }     // T[64] (U)
+    HEC_HD size_t gi() const { return d() + (UPPER ? kSub * sizeof(T) : 0); }   // int[64]
+    HEC_HD size_t po() const { return gi() + kSub * sizeof(int); }              // int[64]
+    HEC_HD size_t a() const { return po() + kSub * sizeof(int); }               // int[KC][64]
+    HEC_HD size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
+};
+
+// LDS: [filled[D] | consumed | part | zero (16 B)] [part's sub-segment starts,
+//      S+1] [ring of recent results, W] [D slots]
+HEC_HD inline size_t ctrl_head(int D) { return align16((size_t)(D + 2) * sizeof(int)) + 16; }
+HEC_HD inline size_t ctrl_bytes(int D, int S) { return ctrl_head(D) + align16((size_t)(S + 1) * sizeof(int)); }
+
+template <class T, bool UPPER>
+size_t lds_bytes(int KC, int W, int D, int S) {
+    return ctrl_bytes(D, S) + align16((size_t)W * sizeof(T)) + (size_t)D * Slot<T, UPPER>{KC}.bytes();
+}
+
+// Eq. (11): level of each row, 0-based, for the strict lower (upper == false)
+// or strict upper triangle of a pattern with known diagonal positions, then
+// Alg. 3's grouping: level_ptr and perm with rows ascending inside each level
+// (stable counting sort). Returns the number of levels.
+inline int32_t compute_levels(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, bool upper,
+                              std::vector<int32_t> &level_ptr, std::vector<int32_t> &perm,
+                              std::vector<int32_t> *lev_out = nullptr) {
+    std::vector<int32_t> lev(n);
+    int32_t nlev = 0;
+    if (!upper) {
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t l = 0;
+            for (int32_t e = LUp[i]; e < diag[i]; ++e) l = std::max(l, lev[LUj[e]] + 1);
+            lev[i] = l;
+            nlev = std::max(nlev, l + 1);
+        }
+    } else {
+        for (int32_t i = n - 1; i >= 0; --i) {
+            int32_t l = 0;
+            for (int32_t e = diag[i] + 1; e < LUp[i + 1]; ++e) l = std::max(l, lev[LUj[e]] + 1);
+            lev[i] = l;
+            nlev = std::max(nlev, l + 1);
+        }
+    }
+    level_ptr.assign(nlev + 1, 0);
+    for (int32_t i = 0; i < n; ++i) level_ptr[lev[i] + 1]++;
+    for (int32_t l = 0; l < nlev; ++l) level_ptr[l + 1] += level_ptr[l];
+    std::vector<int32_t> next(level_ptr.begin(), level_ptr.end() - 1);
+    perm.resize(n);
+    for (int32_t i = 0; i < n; ++i) perm[next[lev[i]]++] = i;
+    if (lev_out) lev_out->swap(lev);
+    return nlev;
+}
+
+// Recognises a natural-order 5- or 7-point stencil (cell x + nx*(y + ny*z)):
+// the strictly lower entries of A have offsets i - j in {1, nx, nx*ny} only,
+// with exactly the counts such a grid gives. The answer only steers how the
+// triangular solves are partitioned (a performance choice; any answer is correct).
+inline void detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t &nx, int32_t &ny, int32_t &nz) {
+    nx = ny = nz = 0;
+    int64_t off[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+    int nd = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = Ap[i]; e < Ap[i + 1] && Aj[e] < i; ++e) {
+            int64_t d = (int64_t)i - Aj[e];
+            int k = 0;
+            while (k < nd && off[k] != d) ++k;
+            if (k == nd) {
+                if (nd == 3) return;
+                off[nd++] = d;
+            }
+            cnt[k]++;
+        }
+    }
+    for (int a = 0; a < nd; ++a)
+        for (int b = a + 1; b < nd; ++b)
+            if (off[b] < off[a]) {
+                std::swap(off[a], off[b]);
+                std::swap(cnt[a], cnt[b]);
+            }
+    if (nd < 2 || off[0] != 1) return;
+    if (nd == 3 && off[2] % off[1] != 0) return;
+    int64_t X = off[1], Y = nd == 3 ? off[2] / off[1] : (int64_t)n / off[1];
+    int64_t plane = X * Y;
+    if (plane <= 0 || n % plane != 0) return;
+    int64_t Z = n / plane;
+    if (cnt[0] != (X - 1) * Y * Z || cnt[1] != X * (Y - 1) * Z) return;
+    if (nd == 3 && cnt[2] != X * Y * (Z - 1)) return;
+    if (nd == 2 && Z != 1) return;
+    nx = (int32_t)X;
+    ny = (int32_t)Y;
+    nz = (int32_t)Z;
+}
+
+// The blocked execution plan of one triangle.
+//  * Parts: with a recognised grid, x-y tiles spanning all z (about kTileParts
+//    of them) numbered in the order the triangle is solved, kept only if every
+//    dependency then lies in the same or an earlier part; otherwise contiguous
+//    row ranges in that order. Parts are claimed in order at run time.
+//  * Positions: each part's rows at consecutive positions, by (level, row).
+//  * Sub-segments: runs of one level inside a part, at most kSub rows.
+//  * enc[s*ldq + q]: the dependency of entry s of position q: -(local position
+//    + 1) inside the part, the row itself outside it, kPad for padding.
+//  * W: size of the ring of recent results (a power of two that spans the
+//    longest distance from a row to an in-part dependency, plus kSub).
+//  * D64/D32: LDS ring depth for the FP64/FP32 solves; 0 when the plan does not
+//    fit in LDS (more than 32 entries per row): then blocked == false and the
+//    solve polls every dependency (level-order positions in 64-row chunks).
+struct HostPlan {
+    int32_t n = 0, nlev = 0, K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 64, S = 0, D64 = 0, D32 = 0;
+    bool blocked = false;
+    size_t lds64 = 0, lds32 = 0;
+    std::vector<int32_t> level_ptr, perm, lev;
+    std::vector<int32_t> part_ss, part_pos, ss_pos, grow, part_of, pos, chunks;
+    std::vector<int32_t> enc, src, psrc;  // src/psrc: index into the factor's value array
+};
+
+inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
+                      int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P) {
+    P = HostPlan();
+    P.n = n;
+    P.nlev = compute_levels(n, LUp, LUj, diag, upper, P.level_ptr, P.perm, &P.lev);
+    int32_t K = 0;
+    for (int32_t i = 0; i < n; ++i) K = std::max(K, upper ? LUp[i + 1] - diag[i] - 1 : diag[i] - LUp[i]);
+    P.K = K;
+    P.KC = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32;
+    P.ldq = (int32_t)(((int64_t)n + 63) / 64 * 64);
+    if (n == 0) return;
+    auto deps = [&](int32_t i, int32_t &a, int32_t &b) {
+        a = upper ? diag[i] + 1 : LUp[i];
+        b = upper ? LUp[i + 1] : diag[i];
+    };
+
+    int64_t R = std::max<int64_t>(kMinPartRows, (n + kTargetParts - 1) / kTargetParts);
+    R = std::min<int64_t>(R, n);
+    std::vector<int32_t> &part_of = P.part_of, &pos = P.pos, &grow = P.grow;
+    part_of.assign(n, 0);
+    pos.assign(n, 0);
+    grow.assign(n, 0);
+    bool tiled = false;
+    int32_t ntiles = 0;
+    if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
+        const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
+        const int64_t plane = (int64_t)gnx * gny;
+        int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
+        const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
+        const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
+        ntiles = PX * PY;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t xx = i % gnx, yy = (i / gnx) % gny;
+            int32_t t = xx / tx + PX * (yy / ty);
+            part_of[i] = upper ? ntiles - 1 - t : t;
+        }
+        tiled = ntiles > 1;
+        for (int32_t i = 0; i < n && tiled; ++i) {
+            int32_t a, b;
+            deps(i, a, b);
+            for (int32_t e = a; e < b; ++e)
+                if (part_of[LUj[e]] > part_of[i]) {
+                    tiled = false;
+                    break;
+                }
+        }
+    }
+    for (;;) {
+        int32_t nparts;
+        if (tiled) {
+            nparts = ntiles;
+        } else {
+            nparts = (int32_t)((n + R - 1) / R);
+            for (int32_t i = 0; i < n; ++i) part_of[i] = (int32_t)((upper ? (int64_t)(n - 1 - i) : (int64_t)i) / R);
+        }
+        P.part_pos.assign(nparts + 1, 0);
+        for (int32_t i = 0; i < n; ++i) P.part_pos[part_of[i] + 1]++;
+        for (int32_t p = 0; p < nparts; ++p) P.part_pos[p + 1] += P.part_pos[p];
+        std::vector<int32_t> fillp(P.part_pos.begin(), P.part_pos.end() - 1);
+        for (int32_t t = 0; t < n; ++t) {
+            int32_t i = P.perm[t];
+            int32_t q = fillp[part_of[i]]++;
+            pos[i] = q;
+            grow[q] = i;
+        }
+        P.part_ss.assign(nparts + 1, 0);
+        P.ss_pos.clear();
+        for (int32_t p = 0; p < nparts; ++p) {
+            P.part_ss[p] = (int32_t)P.ss_pos.size();
+            int32_t q = P.part_pos[p];
+            while (q < P.part_pos[p + 1]) {
+                P.ss_pos.push_back(q);
+                int32_t l = P.lev[grow[q]];
+                int32_t e = q + 1;
+                while (e < P.part_pos[p + 1] && e - q < kSub && P.lev[grow[e]] == l) ++e;
+                q = e;
+            }
+        }
+        P.part_ss[nparts] = (int32_t)P.ss_pos.size();
+        P.ss_pos.push_back(n);
+        int64_t maxd = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t a, b;
+            deps(i, a, b);
+            for (int32_t e = a; e < b; ++e) {
+                int32_t j = LUj[e];
+                if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, (int64_t)pos[i] - pos[j]);
+            }
+        }
+        P.W = 64;
+        while (P.W < maxd + kSub) P.W *= 2;
+        P.S = 0;
+        for (int32_t p = 0; p < nparts; ++p) P.S = std::max(P.S, P.part_ss[p + 1] - P.part_ss[p]);
+        auto fit = [&](auto tag) {
+            using T = decltype(tag);
+            int best = 0;
+            for (int D = 4; D <= kMaxRing; ++D) {
+                size_t bb = upper ? lds_bytes<T, true>(P.KC, P.W, D, P.S) : lds_bytes<T, false>(P.KC, P.W, D, P.S);
+                if ((int64_t)bb <= lds_max) best = D;
+            }
+            return best;
+        };
+        P.D64 = fit(double());
+        P.D32 = has_f32 ? fit(float()) : 4;
+        P.nparts = nparts;
+        if ((P.D64 >= 4 && P.D32 >= 4) || R <= kSub || K > 32) break;
+        tiled = false;                       // fall back to (smaller) contiguous parts
+        R = std::max<int64_t>(kSub, R / 2);  // a smaller part keeps the ring of results smaller
+    }
+    P.blocked = P.D64 >= 4 && P.D32 >= 4 && K <= 32;
+    if (!P.blocked) {
+        for (int32_t t = 0; t < n; ++t) {
+            grow[t] = P.perm[t];
+            pos[P.perm[t]] = t;
+            part_of[P.perm[t]] = t;
+        }
+        P.part_pos.assign(2, 0);
+        P.part_pos[1] = n;
+        P.chunks.assign(1, 0);
+        for (int32_t l = 0; l < P.nlev; ++l)
+            for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; q += kSub)
+                P.chunks.push_back(std::min(q + kSub, P.level_ptr[l + 1]));
+        P.part_ss.assign(2, 0);
+        P.ss_pos.assign(1, 0);
+        P.nparts = 0;
+    }
+    P.nss = (int32_t)P.ss_pos.size() - 1;
+    P.lds64 = upper ? lds_bytes<double, true>(P.KC, P.W, P.D64, P.S) : lds_bytes<double, false>(P.KC, P.W, P.D64, P.S);
+    P.lds32 = upper ? lds_bytes<float, true>(P.KC, P.W, P.D32, P.S) : lds_bytes<float, false>(P.KC, P.W, P.D32, P.S);
+    const size_t slab = (size_t)K * P.ldq;
+    P.enc.assign(slab, kPad);
+    P.src.assign(slab, -1);
+    if (upper) P.psrc.assign(P.ldq, -1);
+    for (int32_t q = 0; q < n; ++q) {
+        int32_t i = grow[q];
+        int32_t a, b;
+        deps(i, a, b);
+        int32_t pstart = P.blocked ? P.part_pos[part_of[i]] : 0;
+        for (int32_t e = a, s2 = 0; e < b; ++e, ++s2) {
+            int32_t j = LUj[e];
+            P.enc[(size_t)s2 * P.ldq + q] = P.blocked && part_of[j] == part_of[i] ? -(pos[j] - pstart + 1) : j;
+            P.src[(size_t)s2 * P.ldq + q] = e;
+        }
+        if (upper) P.psrc[q] = diag[i];
+    }
+}
+
+}  // namespace plan
+}  // namespace hec

@@ -1,0 +1,73 @@
+// CPU build of the triangular-solve planner (plan.hpp) with a small C ABI, so
+// that a plan can be built and inspected without a GPU: the test suite replays
+// it on the host (ordering, ring and LDS limits, deadlock freedom) against the
+// reference triangular solves. Built with the host compiler into libhecplan.so.
+#include <cstring>
+#include <new>
+
+#include "plan.hpp"
+
+using hec::plan::HostPlan;
+
+extern "C" {
+
+// Builds the plan of the strict lower (upper == 0) or strict upper triangle of
+// the factor pattern (LUp, LUj, diag: row pointers, columns, diagonal
+// positions; 0-based) with the grid sizes detected from A (all 0: none) and
+// lds_max bytes of LDS per workgroup. Returns NULL on allocation failure.
+void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
+                   int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max) {
+    HostPlan *P = new (std::nothrow) HostPlan();
+    if (!P) return nullptr;
+    try {
+        hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P);
+    } catch (...) {
+        delete P;
+        return nullptr;
+    }
+    return P;
+}
+
+// meta[0..15] = n, nlev, K, KC, ldq, nparts, nss, W, S, D64, D32, blocked,
+// lds64, lds32, kSub, kPad.
+void hecplan_meta(const void *h, int64_t *meta) {
+    const HostPlan &P = *(const HostPlan *)h;
+    const int64_t m[16] = {P.n, P.nlev, P.K, P.KC, P.ldq, P.nparts, P.nss, P.W, P.S, P.D64, P.D32,
+                           P.blocked ? 1 : 0, (int64_t)P.lds64, (int64_t)P.lds32, hec::plan::kSub,
+                           hec::plan::kPad};
+    std::memcpy(meta, m, sizeof(m));
+}
+
+// Copies the named array (level_ptr, perm, lev, part_ss, part_pos, ss_pos,
+// grow, part_of, pos, chunks, enc, src, psrc) into dst when dst != NULL.
+// Returns its length, or -1 for an unknown name.
+int64_t hecplan_array(const void *h, const char *name, int32_t *dst) {
+    const HostPlan &P = *(const HostPlan *)h;
+    const std::vector<int32_t> *v = nullptr;
+    if (!std::strcmp(name, "level_ptr")) v = &P.level_ptr;
+    else if (!std::strcmp(name, "perm")) v = &P.perm;
+    else if (!std::strcmp(name, "lev")) v = &P.lev;
+    else if (!std::strcmp(name, "part_ss")) v = &P.part_ss;
+    else if (!std::strcmp(name, "part_pos")) v = &P.part_pos;
+    else if (!std::strcmp(name, "ss_pos")) v = &P.ss_pos;
+    else if (!std::strcmp(name, "grow")) v = &P.grow;
+    else if (!std::strcmp(name, "part_of")) v = &P.part_of;
+    else if (!std::strcmp(name, "pos")) v = &P.pos;
+    else if (!std::strcmp(name, "chunks")) v = &P.chunks;
+    else if (!std::strcmp(name, "enc")) v = &P.enc;
+    else if (!std::strcmp(name, "src")) v = &P.src;
+    else if (!std::strcmp(name, "psrc")) v = &P.psrc;
+    if (!v) return -1;
+    if (dst && !v->empty()) std::memcpy(dst, v->data(), v->size() * sizeof(int32_t));
+    return (int64_t)v->size();
+}
+
+void hecplan_free(void *h) { delete (HostPlan *)h; }
+
+// Grid recognition used to choose tiled parts: out = {nx, ny, nz}, all 0 when
+// the pattern is not a natural-order 5/7-point stencil.
+void hecplan_detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t *out) {
+    hec::plan::detect_grid(n, Ap, Aj, out[0], out[1], out[2]);
+}
+
+}  // extern "C"

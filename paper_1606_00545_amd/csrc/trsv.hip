@@ -40,22 +40,14 @@ namespace {
 
 constexpr int kPrefetchWaves = 15;
 constexpr int kBlkThreads = 64 * (1 + kPrefetchWaves);
-constexpr int kSub = 64;            // rows per sub-segment (one solver wavefront)
-constexpr int kPad = INT_MIN;       // padding entry of a row shorter than K
 constexpr int kBatch = 8;           // entries loaded per batch by a prefetcher lane
-
-#ifndef HEC_TRSV_TARGET_PARTS
-#define HEC_TRSV_TARGET_PARTS 64
-#endif
-#ifndef HEC_TRSV_MIN_PART_ROWS
-#define HEC_TRSV_MIN_PART_ROWS 4096
-#endif
-#ifndef HEC_TRSV_TILE_PARTS
-#define HEC_TRSV_TILE_PARTS 256
-#endif
-#ifndef HEC_TRSV_MAX_RING
-#define HEC_TRSV_MAX_RING 32
-#endif
+using plan::kPad;
+using plan::kSub;
+using plan::align16;
+using plan::ctrl_bytes;
+using plan::ctrl_head;
+using plan::lds_bytes;
+using plan::Slot;
 
 template <class T> struct Sentinel;
 template <> struct Sentinel<double> {
@@ -92,35 +84,6 @@ __device__ __forceinline__ T from_bits(typename Sentinel<T>::U u) {
     T v;
     __builtin_memcpy(&v, &u, sizeof(T));
     return v;
-}
-
-__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
-
-// Byte offsets inside one LDS slot (64 rows of one sub-segment, KC entries per
-// row: the row's entries padded to a compile-time width).
-template <class T, bool UPPER>
-struct Slot {
-    int KC;
-    __host__ __device__ size_t b() const { return 0; }                                    // T[64]
-    __host__ __device__ size_t xe() const { return b() + kSub * sizeof(T); }              // T[KC][64]
-    __host__ __device__ size_t v() const { return xe() + (size_t)KC * kSub * sizeof(T); }  // T[KC][64]
-    __host__ __device__ size_t d() const { return v() + (size_t)KC * kSub * sizeof(T); }   // T[64] (U)
-    __host__ __device__ size_t gi() const { return d() + (UPPER ? kSub * sizeof(T) : 0); }  // int[64]
-    __host__ __device__ size_t po() const { return gi() + kSub * sizeof(int); }           // int[64]
-    __host__ __device__ size_t a() const { return po() + kSub * sizeof(int); }            // int[KC][64]
-    __host__ __device__ size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
-};
-
-// LDS: [filled[D] | consumed | part | zero (16 B)] [part's sub-segment
-//      starts, S+1] [ring of recent results, W] [D slots]
-__host__ __device__ inline size_t ctrl_head(int D) { return align16((size_t)(D + 2) * sizeof(int)) + 16; }
-__host__ __device__ inline size_t ctrl_bytes(int D, int S) {
-    return ctrl_head(D) + align16((size_t)(S + 1) * sizeof(int));
-}
-
-template <class T, bool UPPER>
-size_t lds_bytes(int KC, int W, int D, int S) {
-    return ctrl_bytes(D, S) + align16((size_t)W * sizeof(T)) + (size_t)D * Slot<T, UPPER>{KC}.bytes();
 }
 
 struct PlanArgs {
@@ -176,9 +139,27 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
             // ---------------- solver: two LDS round trips and KC fused multiply-adds per row
             __builtin_amdgcn_s_setprio(3);
             int slot = 0;
+            int ready = 0;  // sub-segments [rel, ready) are known to be filled
             for (int rel = 0; rel < nss; ++rel) {
-                while (__hip_atomic_load(&filled[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != rel)
-                    __builtin_amdgcn_s_sleep(1);
+                if (rel >= ready) {
+                    // look at up to 8 slots in one LDS round trip; wait for the first
+                    for (;;) {
+                        int ok = 0;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int r2 = rel + u;
+                            int sl2 = slot + u;
+                            sl2 = sl2 >= D ? sl2 - D : sl2;
+                            const int f = __hip_atomic_load(&filled[sl2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            ok += (ok == u && u < D && r2 < nss && f == r2) ? 1 : 0;
+                        }
+                        if (ok > 0) {
+                            ready = rel + ok;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
                 const int q0 = sspos[rel], cnt = sspos[rel + 1] - q0;  // rows and first position
                 const char *sl = smem + slots_off + slot * sb;
                 T acc = ((const T *)(sl + L.b()))[lane];
@@ -204,8 +185,12 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     store_coherent(x + gi, acc);
                     if (yother) yother[po] = acc;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                if (lane == 0) __hip_atomic_store(consumed, rel + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // release consumed slots to the prefetchers every 4 sub-segments (and at the end)
+                if ((rel & 3) == 3 || rel + 1 == nss) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    if (lane == 0)
+                        __hip_atomic_store(consumed, rel + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
                 slot = slot + 1 == D ? 0 : slot + 1;
             }
             __builtin_amdgcn_s_setprio(0);
@@ -482,185 +467,55 @@ template void trsv_launch<float>(const hec_levels_s &, uint32_t, const float *, 
 
 void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *upper_plan, hipStream_t s) {
     const int32_t n = M.n;
-    std::vector<int32_t> lev;
-    tri.nlev = compute_levels(n, M.hLUp, M.hLUj, M.hdiag, upper, tri.hlevel_ptr, tri.hperm, &lev);
-    int32_t K = 0;
-    for (int32_t i = 0; i < n; ++i)
-        K = std::max(K, upper ? M.hLUp[i + 1] - M.hdiag[i] - 1 : M.hdiag[i] - M.hLUp[i]);
-    tri.K = K;
-    tri.KC = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32;
-    tri.ldq = (int32_t)(((int64_t)n + 63) / 64 * 64);
+    plan::HostPlan P;
+    plan::make_plan(n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, M.has_f32,
+                    max_lds_per_block() - 256, P);
+    tri.nlev = P.nlev;
+    tri.hlevel_ptr = std::move(P.level_ptr);
+    tri.hperm = std::move(P.perm);
+    tri.K = P.K;
+    tri.KC = P.KC;
+    tri.ldq = P.ldq;
     if (n == 0) return;
-    const int lds_max = max_lds_per_block() - 256;
-
-    // Parts. With a recognised grid (natural-order 5/7-point stencil, see
-    // detect_grid) the rows are cut into x-y tiles spanning all z, numbered in
-    // the order the triangle is solved, when that keeps every dependency in the
-    // same or an earlier part; otherwise into contiguous row ranges.
-    int64_t R = std::max<int64_t>(HEC_TRSV_MIN_PART_ROWS, (n + HEC_TRSV_TARGET_PARTS - 1) / HEC_TRSV_TARGET_PARTS);
-    R = std::min<int64_t>(R, n);
-    std::vector<int32_t> part_of(n), pos(n), grow(n), part_pos, part_ss, ss_pos;
-    bool tiled = false;
-    int32_t ntiles = 0;
-    if (M.gnx > 0 && (int64_t)M.gnx * M.gny * M.gnz == n && n >= 2 * HEC_TRSV_MIN_PART_ROWS) {
-        const int64_t target = std::min<int64_t>(HEC_TRSV_TILE_PARTS, n / HEC_TRSV_MIN_PART_ROWS);
-        const int64_t plane = (int64_t)M.gnx * M.gny;
-        int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
-        const int32_t tx = (int32_t)std::min<int64_t>(T, M.gnx), ty = (int32_t)std::min<int64_t>(T, M.gny);
-        const int32_t PX = (M.gnx + tx - 1) / tx, PY = (M.gny + ty - 1) / ty;
-        ntiles = PX * PY;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t xx = i % M.gnx, yy = (i / M.gnx) % M.gny;
-            int32_t t = xx / tx + PX * (yy / ty);
-            part_of[i] = upper ? ntiles - 1 - t : t;
-        }
-        tiled = ntiles > 1;
-        for (int32_t i = 0; i < n && tiled; ++i) {  // every dependency in the same or an earlier part
-            int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
-            int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
-            for (int32_t e = a; e < b; ++e)
-                if (part_of[M.hLUj[e]] > part_of[i]) { tiled = false; break; }
-        }
+    tri.blocked = P.blocked;
+    tri.nparts = P.nparts;
+    tri.nss = P.nss;
+    tri.W = P.W;
+    tri.S = P.S;
+    tri.D64 = P.D64;
+    tri.D32 = P.D32;
+    tri.lds64 = P.lds64;
+    tri.lds32 = P.lds32;
+    if (!P.blocked) {
+        tri.nchunks = (int32_t)P.chunks.size() - 1;
+        tri.chunk_ptr.alloc(P.chunks.size());
+        tri.chunk_ptr.upload(P.chunks.data(), P.chunks.size(), s);
     }
-    int32_t W = 64, S = 0;
-    int D64 = 0, D32 = 0;
-    for (;;) {
-        int32_t nparts;
-        if (tiled) {
-            nparts = ntiles;
-        } else {
-            nparts = (int32_t)((n + R - 1) / R);
-            for (int32_t i = 0; i < n; ++i) part_of[i] = (int32_t)((upper ? (int64_t)(n - 1 - i) : (int64_t)i) / R);
-        }
-        part_pos.assign(nparts + 1, 0);
-        for (int32_t i = 0; i < n; ++i) part_pos[part_of[i] + 1]++;
-        for (int32_t p = 0; p < nparts; ++p) part_pos[p + 1] += part_pos[p];
-        // positions: each part's rows in (level, row) order, i.e. the global schedule restricted to the part
-        std::vector<int32_t> fillp(part_pos.begin(), part_pos.end() - 1);
-        for (int32_t t = 0; t < n; ++t) {
-            int32_t i = tri.hperm[t];
-            int32_t q = fillp[part_of[i]]++;
-            pos[i] = q;
-            grow[q] = i;
-        }
-        // sub-segments: runs of one level inside a part, at most 64 rows
-        part_ss.assign(nparts + 1, 0);
-        ss_pos.clear();
-        for (int32_t p = 0; p < nparts; ++p) {
-            part_ss[p] = (int32_t)ss_pos.size();
-            int32_t q = part_pos[p];
-            while (q < part_pos[p + 1]) {
-                ss_pos.push_back(q);
-                int32_t l = lev[grow[q]];
-                int32_t e = q + 1;
-                while (e < part_pos[p + 1] && e - q < kSub && lev[grow[e]] == l) ++e;
-                q = e;
-            }
-        }
-        part_ss[nparts] = (int32_t)ss_pos.size();
-        ss_pos.push_back(n);
-        // ring of recent results: must span the longest distance to an in-part dependency
-        int64_t maxd = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
-            int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
-            for (int32_t e = a; e < b; ++e) {
-                int32_t j = M.hLUj[e];
-                if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, pos[i] - pos[j]);
-            }
-        }
-        W = 64;
-        while (W < maxd + kSub) W *= 2;
-        S = 0;
-        for (int32_t p = 0; p < nparts; ++p) S = std::max(S, part_ss[p + 1] - part_ss[p]);
-        auto fit = [&](auto tag) {
-            using T = decltype(tag);
-            int best = 0;
-            for (int D = 4; D <= HEC_TRSV_MAX_RING; ++D) {
-                size_t b = upper ? lds_bytes<T, true>(tri.KC, W, D, S) : lds_bytes<T, false>(tri.KC, W, D, S);
-                if ((int64_t)b <= lds_max) best = D;
-            }
-            return best;
-        };
-        D64 = fit(double());
-        D32 = M.has_f32 ? fit(float()) : 4;
-        if ((D64 >= 4 && D32 >= 4) || R <= kSub || K > 32) break;
-        tiled = false;                       // fall back to (smaller) contiguous parts
-        R = std::max<int64_t>(kSub, R / 2);  // a smaller part keeps the ring of results smaller
-    }
-    tri.blocked = D64 >= 4 && D32 >= 4 && K <= 32;
-    if (!tri.blocked) {
-        // rows too long for the LDS slots: one part per row in level order, every
-        // dependency polled in global memory, 64-row chunks inside each level
-        for (int32_t t = 0; t < n; ++t) {
-            grow[t] = tri.hperm[t];
-            pos[tri.hperm[t]] = t;
-            part_of[tri.hperm[t]] = t;
-        }
-        part_pos.assign(2, 0);
-        part_pos[1] = n;
-        std::vector<int32_t> chunks{0};
-        for (int32_t l = 0; l < tri.nlev; ++l)
-            for (int32_t q = tri.hlevel_ptr[l]; q < tri.hlevel_ptr[l + 1]; q += kSub)
-                chunks.push_back(std::min(q + kSub, tri.hlevel_ptr[l + 1]));
-        tri.nchunks = (int32_t)chunks.size() - 1;
-        tri.chunk_ptr.alloc(chunks.size());
-        tri.chunk_ptr.upload(chunks.data(), chunks.size(), s);
-        part_ss.assign(2, 0);
-        ss_pos.assign(1, 0);
-    }
-    const int32_t nparts = tri.blocked ? (int32_t)part_pos.size() - 1 : 0;
-    tri.nparts = nparts;
-    tri.nss = (int32_t)ss_pos.size() - 1;
-    tri.W = W;
-    tri.S = S;
-    tri.D64 = D64;
-    tri.D32 = D32;
-    tri.lds64 = upper ? lds_bytes<double, true>(tri.KC, W, D64, S) : lds_bytes<double, false>(tri.KC, W, D64, S);
-    tri.lds32 = upper ? lds_bytes<float, true>(tri.KC, W, D32, S) : lds_bytes<float, false>(tri.KC, W, D32, S);
-
-    // entries per position: in-part dependencies by local position, others by row
-    const size_t slab = (size_t)K * tri.ldq;
-    std::vector<int32_t> enc(slab, kPad), src(slab, -1), psrc;
-    if (upper) psrc.assign(tri.ldq, -1);
-    for (int32_t q = 0; q < n; ++q) {
-        int32_t i = grow[q];
-        int32_t a = upper ? M.hdiag[i] + 1 : M.hLUp[i];
-        int32_t b = upper ? M.hLUp[i + 1] : M.hdiag[i];
-        int32_t pstart = tri.blocked ? part_pos[part_of[i]] : 0;
-        for (int32_t e = a, s2 = 0; e < b; ++e, ++s2) {
-            int32_t j = M.hLUj[e];
-            enc[(size_t)s2 * tri.ldq + q] = tri.blocked && part_of[j] == part_of[i] ? -(pos[j] - pstart + 1) : j;
-            src[(size_t)s2 * tri.ldq + q] = e;
-        }
-        if (upper) psrc[q] = M.hdiag[i];
-    }
-    tri.part_ss.alloc(part_ss.size());
-    tri.part_ss.upload(part_ss.data(), part_ss.size(), s);
-    tri.part_pos.alloc(part_pos.size());
-    tri.part_pos.upload(part_pos.data(), part_pos.size(), s);
-    tri.ss_pos.alloc(ss_pos.size());
-    tri.ss_pos.upload(ss_pos.data(), ss_pos.size(), s);
+    tri.part_ss.alloc(P.part_ss.size());
+    tri.part_ss.upload(P.part_ss.data(), P.part_ss.size(), s);
+    tri.part_pos.alloc(P.part_pos.size());
+    tri.part_pos.upload(P.part_pos.data(), P.part_pos.size(), s);
+    tri.ss_pos.alloc(P.ss_pos.size());
+    tri.ss_pos.upload(P.ss_pos.data(), P.ss_pos.size(), s);
     tri.grow.alloc(n);
-    tri.grow.upload(grow.data(), n, s);
+    tri.grow.upload(P.grow.data(), n, s);
     if (!upper && upper_plan) {
         // position of each lower-plan row in the upper plan
         std::vector<int32_t> up_pos(n), other(n);
-        std::vector<int32_t> ug(n);
-        upper_plan->grow.download(ug.data(), n, s);
-        HEC_HIP(hipStreamSynchronize(s));
-        for (int32_t q = 0; q < n; ++q) up_pos[ug[q]] = q;
-        for (int32_t q = 0; q < n; ++q) other[q] = up_pos[grow[q]];
+        for (int32_t q = 0; q < n; ++q) up_pos[upper_plan->hgrow[q]] = q;
+        for (int32_t q = 0; q < n; ++q) other[q] = up_pos[P.grow[q]];
         tri.other.alloc(n);
         tri.other.upload(other.data(), n, s);
+        HEC_HIP(hipStreamSynchronize(s));  // `other` is uploaded from host memory that ends here
     }
+    const size_t slab = (size_t)P.K * P.ldq;
     tri.enc.alloc(slab);
-    tri.enc.upload(enc.data(), slab, s);
+    tri.enc.upload(P.enc.data(), slab, s);
     tri.val.alloc(slab);
     if (M.has_f32) tri.val32.alloc(slab);
     DevBuf<int32_t> dsrc(slab);
     if (slab) {
-        dsrc.upload(src.data(), slab, s);
+        dsrc.upload(P.src.data(), slab, s);
         k_gather<<<ceil_div(slab, 256), 256, 0, s>>>(slab, dsrc.get(), M.LUx.get(), tri.val.get(), tri.val32.get());
         HEC_CHECK_LAUNCH();
     }
@@ -669,12 +524,13 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
         tri.piv.alloc(tri.ldq);
         if (M.has_f32) tri.piv32.alloc(tri.ldq);
         dp.alloc(tri.ldq);
-        dp.upload(psrc.data(), tri.ldq, s);
+        dp.upload(P.psrc.data(), tri.ldq, s);
         k_gather<<<ceil_div(tri.ldq, 256), 256, 0, s>>>(tri.ldq, dp.get(), M.LUx.get(), tri.piv.get(),
                                                         tri.piv32.get());
         HEC_CHECK_LAUNCH();
     }
     HEC_HIP(hipStreamSynchronize(s));
+    tri.hgrow = std::move(P.grow);
 }
 
 }  // namespace hec

@@ -77,7 +77,7 @@ def load(path: str = LIB_PATH):
     L.ilu_info.argtypes = [_vp, _i32p, _i64p]
     L.ilu_export.argtypes = [_vp, _vp, _vp, _vp]
     L.ilu_destroy.argtypes = [_vp]
-    L.level_schedule.argtypes = [_vp, C.POINTER(_vp)]
+    L.level_schedule.argtypes = [_vp, _vp, C.POINTER(_vp)]
     L.levels_info.argtypes = [_vp, _i32p, _i32p, _i32p]
     L.levels_export.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.levels_destroy.argtypes = [_vp]
@@ -234,9 +234,9 @@ def ilu_export(M: Factor):
     return LUp, LUj, LUx
 
 
-def level_schedule(M: Factor) -> Levels:
+def level_schedule(M: Factor, stream=None) -> Levels:
     out = _vp()
-    _check(load().level_schedule(M.ptr, C.byref(out)), "level_schedule")
+    _check(load().level_schedule(M.ptr, _stream_or_null(stream), C.byref(out)), "level_schedule")
     return Levels(out.value)
 
 

@@ -1,0 +1,259 @@
+"""Host-side checks of the triangular-solve plans (Sec. 2.6, Eq. (11), Alg. 3).
+
+The GPU library builds the plan of each triangle with a planner that is also
+compiled for the host alone (libhecplan.so). For ILU(k) factors computed by the
+oracle, every plan is checked for what the solve kernels rely on:
+
+* the level schedule equals the oracle's (Eq. (11), Alg. 3), bit for bit;
+* positions are a permutation; each part holds its rows by (level, row); each
+  sub-segment is one level of one part with at most 64 rows;
+* every dependency outside a part lies in an earlier part (parts are claimed in
+  order, so a workgroup only waits for parts already running: no deadlock);
+* the plan's LDS footprint fits the workgroup limit;
+
+and then replayed on the host in the order the kernels execute it, reading each
+dependency from where the kernel reads it (the ring of the part's recent results,
+which must still hold it, or the output vector, which must already hold it). The
+replay performs the same subtractions in the same order as the oracle's
+substitution, so the two agree bit for bit.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_1606_00545_amd import synth
+from tests import _plan
+
+
+def sparse_random(n, per_row, seed):
+    """Diagonally dominant random matrix, about per_row off-diagonal entries per row."""
+    rng = np.random.default_rng(seed)
+    R = sp.random(n, n, density=per_row / n, random_state=rng, format="csr")
+    R.data = rng.standard_normal(R.data.size)
+    R = R.tolil()
+    R.setdiag(0.0)
+    R = R.tocsr()
+    R.eliminate_zeros()
+    D = sp.diags(1.0 + np.asarray(abs(R).sum(1)).ravel())
+    A = (R + D).tocsr()
+    A.sort_indices()
+    return synth.CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def _cases():
+    yield "poisson2d_64_k0", lambda: synth.poisson2d(64), 0, {}
+    yield "poisson3d_32_k0", lambda: synth.poisson3d(32), 0, {"tiled": True}
+    yield "poisson3d_24_k1", lambda: synth.poisson3d(24), 1, {}
+    yield "tpfa3d_41x37x23_k0", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0, \
+        {"tiled": True}
+    yield "tpfa3d_41x37x23_k1", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 1, {}
+    yield "tpfa2d_301x97_k2", lambda: synth.lognormal_tpfa((301, 97), 1.5, np.random.default_rng(7)), 2, {}
+    yield "random_20000_k1", lambda: sparse_random(20000, 8, 8), 1, {}
+    yield "powerlaw_20000_k0", lambda: synth.powerlaw_random(20000, np.random.default_rng(9)), 0, \
+        {"blocked": False}
+    yield "tpfa3d_small_lds", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0, \
+        {"lds_max": 24 * 1024}
+    yield "tpfa3d_tiny_lds", lambda: synth.lognormal_tpfa((17, 13, 11), 2.0, np.random.default_rng(2)), 1, \
+        {"lds_max": 4 * 1024, "blocked": False}
+    yield "tridiag_1000_k0", lambda: synth.CSR(*_tridiag(1000)), 0, {}
+    yield "diagonal_300", lambda: synth.CSR(*_diagonal(300)), 0, {}
+    yield "single_row", lambda: synth.CSR(*_diagonal(1)), 0, {}
+
+
+def _tridiag(n):
+    Ap = np.concatenate([[0], np.cumsum([2 if i in (0, n - 1) else 3 for i in range(n)])]).astype(np.int32)
+    Aj, Ax = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                Aj.append(j)
+                Ax.append(4.0 if j == i else -1.0 - 0.01 * ((i * 7 + j) % 5))
+    return n, Ap, np.array(Aj, np.int32), np.array(Ax)
+
+
+def _diagonal(n):
+    return n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), 1.0 + np.arange(n) % 3
+
+
+CASES = {name: (mk, k, opt) for name, mk, k, opt in _cases()}
+
+
+@pytest.fixture(scope="module")
+def factors():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            mk, k, opt = CASES[name]
+            A = mk()
+            F = O.iluk(A.n, A.Ap, A.Aj, A.Ax, k)
+            cache[name] = (A, F, opt)
+        return cache[name]
+    return get
+
+
+def check_structure(P, F, upper, lds_max):
+    n, K, ldq, W, kSub, kPad = P["n"], P["K"], P["ldq"], P["W"], P["kSub"], P["kPad"]
+    d = P["diag"]
+    counts = (F.LUp[1:] - d - 1) if upper else (d - F.LUp[:-1])
+    assert K == (counts.max() if n else 0)
+    assert P["KC"] in (4, 8, 16, 32) and (P["KC"] >= K or not P["blocked"])
+    assert ldq % 64 == 0 and ldq >= n
+    grow, pos = P["grow"], P["pos"]
+    assert np.array_equal(np.sort(grow), np.arange(n)), "positions are not a permutation"
+    assert np.array_equal(pos[grow], np.arange(n))
+    enc = P["enc"].reshape(K, ldq)
+    src = P["src"].reshape(K, ldq)
+    # entry s of position q is the s-th entry of the row's triangle, in row order
+    for q in range(0, n, max(1, n // 2000)):
+        i = grow[q]
+        a = d[i] + 1 if upper else F.LUp[i]
+        c = counts[i]
+        assert np.array_equal(src[:c, q], np.arange(a, a + c))
+        assert (src[c:, q] == -1).all() and (enc[c:, q] == kPad).all()
+    assert (enc[:, n:] == kPad).all()
+    if upper:
+        assert np.array_equal(P["psrc"][:n], d[grow])
+    if not P["blocked"]:
+        assert np.array_equal(grow, P["perm"])
+        ch = P["chunks"]
+        lp = P["level_ptr"]
+        assert ch[0] == 0 and ch[-1] == n and (np.diff(ch) > 0).all() and (np.diff(ch) <= kSub).all()
+        assert set(lp.tolist()) <= set(ch.tolist()), "a chunk crosses a level boundary"
+        assert ((enc >= 0) | (enc == kPad)).all()
+        return
+    nparts = P["nparts"]
+    pp, pss, ssp = P["part_pos"], P["part_ss"], P["ss_pos"]
+    assert pp[0] == 0 and pp[-1] == n and (np.diff(pp) > 0).all()
+    part_of = P["part_of"]
+    assert np.array_equal(part_of[grow], np.repeat(np.arange(nparts), np.diff(pp)))
+    lev = P["lev"]
+    assert pss[0] == 0 and pss[-1] == P["nss"] and ssp[-1] == n
+    S = 0
+    for p in range(nparts):
+        starts = ssp[pss[p]:pss[p + 1] + 1]
+        assert starts[0] == pp[p] and starts[-1] == pp[p + 1]
+        sizes = np.diff(starts)
+        assert (sizes > 0).all() and (sizes <= kSub).all()
+        S = max(S, pss[p + 1] - pss[p])
+        rows = grow[pp[p]:pp[p + 1]]
+        key = lev[rows].astype(np.int64) * n + rows
+        assert (np.diff(key) > 0).all(), "part rows are not in (level, row) order"
+        # one level per sub-segment
+        seg = np.repeat(np.arange(len(sizes)), sizes)
+        lv = lev[rows]
+        first = lv[np.searchsorted(seg, seg)]
+        assert np.array_equal(lv, first)
+    assert S == P["S"]
+    assert P["W"] >= 64 and P["W"] & (P["W"] - 1) == 0
+    assert 4 <= P["D64"] <= 32 and 4 <= P["D32"] <= 32
+    assert P["lds64"] <= lds_max and P["lds32"] <= lds_max
+    # dependencies: inside the part by local position, otherwise in an earlier part
+    qs = np.arange(n)
+    for s in range(K):
+        e = enc[s, :n]
+        outer = e >= 0
+        assert (part_of[e[outer]] < part_of[grow[qs[outer]]]).all(), "dependency in a later part"
+        inner = (e < 0) & (e != kPad)
+        lp = -e[inner] - 1
+        owner = part_of[grow[qs[inner]]]
+        j = grow[pp[owner] + lp]
+        assert np.array_equal(j, F.LUj[src[s, :n][inner]])
+        assert np.array_equal(e[outer], F.LUj[src[s, :n][outer]])
+
+
+def replay(P, F, b, upper):
+    """Runs the plan on the host in kernel order; returns x (by row)."""
+    n, K, ldq, W, kPad = P["n"], P["K"], P["ldq"], P["W"], P["kPad"]
+    grow = P["grow"]
+    enc = P["enc"].reshape(K, ldq)
+    src = P["src"].reshape(K, ldq)
+    x = np.full(n, np.nan)
+    done = np.zeros(n, bool)
+
+    def segment(q0, q1, ring, ring_pos, pos0, earlier):
+        rows = grow[q0:q1]
+        acc = b[rows].copy()
+        for s in range(K):
+            e = enc[s, q0:q1]
+            sr = src[s, q0:q1]
+            pad = e == kPad
+            outer = e >= 0
+            inner = ~pad & ~outer
+            xv = np.zeros(q1 - q0)
+            if inner.any():
+                lp = -e[inner] - 1
+                slot = lp & (W - 1)
+                assert (ring_pos[slot] == lp).all(), "ring no longer holds a dependency"
+                xv[inner] = ring[slot]
+            if outer.any():
+                assert done[e[outer]].all(), "dependency not solved before its reader"
+                assert earlier(e[outer]).all()
+                xv[outer] = x[e[outer]]
+            v = np.where(pad, 0.0, F.LUx[np.where(pad, 0, sr)])
+            acc = acc - v * xv
+        if upper:
+            acc = acc / F.LUx[P["psrc"][q0:q1]]
+        if ring is not None:
+            loc = np.arange(q0, q1) - pos0
+            ring[loc & (W - 1)] = acc
+            ring_pos[loc & (W - 1)] = loc
+        x[rows] = acc
+        done[rows] = True
+
+    if P["blocked"]:
+        pp, pss, ssp, part_of = P["part_pos"], P["part_ss"], P["ss_pos"], P["part_of"]
+        for p in range(P["nparts"]):
+            ring = np.zeros(W)
+            ring_pos = np.full(W, -1, np.int64)
+            for t in range(pss[p], pss[p + 1]):
+                segment(ssp[t], ssp[t + 1], ring, ring_pos, pp[p], lambda j, p=p: part_of[j] < p)
+    else:
+        ch, pos = P["chunks"], P["pos"]
+        for c in range(len(ch) - 1):
+            segment(ch[c], ch[c + 1], None, None, 0, lambda j, c=c: pos[j] < ch[c])
+    assert done.all()
+    return x
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_plan_structure_and_replay(factors, name):
+    A, F, opt = factors(name)
+    grid = _plan.detect_grid(A)
+    lds_max = opt.get("lds_max", _plan.LDS_MAX)
+    b = np.random.default_rng(11).uniform(-1, 1, A.n)
+    y_o = O.trsv_lower(F, b)
+    x_o = O.trsv_upper(F, y_o)
+    for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
+        P = _plan.make_plan(F, upper, grid, lds_max=lds_max)
+        o = O.level_schedule(F.n, F.LUp, F.LUj, "upper" if upper else "lower")
+        assert P["nlev"] == o.nlev
+        assert np.array_equal(P["level_ptr"], o.level_ptr) and np.array_equal(P["perm"], o.perm)
+        assert np.array_equal(P["lev"], o.lev)
+        if "blocked" in opt:
+            assert bool(P["blocked"]) == opt["blocked"]
+        if opt.get("tiled"):
+            assert P["blocked"] and P["nparts"] > 1
+            # tiles: a part's rows are not one contiguous row range
+            pp = P["part_pos"]
+            rows = P["grow"][pp[0]:pp[1]]
+            assert rows.max() - rows.min() + 1 > rows.size
+        check_structure(P, F, upper, lds_max)
+        x = replay(P, F, rhs, upper)
+        assert np.array_equal(x.view(np.uint64), ref.view(np.uint64)), "replay differs from the oracle"
+
+
+def test_detect_grid():
+    assert _plan.detect_grid(synth.poisson3d(12)) == (12, 12, 12)
+    assert _plan.detect_grid(synth.lognormal_tpfa((7, 5, 3), 1.0, np.random.default_rng(1))) == (7, 5, 3)
+    assert _plan.detect_grid(synth.lognormal_tpfa((31, 23), 1.0, np.random.default_rng(1))) == (31, 23, 1)
+    assert _plan.detect_grid(sparse_random(500, 4, 1)) == (0, 0, 0)
+    # a 7-point pattern with one extra entry is no longer a grid
+    A = synth.poisson3d(6)
+    D = sp.csr_matrix((A.Ax, A.Aj, A.Ap), shape=(A.n, A.n)).tolil()
+    D[100, 3] = -0.5
+    D = D.tocsr()
+    D.sort_indices()
+    B = synth.CSR(A.n, D.indptr.astype(np.int32), D.indices.astype(np.int32), D.data)
+    assert _plan.detect_grid(B) == (0, 0, 0)
