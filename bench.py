@@ -41,8 +41,9 @@ def parse():
     p.add_argument("--cpu-sample-iters", type=int, default=30)
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
-                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving"],
-                   help="diffusion128 is the benchmark line; the others print extra records")
+                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "copy"],
+                   help="diffusion128 is the benchmark line; the others print extra records "
+                        "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     p.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     return p.parse_args()
@@ -319,7 +320,6 @@ def extra(args):
                          "seconds": round(inf["seconds"], 4), "rel_res": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
                          "err_vs_x_true": float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))}
             log(f"[bench] {name}: {res[name]}")
-        res["mixed_vs_fp64_x"] = None
         zb = torch.empty_like(b)
         zf = torch.empty(A.n, dtype=torch.float32, device=dev)
         bf = b.float()
@@ -329,6 +329,13 @@ def extra(args):
                     "trsv_lu_us_f32": round(time_launches(lambda: hec.trsv_levels(F, lv, bf, zf, hec.LU), 10, stream) * 1e6, 1)})
     elif args.workload == "serving":
         out.update(serving(args))
+    elif args.workload == "copy":
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        t = time_launches(lambda: dst.copy_(src), 5, stream)
+        out.update({"bytes_read": nbytes, "bytes_written": nbytes, "us": round(t * 1e6, 1),
+                    "GBps": round(2 * nbytes / t / 1e9, 1)})
     print(json.dumps(out), flush=True)
 
 

@@ -183,6 +183,43 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
 hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
                           const hec_solve_opts *opts, hec_solve_info *info, void *stream);
 
+/* ---------------------------------------------------------------- batched small systems */
+
+/* Largest system (rows) a batch context accepts: the per-system intermediate
+ * vector of the preconditioner solve lives in the workgroup's LDS. */
+#define HEC_BATCH_MAX_N 16384
+
+typedef struct hec_batch_s *hec_batch; /* context for gmres_solve_batched */
+
+/* Creates a context for batches of up to `capacity` systems of at most `max_n`
+ * rows each, solved by GMRES(restart). It owns pinned staging memory, device
+ * descriptor and result arrays, and a workspace of (2*restart + 3) * max_n
+ * doubles per system (allocated here, so solving allocates nothing).
+ * use_graph != 0: the first solve records descriptor upload, kernel and result
+ * download into a hipGraph, and every later solve replays it. */
+hec_status batch_create(int32_t capacity, int32_t restart, int32_t max_n, int32_t use_graph, hec_batch *out);
+
+hec_status batch_destroy(hec_batch B);
+
+/* Restarted GMRES (Sec. 2.7) on `count` independent systems A[i] x[i] = b[i] in
+ * one persistent launch, one workgroup per system (the serving path for small
+ * systems). Same method as gmres_solve on each system: right preconditioning with
+ * the factor M[i] (Eq. (7)-(8)) applied level by level in the order of lv[i]
+ * (Eq. (11), Alg. 3), classical Gram-Schmidt twice, Givens rotations, restarts
+ * from the FP64 true residual; precision 1 runs each cycle on the FP32 value
+ * copies (HEC_KEEP_F32 on A[i] and M[i]) with FP64 vectors and refinement.
+ * The Krylov basis is FP64 in both precisions. A[i], M[i], lv[i] are handles of
+ * the same size n_i <= max_n; b[i], x[i] are device FP64 vectors of n_i
+ * elements; opts->restart must equal the context's. A system's result does not
+ * depend on the rest of the batch. `stream`: the call waits for work already
+ * queued on it, runs on the context's own stream and synchronises before it
+ * returns; calls on one context must not overlap. info (may be NULL): `count`
+ * entries. Returns HEC_ERR_NOT_CONVERGED if any system did not converge (its
+ * info entry says which). */
+hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, const hec_ilu *M,
+                               const hec_levels *lv, const double *const *b, double *const *x,
+                               const hec_solve_opts *opts, hec_solve_info *info, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *hec_last_error(void);
 

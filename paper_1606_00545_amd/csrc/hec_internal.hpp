@@ -168,6 +168,7 @@ struct hec_ilu_s {
 struct hec_tri {
     int32_t nlev = 0;
     std::vector<int32_t> hlevel_ptr, hperm;  // Alg. 3: level start pointers, rows by (level, row)
+    hec::DevBuf<int32_t> dlevel_ptr, dperm;  // device copies (used by the batched small-system solver)
     int32_t K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 0, S = 0;  // KC: K padded to 4/8/16/32
     int32_t D64 = 0, D32 = 0;                // ring depths for the FP64 / FP32 solve
     bool blocked = true;                     // false: rows too long for LDS slots, per-row polling kernel

@@ -136,54 +136,84 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
         __syncthreads();
 
         if (wave == 0) {
-            // ---------------- solver: two LDS round trips and KC fused multiply-adds per row
+            // ---------------- solver: one LDS round trip and KC fused multiply-adds per row.
+            // The next sub-segment's header and dependency addresses are read while the
+            // current one is computed (two register sets used alternately), so the only
+            // dependent LDS access of a step is the read of its dependencies' values.
             __builtin_amdgcn_s_setprio(3);
-            int slot = 0;
-            int ready = 0;  // sub-segments [rel, ready) are known to be filled
-            for (int rel = 0; rel < nss; ++rel) {
-                if (rel >= ready) {
-                    // look at up to 8 slots in one LDS round trip; wait for the first
-                    for (;;) {
-                        int ok = 0;
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int r2 = rel + u;
-                            int sl2 = slot + u;
-                            sl2 = sl2 >= D ? sl2 - D : sl2;
-                            const int f = __hip_atomic_load(&filled[sl2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            ok += (ok == u && u < D && r2 < nss && f == r2) ? 1 : 0;
-                        }
-                        if (ok > 0) {
-                            ready = rel + ok;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                const int q0 = sspos[rel], cnt = sspos[rel + 1] - q0;  // rows and first position
-                const char *sl = smem + slots_off + slot * sb;
-                T acc = ((const T *)(sl + L.b()))[lane];
-                const int gi = ((const int *)(sl + L.gi()))[lane];
-                const int po = ((const int *)(sl + L.po()))[lane];
-                T dd = (T)1;
-                if constexpr (UPPER) dd = ((const T *)(sl + L.d()))[lane];
+            struct Head {
+                T b, d;
+                int gi, po, q0, cnt;
                 uint32_t ad[KC];
-                T av[KC];
+            };
+            int ready = 0;  // sub-segments [.., ready) are known to be filled
+            // Waits until sub-segment r (in slot sl) is filled; returns the end of the
+            // run of consecutive filled sub-segments starting at r (at most 8 looked at).
+            // The flags are read with relaxed loads in one round trip: a slot's contents
+            // are complete before its flag is written (the prefetcher waits for its LDS
+            // writes first), LDS accesses of one wavefront complete in order, and the
+            // signal fence keeps the compiler from moving slot reads above the check.
+            auto scan = [&](int r, int sl) -> int {
+                for (;;) {
+                    int f[8];
 #pragma unroll
-                for (int u = 0; u < KC; ++u) {
-                    ad[u] = ((const uint32_t *)(sl + L.a()))[u * kSub + lane];
-                    av[u] = ((const T *)(sl + L.v()))[u * kSub + lane];
+                    for (int u = 0; u < 8; ++u) {
+                        int s2 = sl + u;
+                        s2 = s2 >= D ? s2 - D : s2;  // in bounds of the control block for every D >= 4
+                        f[u] = __hip_atomic_load(&filled[s2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) m |= (u < D && r + u < nss && f[u] == r + u) ? 1u << u : 0u;
+                    const int ok = __builtin_ctz(~m);  // filled sub-segments r, r+1, ... in a row
+                    if (ok > 0) {
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        return r + ok;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                T xv[KC];
+            };
+            auto load_head = [&](int r, int sl, Head &H) {
+                const char *p2 = smem + slots_off + sl * sb;
+                H.q0 = sspos[r];
+                H.cnt = sspos[r + 1] - H.q0;
+                H.b = ((const T *)(p2 + L.b()))[lane];
+                H.gi = ((const int *)(p2 + L.gi()))[lane];
+                H.po = ((const int *)(p2 + L.po()))[lane];
+                H.d = (T)1;
+                if constexpr (UPPER) H.d = ((const T *)(p2 + L.d()))[lane];
 #pragma unroll
-                for (int u = 0; u < KC; ++u) xv[u] = *(const T *)(smem + ad[u]);
+                for (int u = 0; u < KC; ++u) H.ad[u] = ((const uint32_t *)(p2 + L.a()))[u * kSub + lane];
+            };
+            // Two register sets fit the 128-VGPR budget of a 1024-thread workgroup for
+            // rows of up to 64 bytes of values; longer rows load the next header after
+            // the step instead (nxt is then cur).
+            constexpr bool kPipe = KC * sizeof(T) <= 64;
+            // One sub-segment: cur is loaded; nxt receives sub-segment rel + 1.
+            auto step = [&](int rel, int slot, Head &cur, Head &nxt) {
+                const int nslot = slot + 1 == D ? 0 : slot + 1;
+                const char *p2 = smem + slots_off + slot * sb;
+                const bool pre = kPipe && rel + 1 < ready;
+                T acc = cur.b;
+                // entries in chunks of at most 8 (bounds the live registers of long rows)
+                constexpr int CH = KC < 8 ? KC : 8;
 #pragma unroll
-                for (int u = 0; u < KC; ++u) acc -= av[u] * xv[u];
-                if constexpr (UPPER) acc = acc / dd;
-                if (lane < cnt) {
-                    sx[(q0 - pos0 + lane) & (W - 1)] = acc;
-                    store_coherent(x + gi, acc);
-                    if (yother) yother[po] = acc;
+                for (int c0 = 0; c0 < KC; c0 += CH) {
+                    T xv[CH], av[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        xv[u] = *(const T *)(smem + cur.ad[c0 + u]);
+                        av[u] = ((const T *)(p2 + L.v()))[(c0 + u) * kSub + lane];
+                    }
+                    if (c0 == 0 && pre) load_head(rel + 1, nslot, nxt);
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) acc -= av[u] * xv[u];
+                }
+                if constexpr (UPPER) acc = acc / cur.d;
+                if (lane < cur.cnt) {
+                    sx[(cur.q0 - pos0 + lane) & (W - 1)] = acc;
+                    store_coherent(x + cur.gi, acc);
+                    if (yother) yother[cur.po] = acc;
                 }
                 // release consumed slots to the prefetchers every 4 sub-segments (and at the end)
                 if ((rel & 3) == 3 || rel + 1 == nss) {
@@ -191,7 +221,30 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     if (lane == 0)
                         __hip_atomic_store(consumed, rel + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
-                slot = slot + 1 == D ? 0 : slot + 1;
+                if (kPipe && !pre && rel + 1 < nss) {
+                    ready = scan(rel + 1, nslot);
+                    load_head(rel + 1, nslot, nxt);
+                }
+                return nslot;
+            };
+            int slot = 0;
+            if constexpr (kPipe) {
+                Head h0, h1;
+                if (nss > 0) {
+                    ready = scan(0, 0);
+                    load_head(0, 0, h0);
+                }
+                for (int rel = 0; rel < nss; rel += 2) {
+                    slot = step(rel, slot, h0, h1);
+                    if (rel + 1 < nss) slot = step(rel + 1, slot, h1, h0);
+                }
+            } else {
+                for (int rel = 0; rel < nss; ++rel) {
+                    if (rel >= ready) ready = scan(rel, slot);
+                    Head h;
+                    load_head(rel, slot, h);
+                    slot = step(rel, slot, h, h);
+                }
             }
             __builtin_amdgcn_s_setprio(0);
         } else {
@@ -471,6 +524,11 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     plan::make_plan(n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, M.has_f32,
                     max_lds_per_block() - 256, P);
     tri.nlev = P.nlev;
+    tri.dlevel_ptr.alloc(P.level_ptr.size());
+    tri.dlevel_ptr.upload(P.level_ptr.data(), P.level_ptr.size(), s);
+    tri.dperm.alloc(P.perm.size());
+    tri.dperm.upload(P.perm.data(), P.perm.size(), s);
+    HEC_HIP(hipStreamSynchronize(s));  // the host arrays move below
     tri.hlevel_ptr = std::move(P.level_ptr);
     tri.hperm = std::move(P.perm);
     tri.K = P.K;

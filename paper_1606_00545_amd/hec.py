@@ -25,7 +25,9 @@ LOWER, UPPER, LU = 1, 2, 3
 EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "ilu_factor", "ilu_info", "ilu_export", "ilu_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
-            "trsv_levels", "gmres_solve", "bicgstab_solve", "hec_last_error")
+            "trsv_levels", "gmres_solve", "bicgstab_solve",
+            "batch_create", "batch_destroy", "gmres_solve_batched", "hec_last_error")
+BATCH_MAX_N = 16384
 
 
 class HecError(RuntimeError):
@@ -84,6 +86,10 @@ def load(path: str = LIB_PATH):
     L.trsv_levels.argtypes = [_vp, _vp, C.c_uint32, C.c_int, _vp, _vp, _vp]
     L.gmres_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _vp]
     L.bicgstab_solve.argtypes = L.gmres_solve.argtypes
+    L.batch_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_vp)]
+    L.batch_destroy.argtypes = [_vp]
+    L.gmres_solve_batched.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts),
+                                      _vp, _vp]
     for name in EXPORTED:
         if name != "hec_last_error":
             getattr(L, name).restype = C.c_int
@@ -159,6 +165,17 @@ class Factor(_Handle):
 
 class Levels(_Handle):
     _destroy = "levels_destroy"
+
+
+class Batch(_Handle):
+    """Context of gmres_solve_batched: up to `capacity` systems of at most `max_n` rows."""
+    _destroy = "batch_destroy"
+
+    def __init__(self, capacity: int, restart: int = 30, max_n: int = BATCH_MAX_N, use_graph: bool = True):
+        h = _vp()
+        _check(load().batch_create(capacity, restart, max_n, int(use_graph), C.byref(h)), "batch_create")
+        super().__init__(h.value)
+        self.capacity, self.restart, self.max_n = capacity, restart, max_n
 
 
 # ---------------------------------------------------------------- HEC matrix
@@ -294,3 +311,23 @@ def bicgstab_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, r
     if check and code != OK:
         _check(code, "bicgstab_solve")
     return info.as_dict()
+
+
+def gmres_solve_batched(B: Batch, systems, maxit: int = 10000, rtol: float = 1e-8, precision: int = 0,
+                        x0_zero: bool = True, ir_rtol: float = 0.0, inner_rtol: float = 1e-4, stream=None,
+                        check: bool = True) -> list:
+    """GMRES(B.restart) on every (A, M, lv, b, x) of `systems` in one launch; returns one info dict each."""
+    import torch
+    count = len(systems)
+    o = _opts(B.restart, maxit, rtol, precision, x0_zero, ir_rtol, inner_rtol)
+    arr = lambda vals: (_vp * max(1, count))(*vals)
+    A = arr([s[0].ptr for s in systems])
+    M = arr([s[1].ptr for s in systems])
+    lv = arr([s[2].ptr for s in systems])
+    b = arr([_dev(s[3], torch.float64) for s in systems])
+    x = arr([_dev(s[4], torch.float64) for s in systems])
+    infos = (SolveInfo * max(1, count))()
+    code = load().gmres_solve_batched(B.ptr, count, A, M, lv, b, x, C.byref(o), infos, _stream(stream))
+    if check and code != OK:
+        _check(code, "gmres_solve_batched")
+    return [infos[i].as_dict() for i in range(count)]
