@@ -46,6 +46,7 @@ def parse():
                         "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     p.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
+    p.add_argument("--batch-max-n", type=int, default=8192, help="serving: largest batched system")
     return p.parse_args()
 
 
@@ -341,61 +342,51 @@ def extra(args):
 
 def serving(args):
     """Serving: requests (2D or 3D lognormal diffusion, n log-uniform in [1e3, 1e6],
-    per-request seed) arrive as a Poisson process at 0.7x the measured sequential
-    FP64 throughput; FP64 and mixed precision runs replay the same trace."""
-    import threading
-    import queue
+    sigma in [0.5, 3], per-request seed). Three server configurations replay the same
+    requests: FP64 with every request on its own stream ("fp64"), FP64 with small
+    systems batched into persistent launches ("fp64_batched"), and mixed precision
+    with batching ("mixed_batched"). Closed loop (all requests queued at t=0) gives
+    throughput; open loop (Poisson arrivals at 0.7x the fp64 closed-loop rate)
+    gives p50/p99 latency at a stated load."""
     from paper_1606_00545_amd import serve, synth
-    import torch
 
-    reqs = synth.serving_requests(args.requests)
-
-    def build(spec, prec):
+    t0 = time.time()
+    specs = synth.serving_requests(args.requests)
+    systems = []
+    for spec in specs:
         A, xt = synth.request_system(spec)
-        # b = A x_true through scipy on the host (client side, outside the measured latency)
-        b = A.to_scipy() @ xt
-        return serve.Request(spec.rid, A, b, precision=prec, rtol=1e-8)
+        systems.append((spec.rid, A, A.to_scipy() @ xt))  # b = A x_true on the host (client side)
+    log(f"[bench] serving: {len(systems)} requests generated in {time.time() - t0:.1f}s; "
+        f"batched route n <= {args.batch_max_n}: {sum(1 for _, A, _ in systems if A.n <= args.batch_max_n)}")
+    configs = (("fp64", 0, 0), ("fp64_batched", 0, args.batch_max_n), ("mixed_batched", 1, args.batch_max_n))
 
-    # calibration: sequential FP64 service time on the first few requests
-    cal = [build(s, 0) for s in reqs[:12]]
-    srv = serve.Server(slots=1)
-    t = time.perf_counter()
-    srv.run(cal)
-    seq_rate = len(cal) / (time.perf_counter() - t)
-    rate = 0.7 * seq_rate
-    arrivals = synth.poisson_arrivals(len(reqs), rate)
-    out = {"requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 3),
-           "sequential_fp64_solves_per_s": round(seq_rate, 3)}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
-        q = queue.Queue(maxsize=16)
-
-        def producer():
-            for spec, t_arr in zip(reqs, arrivals):
-                r = build(spec, prec)
-                r.arrival = float(t_arr)
-                q.put(r)
-            q.put(None)
-
-        def source():
-            while True:
-                r = q.get()
-                if r is None:
-                    return
-                yield r
-
-        th = threading.Thread(target=producer, daemon=True)
-        th.start()
-        srv = serve.Server(slots=args.slots)
+    def run(prec, bmax, arrivals):
+        reqs = [serve.Request(rid, A, b, precision=prec, rtol=1e-8, arrival=float(t))
+                for (rid, A, b), t in zip(systems, arrivals)]
+        srv = serve.Server(slots=args.slots, batch_max_n=bmax)
         t = time.perf_counter()
-        res = srv.run(source(), t0=t)
+        res = srv.run(reqs, t0=t)
         span = max(r.done for r in res) if res else 0.0
         st = serve.latency_stats(res)
         ok = sum(1 for r in res if r.info["status"] == 0 and r.info["rel_res_true"] <= 1e-8)
-        out[name] = {"completed": len(res), "converged": ok, "errors": len(srv.errors),
-                     "solves_per_s": round(len(res) / span, 3) if span else None,
-                     "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
-                     "peak_inflight": srv.peak_inflight}
-        log(f"[bench] serving {name}: {out[name]}")
+        return {"completed": len(res), "converged": ok, "errors": len(srv.errors),
+                "solves_per_s": round(len(res) / span, 3) if span else None,
+                "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                "peak_inflight": srv.peak_inflight, "batched_launches": len(srv.batches),
+                "mean_batch": round(float(np.mean(srv.batches)), 1) if srv.batches else 0}
+
+    out = {"requests": len(systems), "slots": args.slots, "batch_max_n": args.batch_max_n}
+    closed = {}
+    for name, prec, bmax in configs:
+        closed[name] = run(prec, bmax, np.zeros(len(systems)))
+        log(f"[bench] serving closed-loop {name}: {closed[name]}")
+    rate = 0.7 * closed["fp64"]["solves_per_s"]
+    arrivals = synth.poisson_arrivals(len(systems), rate)
+    opened = {}
+    for name, prec, bmax in configs:
+        opened[name] = run(prec, bmax, arrivals)
+        log(f"[bench] serving open-loop {name} at {rate:.2f}/s: {opened[name]}")
+    out.update({"closed_loop": closed, "open_loop_rate_per_s": round(rate, 3), "open_loop": opened})
     return out
 
 

@@ -185,9 +185,10 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
 
 /* ---------------------------------------------------------------- batched small systems */
 
-/* Largest system (rows) a batch context accepts: the per-system intermediate
- * vector of the preconditioner solve lives in the workgroup's LDS. */
-#define HEC_BATCH_MAX_N 16384
+/* Largest system (rows) a batch context accepts: the two triangular solves of a
+ * system keep their vectors in the workgroup's LDS. level_schedule prepares the
+ * level-ordered factor copies the batched solver reads for every n up to this. */
+#define HEC_BATCH_MAX_N 8192
 
 typedef struct hec_batch_s *hec_batch; /* context for gmres_solve_batched */
 

@@ -8,9 +8,11 @@
 // carried out by the workgroup alone:
 //  * SpMV over the HEC arrays (Alg. 1: the ELL slab, then the CSR remainder),
 //    one row per thread, FP64 accumulation;
-//  * the preconditioner solve level by level (Eq. (11), Alg. 3): the rows of a
-//    level are spread over the threads, a workgroup barrier separates levels,
-//    and the intermediate vector stays in LDS;
+//  * the preconditioner solve in level order (Eq. (11), Alg. 3) over a
+//    level-ordered copy of each triangle: 64-row chunks of one level are taken
+//    by the 16 wavefronts in turn, and a row reads each dependency from LDS as
+//    soon as it is final (the LDS vectors start filled with a signalling-NaN
+//    pattern that arithmetic never produces), so no barrier separates levels;
 //  * classical Gram-Schmidt applied twice, deterministic block reductions,
 //    Givens rotations and the small least-squares solve in FP64 in LDS;
 //  * cycles restart from the FP64 true residual. precision 1: each cycle uses the
@@ -20,6 +22,7 @@
 // system's result is bit-identical alone and in any batch.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <mutex>
 
@@ -28,23 +31,26 @@
 namespace hec {
 namespace {
 
-constexpr int kBT = 256;          // threads per system
+constexpr int kBT = 1024;         // threads per system
 constexpr int kBW = kBT / 64;     // wavefronts per system
 constexpr int kBMaxM = 32;        // largest restart length
 constexpr int kBRedStride = 33;   // per-wavefront partial sums in LDS
+constexpr int kRows = (HEC_BATCH_MAX_N + kBT - 1) / kBT;  // rows per thread at most
 
 struct BatchSys {
-    int32_t n, K, ld, nlevL, nlevU, has_rem;
+    int32_t n, K, ld, has_rem;
     const int32_t *ell_col;
     const double *ell_val;
     const float *ell_val32;
     const int32_t *rem_ptr, *rem_col;
     const double *rem_val;
     const float *rem_val32;
-    const int32_t *LUp, *LUj, *diag;
-    const double *LUx;
-    const float *LUx32;
-    const int32_t *lvlL, *permL, *lvlU, *permU;
+    // level-ordered triangles (lower, upper): chunk starts, position -> row,
+    // dependency rows and values at s*ldq + q, pivots (upper)
+    int32_t KL, KU, ldq, nchL, nchU;
+    const int32_t *chL, *rowL, *colL, *chU, *rowU, *colU;
+    const double *valL, *valU, *pivU;
+    const float *valL32, *valU32, *pivU32;
     const double *b;
     double *x;
     double *ws;  // (2m + 3) * n doubles: V (m+1), Z (m), r, w
@@ -60,15 +66,18 @@ struct BatchOut {
     double rel_res_true, rel_res_est;
 };
 
-// LDS layout of one system (dynamic): ly[max_n] | red[kBW][33] | H[(m+1)][m] |
-// cs[m] | sn[m] | g[m+1] | y[m] | sc[8]
+// LDS layout of one system (dynamic): ly[max_n] | lz[max_n] | red[kBW][33] |
+// H[(m+1)][m] | cs[m] | sn[m] | g[m+1] | y[m] | sc[8]
 struct Lds {
-    double *ly, *red, *H, *cs, *sn, *g, *y, *sc;
+    double *ly, *lz, *red, *H, *cs, *sn, *g, *y, *sc;
 };
 
 __host__ __device__ inline size_t batch_lds_bytes(int max_n, int m) {
-    return sizeof(double) * ((size_t)max_n + kBW * kBRedStride + (size_t)(m + 1) * m + 4 * (size_t)m + 1 + 8);
+    return sizeof(double) * (2 * (size_t)max_n + kBW * kBRedStride + (size_t)(m + 1) * m + 4 * (size_t)m + 1 + 8);
 }
+
+constexpr unsigned long long kSent = 0x7FF4DEADBEEF1234ull;  // signalling NaN: never produced by arithmetic
+constexpr unsigned long long kQNaN = 0x7FF8000000000000ull;
 
 template <class VT> __device__ __forceinline__ const VT *ellv(const BatchSys &S);
 template <> __device__ __forceinline__ const double *ellv<double>(const BatchSys &S) { return S.ell_val; }
@@ -76,9 +85,16 @@ template <> __device__ __forceinline__ const float *ellv<float>(const BatchSys &
 template <class VT> __device__ __forceinline__ const VT *remv(const BatchSys &S);
 template <> __device__ __forceinline__ const double *remv<double>(const BatchSys &S) { return S.rem_val; }
 template <> __device__ __forceinline__ const float *remv<float>(const BatchSys &S) { return S.rem_val32; }
-template <class VT> __device__ __forceinline__ const VT *luv(const BatchSys &S);
-template <> __device__ __forceinline__ const double *luv<double>(const BatchSys &S) { return S.LUx; }
-template <> __device__ __forceinline__ const float *luv<float>(const BatchSys &S) { return S.LUx32; }
+template <class VT> __device__ __forceinline__ const VT *fval(const BatchSys &S, bool up);
+template <> __device__ __forceinline__ const double *fval<double>(const BatchSys &S, bool up) {
+    return up ? S.valU : S.valL;
+}
+template <> __device__ __forceinline__ const float *fval<float>(const BatchSys &S, bool up) {
+    return up ? S.valU32 : S.valL32;
+}
+template <class VT> __device__ __forceinline__ const VT *fpiv(const BatchSys &S);
+template <> __device__ __forceinline__ const double *fpiv<double>(const BatchSys &S) { return S.pivU; }
+template <> __device__ __forceinline__ const float *fpiv<float>(const BatchSys &S) { return S.pivU32; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -133,32 +149,66 @@ __device__ void b_spmv(const BatchSys &S, const double *x, double *y, const doub
     __syncthreads();
 }
 
-// out = U^{-1} L^{-1} v (Eq. (7)-(8)) by levels (Eq. (11), Alg. 3); the
-// intermediate vector lives in LDS. Ends with a barrier.
+__device__ __forceinline__ unsigned long long lds_load_bits(const double *p) {
+    return __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One triangle in level order: wavefront w takes chunks w, w + 16, ... (each at
+// most 64 rows of one level); a row waits in LDS for each dependency to leave the
+// sentinel. Every dependency lies in an earlier chunk, so the lowest unfinished
+// chunk can always proceed. Lower: dst = L^{-1} src (src in global memory, unit
+// diagonal). Upper: dst = U^{-1} src (src in LDS), also stored to out.
+template <class VT, bool UPPER>
+__device__ void b_tri(const BatchSys &S, const double *src, double *dst, double *out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nch = UPPER ? S.nchU : S.nchL, K = UPPER ? S.KU : S.KL, ldq = S.ldq;
+    const int32_t *ch = UPPER ? S.chU : S.chL, *rowp = UPPER ? S.rowU : S.rowL, *colp = UPPER ? S.colU : S.colL;
+    const VT *valp = fval<VT>(S, UPPER);
+    for (int c = wave; c < nch; c += kBW) {
+        const int q = ch[c] + lane;
+        if (q >= ch[c + 1]) continue;
+        const int row = rowp[q];
+        double acc = src[row];
+        for (int s0 = 0; s0 < K; s0 += 8) {
+            int j[8];
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int s = s0 + u;
+                j[u] = s < K ? colp[(size_t)s * ldq + q] : INT_MIN;
+                a[u] = j[u] >= 0 ? (double)valp[(size_t)s * ldq + q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j[u] < 0) continue;
+                unsigned long long bits = lds_load_bits(dst + j[u]);
+                while (bits == kSent) {
+                    __builtin_amdgcn_s_sleep(1);
+                    bits = lds_load_bits(dst + j[u]);
+                }
+                acc -= a[u] * __longlong_as_double((long long)bits);
+            }
+        }
+        if constexpr (UPPER) acc = acc / (double)fpiv<VT>(S)[q];
+        unsigned long long r = (unsigned long long)__double_as_longlong(acc);
+        if (r == kSent) r = kQNaN;  // keep a final value distinguishable from "not ready"
+        if (out) out[row] = __longlong_as_double((long long)r);
+        __hip_atomic_store((unsigned long long *)(dst + row), r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// out = U^{-1} L^{-1} v (Eq. (7)-(8)). Ends with a barrier.
 template <class VT>
 __device__ void b_prec(const BatchSys &S, const double *v, double *out, const Lds &L) {
-    const VT *lu = luv<VT>(S);
-    double *ly = L.ly;
-    for (int l = 0; l < S.nlevL; ++l) {
-        for (int t = S.lvlL[l] + threadIdx.x; t < S.lvlL[l + 1]; t += kBT) {
-            const int i = S.permL[t];
-            double s = v[i];
-            for (int e = S.LUp[i]; e < S.diag[i]; ++e) s -= (double)lu[e] * ly[S.LUj[e]];
-            ly[i] = s;
-        }
-        __syncthreads();
+    const double sent = __longlong_as_double((long long)kSent);
+    for (int i = threadIdx.x; i < S.n; i += kBT) {
+        L.ly[i] = sent;
+        L.lz[i] = sent;
     }
-    for (int l = 0; l < S.nlevU; ++l) {
-        for (int t = S.lvlU[l] + threadIdx.x; t < S.lvlU[l + 1]; t += kBT) {
-            const int i = S.permU[t];
-            const int d = S.diag[i];
-            double s = ly[i];
-            for (int e = d + 1; e < S.LUp[i + 1]; ++e) s -= (double)lu[e] * ly[S.LUj[e]];
-            ly[i] = s / (double)lu[d];
-        }
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < S.n; i += kBT) out[i] = ly[i];
+    __syncthreads();
+    b_tri<VT, false>(S, v, L.ly, nullptr);
+    __syncthreads();
+    b_tri<VT, true>(S, L.ly, L.lz, out);
     __syncthreads();
 }
 
@@ -181,16 +231,33 @@ __device__ int b_cycle(const BatchSys &S, int m, int mcyc, double tol, const dou
         b_spmv<VT>(S, zj, w, nullptr);
         // classical Gram-Schmidt, twice: h = V^T w, w -= V h
         for (int pass = 0; pass < 2; ++pass) {
-            double p[kBMaxM + 1];
+            // the thread's rows of w in registers; one wavefront sum per basis vector
+            double wr[kRows];
 #pragma unroll
-            for (int k = 0; k <= kBMaxM; ++k) p[k] = 0.0;
-            for (int i = threadIdx.x; i < n; i += kBT) {
-                const double wi = w[i];
-#pragma unroll
-                for (int k = 0; k <= kBMaxM; ++k)
-                    if (k <= j) p[k] += V[(size_t)k * n + i] * wi;
+            for (int r = 0; r < kRows; ++r) {
+                const int i = threadIdx.x + r * kBT;
+                wr[r] = i < n ? w[i] : 0.0;
             }
-            block_sums<kBMaxM + 1>(p, j + 1, L, L.y);
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int k = 0; k <= j; ++k) {
+                const double *vk = V + (size_t)k * n;
+                double p = 0.0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const int i = threadIdx.x + r * kBT;
+                    if (i < n) p += vk[i] * wr[r];
+                }
+                p = wave_sum(p);
+                if (lane == 0) L.red[wave * kBRedStride + k] = p;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x <= j) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < kBW; ++q) t += L.red[q * kBRedStride + threadIdx.x];
+                L.y[threadIdx.x] = t;
+            }
+            __syncthreads();
             for (int i = threadIdx.x; i < n; i += kBT) {
                 double wi = w[i];
                 for (int k = 0; k <= j; ++k) wi -= V[(size_t)k * n + i] * L.y[k];
@@ -254,7 +321,8 @@ __global__ __launch_bounds__(kBT) void k_gmres_batch(const BatchHead *__restrict
     const int m = H.restart;
     Lds L;
     L.ly = (double *)bsmem;
-    L.red = L.ly + max_n;
+    L.lz = L.ly + max_n;
+    L.red = L.lz + max_n;
     L.H = L.red + kBW * kBRedStride;
     L.cs = L.H + (size_t)(m + 1) * m;
     L.sn = L.cs + m;
@@ -428,12 +496,12 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
             if (a->n > 0 && (!b[i] || !x[i])) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
             if (mixed && (!a->has_f32 || !f->has_f32))
                 fail(HEC_ERR_INVALID_ARG, "mixed precision needs HEC_KEEP_F32 on the matrix and the factor");
+            if (a->n > 0 && (l->lower.flat.nchunks == 0 || l->upper.flat.nchunks == 0))
+                fail(HEC_ERR_INVALID_ARG, "levels handle has no level-ordered copy (n above HEC_BATCH_MAX_N)");
             BatchSys &S = B->h_sys[i];
             S.n = a->n;
             S.K = a->K;
             S.ld = a->ld;
-            S.nlevL = l->lower.nlev;
-            S.nlevU = l->upper.nlev;
             S.has_rem = a->nnz_rem > 0;
             S.ell_col = a->ell_col.get();
             S.ell_val = a->ell_val.get();
@@ -442,15 +510,24 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
             S.rem_col = a->rem_col.get();
             S.rem_val = a->rem_val.get();
             S.rem_val32 = a->rem_val32.get();
-            S.LUp = f->LUp.get();
-            S.LUj = f->LUj.get();
-            S.diag = f->diag.get();
-            S.LUx = f->LUx.get();
-            S.LUx32 = f->LUx32.get();
-            S.lvlL = l->lower.dlevel_ptr.get();
-            S.permL = l->lower.dperm.get();
-            S.lvlU = l->upper.dlevel_ptr.get();
-            S.permU = l->upper.dperm.get();
+            const hec_flat &fl = l->lower.flat, &fu = l->upper.flat;
+            S.KL = fl.K;
+            S.KU = fu.K;
+            S.ldq = fl.ldq;
+            S.nchL = fl.nchunks;
+            S.nchU = fu.nchunks;
+            S.chL = fl.chunk_ptr.get();
+            S.rowL = fl.row.get();
+            S.colL = fl.col.get();
+            S.valL = fl.val.get();
+            S.valL32 = fl.val32.get();
+            S.chU = fu.chunk_ptr.get();
+            S.rowU = fu.row.get();
+            S.colU = fu.col.get();
+            S.valU = fu.val.get();
+            S.valU32 = fu.val32.get();
+            S.pivU = fu.piv.get();
+            S.pivU32 = fu.piv32.get();
             S.b = b[i];
             S.x = x[i];
             S.ws = B->d_ws + per * i;

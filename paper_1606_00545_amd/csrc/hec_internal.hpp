@@ -159,6 +159,17 @@ struct hec_ilu_s {
     hec::DevBuf<float> LUx32;
 };
 
+// Level-ordered copy of one triangle for the batched small-system solver:
+// positions in Alg. 3 order cut into chunks of at most 64 rows of one level;
+// entry s of position q at s*ldq + q holds the dependency's row (INT_MIN pad)
+// and its value; piv: u_ii per position (upper only).
+struct hec_flat {
+    int32_t K = 0, ldq = 0, nchunks = 0;
+    hec::DevBuf<int32_t> chunk_ptr, row, col;
+    hec::DevBuf<double> val, piv;
+    hec::DevBuf<float> val32, piv32;
+};
+
 // One triangle of the factor with its level schedule (Eq. (11), Alg. 3) and
 // the blocked execution plan of the triangular solve: rows are cut into parts
 // (contiguous row ranges in the order the triangle is solved), each part's rows
@@ -168,7 +179,7 @@ struct hec_ilu_s {
 struct hec_tri {
     int32_t nlev = 0;
     std::vector<int32_t> hlevel_ptr, hperm;  // Alg. 3: level start pointers, rows by (level, row)
-    hec::DevBuf<int32_t> dlevel_ptr, dperm;  // device copies (used by the batched small-system solver)
+    hec_flat flat;                           // small systems only: level-ordered copy for the batched solver
     int32_t K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 0, S = 0;  // KC: K padded to 4/8/16/32
     int32_t D64 = 0, D32 = 0;                // ring depths for the FP64 / FP32 solve
     bool blocked = true;                     // false: rows too long for LDS slots, per-row polling kernel
@@ -213,5 +224,8 @@ void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipSt
 // Builds the level schedule and blocked solve plan of one triangle of M (the
 // upper plan must be built first: the lower plan records positions in it).
 void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *upper_plan, hipStream_t s);
+
+// Builds tri.flat (level-ordered copy for the batched solver) for one triangle of M.
+void build_flat(const hec_ilu_s &M, bool upper, hec_tri &tri, hipStream_t s);
 
 }  // namespace hec

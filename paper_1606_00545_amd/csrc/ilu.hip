@@ -229,6 +229,10 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         lv->n = M->n;
         build_tri(*M, true, lv->upper, nullptr, s);
         build_tri(*M, false, lv->lower, &lv->upper, s);
+        if (M->n <= HEC_BATCH_MAX_N) {  // small enough for the batched solver
+            build_flat(*M, false, lv->lower, s);
+            build_flat(*M, true, lv->upper, s);
+        }
         lv->sync.alloc(4);
         HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, 4 * sizeof(uint32_t), s));
         lv->y64.alloc(M->n);

@@ -156,6 +156,7 @@ inline void detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t
 //  * D64/D32: LDS ring depth for the FP64/FP32 solves; 0 when the plan does not
 //    fit in LDS (more than 32 entries per row): then blocked == false and the
 //    solve polls every dependency (level-order positions in 64-row chunks).
+//    flat == true asks for that level-order layout directly.
 struct HostPlan {
     int32_t n = 0, nlev = 0, K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 64, S = 0, D64 = 0, D32 = 0;
     bool blocked = false;
@@ -166,7 +167,8 @@ struct HostPlan {
 };
 
 inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
-                      int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P) {
+                      int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P,
+                      bool flat = false) {
     P = HostPlan();
     P.n = n;
     P.nlev = compute_levels(n, LUp, LUj, diag, upper, P.level_ptr, P.perm, &P.lev);
@@ -181,100 +183,102 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
         b = upper ? LUp[i + 1] : diag[i];
     };
 
-    int64_t R = std::max<int64_t>(kMinPartRows, (n + kTargetParts - 1) / kTargetParts);
-    R = std::min<int64_t>(R, n);
     std::vector<int32_t> &part_of = P.part_of, &pos = P.pos, &grow = P.grow;
     part_of.assign(n, 0);
     pos.assign(n, 0);
     grow.assign(n, 0);
-    bool tiled = false;
-    int32_t ntiles = 0;
-    if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
-        const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
-        const int64_t plane = (int64_t)gnx * gny;
-        int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
-        const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
-        const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
-        ntiles = PX * PY;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t xx = i % gnx, yy = (i / gnx) % gny;
-            int32_t t = xx / tx + PX * (yy / ty);
-            part_of[i] = upper ? ntiles - 1 - t : t;
+    if (!flat) {  // flat: level order only (the layout of the per-row polling solves)
+        int64_t R = std::max<int64_t>(kMinPartRows, (n + kTargetParts - 1) / kTargetParts);
+        R = std::min<int64_t>(R, n);
+        bool tiled = false;
+        int32_t ntiles = 0;
+        if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
+            const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
+            const int64_t plane = (int64_t)gnx * gny;
+            int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
+            const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
+            const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
+            ntiles = PX * PY;
+            for (int32_t i = 0; i < n; ++i) {
+                int32_t xx = i % gnx, yy = (i / gnx) % gny;
+                int32_t t = xx / tx + PX * (yy / ty);
+                part_of[i] = upper ? ntiles - 1 - t : t;
+            }
+            tiled = ntiles > 1;
+            for (int32_t i = 0; i < n && tiled; ++i) {
+                int32_t a, b;
+                deps(i, a, b);
+                for (int32_t e = a; e < b; ++e)
+                    if (part_of[LUj[e]] > part_of[i]) {
+                        tiled = false;
+                        break;
+                    }
+            }
         }
-        tiled = ntiles > 1;
-        for (int32_t i = 0; i < n && tiled; ++i) {
-            int32_t a, b;
-            deps(i, a, b);
-            for (int32_t e = a; e < b; ++e)
-                if (part_of[LUj[e]] > part_of[i]) {
-                    tiled = false;
-                    break;
+        for (;;) {
+            int32_t nparts;
+            if (tiled) {
+                nparts = ntiles;
+            } else {
+                nparts = (int32_t)((n + R - 1) / R);
+                for (int32_t i = 0; i < n; ++i) part_of[i] = (int32_t)((upper ? (int64_t)(n - 1 - i) : (int64_t)i) / R);
+            }
+            P.part_pos.assign(nparts + 1, 0);
+            for (int32_t i = 0; i < n; ++i) P.part_pos[part_of[i] + 1]++;
+            for (int32_t p = 0; p < nparts; ++p) P.part_pos[p + 1] += P.part_pos[p];
+            std::vector<int32_t> fillp(P.part_pos.begin(), P.part_pos.end() - 1);
+            for (int32_t t = 0; t < n; ++t) {
+                int32_t i = P.perm[t];
+                int32_t q = fillp[part_of[i]]++;
+                pos[i] = q;
+                grow[q] = i;
+            }
+            P.part_ss.assign(nparts + 1, 0);
+            P.ss_pos.clear();
+            for (int32_t p = 0; p < nparts; ++p) {
+                P.part_ss[p] = (int32_t)P.ss_pos.size();
+                int32_t q = P.part_pos[p];
+                while (q < P.part_pos[p + 1]) {
+                    P.ss_pos.push_back(q);
+                    int32_t l = P.lev[grow[q]];
+                    int32_t e = q + 1;
+                    while (e < P.part_pos[p + 1] && e - q < kSub && P.lev[grow[e]] == l) ++e;
+                    q = e;
                 }
+            }
+            P.part_ss[nparts] = (int32_t)P.ss_pos.size();
+            P.ss_pos.push_back(n);
+            int64_t maxd = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                int32_t a, b;
+                deps(i, a, b);
+                for (int32_t e = a; e < b; ++e) {
+                    int32_t j = LUj[e];
+                    if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, (int64_t)pos[i] - pos[j]);
+                }
+            }
+            P.W = 64;
+            while (P.W < maxd + kSub) P.W *= 2;
+            P.S = 0;
+            for (int32_t p = 0; p < nparts; ++p) P.S = std::max(P.S, P.part_ss[p + 1] - P.part_ss[p]);
+            auto fit = [&](auto tag) {
+                using T = decltype(tag);
+                int best = 0;
+                for (int D = 4; D <= kMaxRing; ++D) {
+                    size_t bb = upper ? lds_bytes<T, true>(P.KC, P.W, D, P.S) : lds_bytes<T, false>(P.KC, P.W, D, P.S);
+                    if ((int64_t)bb <= lds_max) best = D;
+                }
+                return best;
+            };
+            P.D64 = fit(double());
+            P.D32 = has_f32 ? fit(float()) : 4;
+            P.nparts = nparts;
+            if ((P.D64 >= 4 && P.D32 >= 4) || R <= kSub || K > 32) break;
+            tiled = false;                       // fall back to (smaller) contiguous parts
+            R = std::max<int64_t>(kSub, R / 2);  // a smaller part keeps the ring of results smaller
         }
+        P.blocked = P.D64 >= 4 && P.D32 >= 4 && K <= 32;
     }
-    for (;;) {
-        int32_t nparts;
-        if (tiled) {
-            nparts = ntiles;
-        } else {
-            nparts = (int32_t)((n + R - 1) / R);
-            for (int32_t i = 0; i < n; ++i) part_of[i] = (int32_t)((upper ? (int64_t)(n - 1 - i) : (int64_t)i) / R);
-        }
-        P.part_pos.assign(nparts + 1, 0);
-        for (int32_t i = 0; i < n; ++i) P.part_pos[part_of[i] + 1]++;
-        for (int32_t p = 0; p < nparts; ++p) P.part_pos[p + 1] += P.part_pos[p];
-        std::vector<int32_t> fillp(P.part_pos.begin(), P.part_pos.end() - 1);
-        for (int32_t t = 0; t < n; ++t) {
-            int32_t i = P.perm[t];
-            int32_t q = fillp[part_of[i]]++;
-            pos[i] = q;
-            grow[q] = i;
-        }
-        P.part_ss.assign(nparts + 1, 0);
-        P.ss_pos.clear();
-        for (int32_t p = 0; p < nparts; ++p) {
-            P.part_ss[p] = (int32_t)P.ss_pos.size();
-            int32_t q = P.part_pos[p];
-            while (q < P.part_pos[p + 1]) {
-                P.ss_pos.push_back(q);
-                int32_t l = P.lev[grow[q]];
-                int32_t e = q + 1;
-                while (e < P.part_pos[p + 1] && e - q < kSub && P.lev[grow[e]] == l) ++e;
-                q = e;
-            }
-        }
-        P.part_ss[nparts] = (int32_t)P.ss_pos.size();
-        P.ss_pos.push_back(n);
-        int64_t maxd = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t a, b;
-            deps(i, a, b);
-            for (int32_t e = a; e < b; ++e) {
-                int32_t j = LUj[e];
-                if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, (int64_t)pos[i] - pos[j]);
-            }
-        }
-        P.W = 64;
-        while (P.W < maxd + kSub) P.W *= 2;
-        P.S = 0;
-        for (int32_t p = 0; p < nparts; ++p) P.S = std::max(P.S, P.part_ss[p + 1] - P.part_ss[p]);
-        auto fit = [&](auto tag) {
-            using T = decltype(tag);
-            int best = 0;
-            for (int D = 4; D <= kMaxRing; ++D) {
-                size_t bb = upper ? lds_bytes<T, true>(P.KC, P.W, D, P.S) : lds_bytes<T, false>(P.KC, P.W, D, P.S);
-                if ((int64_t)bb <= lds_max) best = D;
-            }
-            return best;
-        };
-        P.D64 = fit(double());
-        P.D32 = has_f32 ? fit(float()) : 4;
-        P.nparts = nparts;
-        if ((P.D64 >= 4 && P.D32 >= 4) || R <= kSub || K > 32) break;
-        tiled = false;                       // fall back to (smaller) contiguous parts
-        R = std::max<int64_t>(kSub, R / 2);  // a smaller part keeps the ring of results smaller
-    }
-    P.blocked = P.D64 >= 4 && P.D32 >= 4 && K <= 32;
     if (!P.blocked) {
         for (int32_t t = 0; t < n; ++t) {
             grow[t] = P.perm[t];

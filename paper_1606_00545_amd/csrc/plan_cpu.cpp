@@ -14,13 +14,14 @@ extern "C" {
 // Builds the plan of the strict lower (upper == 0) or strict upper triangle of
 // the factor pattern (LUp, LUj, diag: row pointers, columns, diagonal
 // positions; 0-based) with the grid sizes detected from A (all 0: none) and
-// lds_max bytes of LDS per workgroup. Returns NULL on allocation failure.
+// lds_max bytes of LDS per workgroup; flat != 0 asks for the level-order layout.
+// Returns NULL on allocation failure.
 void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
-                   int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max) {
+                   int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max, int32_t flat) {
     HostPlan *P = new (std::nothrow) HostPlan();
     if (!P) return nullptr;
     try {
-        hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P);
+        hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P, flat != 0);
     } catch (...) {
         delete P;
         return nullptr;

@@ -524,11 +524,6 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     plan::make_plan(n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, M.has_f32,
                     max_lds_per_block() - 256, P);
     tri.nlev = P.nlev;
-    tri.dlevel_ptr.alloc(P.level_ptr.size());
-    tri.dlevel_ptr.upload(P.level_ptr.data(), P.level_ptr.size(), s);
-    tri.dperm.alloc(P.perm.size());
-    tri.dperm.upload(P.perm.data(), P.perm.size(), s);
-    HEC_HIP(hipStreamSynchronize(s));  // the host arrays move below
     tri.hlevel_ptr = std::move(P.level_ptr);
     tri.hperm = std::move(P.perm);
     tri.K = P.K;
@@ -589,6 +584,42 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     }
     HEC_HIP(hipStreamSynchronize(s));
     tri.hgrow = std::move(P.grow);
+}
+
+void build_flat(const hec_ilu_s &M, bool upper, hec_tri &tri, hipStream_t s) {
+    const int32_t n = M.n;
+    plan::HostPlan P;
+    plan::make_plan(n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), 0, 0, 0, upper, M.has_f32, 0, P, true);
+    hec_flat &f = tri.flat;
+    f.K = P.K;
+    f.ldq = P.ldq;
+    f.nchunks = n ? (int32_t)P.chunks.size() - 1 : 0;
+    if (n == 0) return;
+    f.chunk_ptr.alloc(P.chunks.size());
+    f.chunk_ptr.upload(P.chunks.data(), P.chunks.size(), s);
+    f.row.alloc(n);
+    f.row.upload(P.grow.data(), n, s);
+    const size_t slab = (size_t)P.K * P.ldq;
+    f.col.alloc(slab);
+    f.col.upload(P.enc.data(), slab, s);
+    f.val.alloc(slab);
+    if (M.has_f32) f.val32.alloc(slab);
+    DevBuf<int32_t> dsrc(slab);
+    if (slab) {
+        dsrc.upload(P.src.data(), slab, s);
+        k_gather<<<ceil_div(slab, 256), 256, 0, s>>>(slab, dsrc.get(), M.LUx.get(), f.val.get(), f.val32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    DevBuf<int32_t> dp;
+    if (upper) {
+        f.piv.alloc(P.ldq);
+        if (M.has_f32) f.piv32.alloc(P.ldq);
+        dp.alloc(P.ldq);
+        dp.upload(P.psrc.data(), P.ldq, s);
+        k_gather<<<ceil_div(P.ldq, 256), 256, 0, s>>>(P.ldq, dp.get(), M.LUx.get(), f.piv.get(), f.piv32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    HEC_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace hec

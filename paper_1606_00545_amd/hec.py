@@ -27,7 +27,7 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched", "hec_last_error")
-BATCH_MAX_N = 16384
+BATCH_MAX_N = 8192
 
 
 class HecError(RuntimeError):

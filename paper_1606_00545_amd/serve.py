@@ -11,9 +11,18 @@ the device, and the host side of one request's setup (symbolic ILU, level
 schedules) runs while others compute, since every library call releases the
 Python interpreter lock.
 
+Small systems (n <= batch_max_n, when batching is on) take another route: a
+slot prepares the system (HEC matrix, factor, level schedules, right-hand side)
+and hands it to the batcher, which solves every prepared small system waiting at
+that moment (up to the batch capacity, after waiting at most batch_wait for more
+to arrive) in one persistent launch replayed from a hipGraph
+(gmres_solve_batched), one workgroup per system. The slot is free again as soon
+as it has handed the system over.
+
 Each result is independent of what else is in flight: every kernel's reduction
-order depends only on the request's own size, so a request solved alone and in
-a mix gives bit-identical solutions.
+order depends only on the request's own size, and a batched system is solved by
+its own workgroup, so a request solved alone and in a mix gives bit-identical
+solutions (on the same route).
 
 Latency of a request = time from its arrival to its solution in host memory.
 """
@@ -82,6 +91,9 @@ class Server:
     slots: int = 8
     mem_budget: int = 64 << 30
     restart: int = 30
+    batch_max_n: int = 0          # 0: no batching; else systems with n <= batch_max_n are batched
+    batch_capacity: int = 256     # systems per batched launch
+    batch_wait: float = 0.002     # seconds the batcher waits for more systems once one is ready
     results: list = field(default_factory=list)
 
     def __post_init__(self):
@@ -90,8 +102,12 @@ class Server:
         self._free_mem = self.mem_budget
         self._inflight = 0
         self._closed = False
+        self._batchq: deque = deque()   # prepared small systems, in hand-over order
+        self._workers_done = False
+        self._streams: list = []        # kept alive until every handle made on them is destroyed
         self.peak_mem = 0
         self.peak_inflight = 0
+        self.batches: list = []         # sizes of the batched launches
         self.errors: list = []
 
     # ------------------------------------------------------------ admission
@@ -135,12 +151,17 @@ class Server:
     def _worker(self, slot: int, t0: float):
         import torch
         stream = torch.cuda.Stream()
+        with self._cv:
+            self._streams.append(stream)
         while True:
             item = self._admit()
             if item is None:
                 return
             req, fp = item
             t_adm = time.perf_counter() - t0
+            if self.batch_max_n and req.A.n <= self.batch_max_n:
+                self._prepare_small(req, fp, t_adm, slot, stream)
+                continue
             try:
                 with torch.cuda.stream(stream):
                     keep = req.precision == 1
@@ -166,11 +187,91 @@ class Server:
             finally:
                 self._release(fp)
 
+    # ------------------------------------------------------------ small systems
+    def _prepare_small(self, req, fp, t_adm, slot, stream):
+        import torch
+        try:
+            with torch.cuda.stream(stream):
+                keep = req.precision == 1
+                M = hec.hec_from_csr(req.A, keep_f32=keep, stream=stream)
+                F = hec.ilu_factor(req.A, k=0, keep_f32=keep, stream=stream)
+                lv = hec.level_schedule(F, stream=stream)
+                bd = torch.from_numpy(req.b).to("cuda", non_blocking=False)
+                x = torch.empty_like(bd)
+                stream.synchronize()
+        except Exception as e:
+            with self._cv:
+                self.errors.append((req.rid, repr(e)))
+            self._release(fp)
+            return
+        with self._cv:
+            self._batchq.append((req, fp, t_adm, slot, M, F, lv, bd, x))
+            self._cv.notify_all()
+
+    def _take_batch(self):
+        """Blocks for the next group of prepared systems with one (precision, rtol)."""
+        with self._cv:
+            while not self._batchq:
+                if self._workers_done:
+                    return None
+                self._cv.wait()
+            deadline = time.perf_counter() + self.batch_wait
+            while len(self._batchq) < self.batch_capacity and not self._workers_done:
+                left = deadline - time.perf_counter()
+                if left <= 0:
+                    break
+                self._cv.wait(left)
+            key = (self._batchq[0][0].precision, self._batchq[0][0].rtol)
+            group, rest = [], deque()
+            while self._batchq:
+                it = self._batchq.popleft()
+                if len(group) < self.batch_capacity and (it[0].precision, it[0].rtol) == key:
+                    group.append(it)
+                else:
+                    rest.append(it)
+            self._batchq = rest
+            return group
+
+    def _batcher(self, t0: float):
+        contexts = {}
+        while True:
+            group = self._take_batch()
+            if group is None:
+                break
+            prec, rtol = group[0][0].precision, group[0][0].rtol
+            try:
+                if prec not in contexts:
+                    contexts[prec] = hec.Batch(self.batch_capacity, self.restart, self.batch_max_n)
+                infos = hec.gmres_solve_batched(contexts[prec], [(it[4], it[5], it[6], it[7], it[8]) for it in group],
+                                                rtol=rtol, precision=prec, check=False)
+                xs = [it[8].cpu().numpy() for it in group]
+                t_done = time.perf_counter() - t0
+                with self._cv:
+                    self.batches.append(len(group))
+                    for it, info, xh in zip(group, infos, xs):
+                        req, fp, t_adm, slot = it[:4]
+                        self.results.append(Result(req.rid, xh, info, req.A.n, fp, req.arrival, t_adm, t_done, slot))
+            except Exception as e:
+                with self._cv:
+                    for it in group:
+                        self.errors.append((it[0].rid, repr(e)))
+            finally:
+                for it in group:
+                    for h in (it[6], it[5], it[4]):
+                        h.close()
+                    self._release(it[1])
+        for B in contexts.values():
+            B.close()
+
     def run(self, source, t0: float | None = None):
         """Serve requests from ``source`` (an iterable of Request, in arrival order):
         each is submitted when its arrival time is reached. Returns the results."""
         t0 = time.perf_counter() if t0 is None else t0
         workers = [threading.Thread(target=self._worker, args=(s, t0), daemon=True) for s in range(self.slots)]
+        batcher = None
+        if self.batch_max_n:
+            batcher = threading.Thread(target=self._batcher, args=(t0,), daemon=True)
+            batcher.start()
         for w in workers:
             w.start()
         for req in source:
@@ -181,6 +282,11 @@ class Server:
         self.close()
         for w in workers:
             w.join()
+        with self._cv:
+            self._workers_done = True
+            self._cv.notify_all()
+        if batcher is not None:
+            batcher.join()
         return self.results
 
 

@@ -25,7 +25,7 @@ def _systems():
         ("tpfa3d_12x11x10_k1", synth.lognormal_tpfa((12, 11, 10), 1.5, np.random.default_rng(32)), 1),
         ("tpfa3d_20_k0", synth.lognormal_tpfa((20, 20, 20), 2.0, np.random.default_rng(33)), 0),
         ("powerlaw_3000", synth.powerlaw_random(3000, np.random.default_rng(34), lmax=64), 0),
-        ("tpfa2d_127x129", synth.lognormal_tpfa((127, 129), 1.0, np.random.default_rng(35)), 0),
+        ("tpfa2d_90x91", synth.lognormal_tpfa((90, 91), 1.0, np.random.default_rng(35)), 0),
         ("single", synth.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])), 0),
     ]
     return out
@@ -56,7 +56,7 @@ def _rel_res(A, x, b):
 
 
 def test_batch_fp64_matches_oracle(prepared):
-    B = hec.Batch(len(prepared), restart=30, max_n=16384)
+    B = hec.Batch(len(prepared), restart=30, max_n=8192)
     xs, infos = _solve(B, prepared)
     for it, x, inf in zip(prepared, xs, infos):
         A, b = it["A"], it["b"]
@@ -74,8 +74,8 @@ def test_batch_fp64_matches_oracle(prepared):
 
 def test_batch_independent_of_composition_and_graph(prepared):
     import torch
-    full = hec.Batch(len(prepared), restart=30, max_n=16384, use_graph=True)
-    eager = hec.Batch(len(prepared), restart=30, max_n=16384, use_graph=False)
+    full = hec.Batch(len(prepared), restart=30, max_n=8192, use_graph=True)
+    eager = hec.Batch(len(prepared), restart=30, max_n=8192, use_graph=False)
     ref, _ = _solve(eager, prepared)
     # graph replays: the whole batch, reversed subsets, single systems, with other work between replays
     orders = [list(range(len(prepared))), list(range(len(prepared)))[::-1], [3, 1], [5], [0, 2, 4, 6, 7]]
@@ -87,7 +87,7 @@ def test_batch_independent_of_composition_and_graph(prepared):
             assert np.array_equal(x.view(np.uint64), ref[i].view(np.uint64)), (rep, prepared[i]["name"])
         torch.cuda.synchronize()
     # alone, in a context sized for one system
-    one = hec.Batch(1, restart=30, max_n=16384)
+    one = hec.Batch(1, restart=30, max_n=8192)
     for i in (1, 5):
         xs, _ = _solve(one, [prepared[i]])
         assert np.array_equal(xs[0].view(np.uint64), ref[i].view(np.uint64))
@@ -96,7 +96,7 @@ def test_batch_independent_of_composition_and_graph(prepared):
 
 
 def test_batch_mixed_precision_reaches_tolerance(prepared):
-    B = hec.Batch(len(prepared), restart=30, max_n=16384)
+    B = hec.Batch(len(prepared), restart=30, max_n=8192)
     xs, infos = _solve(B, prepared, precision=1)
     for it, x, inf in zip(prepared, xs, infos):
         rr = _rel_res(it["A"], x, it["b"])

@@ -1,4 +1,5 @@
-"""GPU serving: continuous batching over streams with memory admission.
+"""GPU serving: continuous batching over streams with memory admission, and the
+batched persistent launch for small systems.
 
 Every request's result must be the same alone and in a mix (bitwise: all
 reductions have a fixed order that depends only on the request's own size),
@@ -73,3 +74,26 @@ def test_arrivals_over_time_and_latency():
         assert x.admitted >= x.arrival - 1e-3 and x.done >= x.admitted and x.latency > 0
     st = serve.latency_stats(res)
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_batched_route_identical_alone_and_in_the_mix():
+    """Small systems go to the batched launch; large ones keep their own streams."""
+    reqs = _requests(precisions=(0, 1))
+    small = [r for r in reqs if r.A.n <= 4096]
+    assert 2 <= len(small) < len(reqs)
+    alone = {}
+    for r in reqs:
+        srv = serve.Server(slots=1, batch_max_n=4096, batch_capacity=8)
+        res = srv.run([r])
+        assert len(res) == 1 and not srv.errors
+        assert len(srv.batches) == (1 if r.A.n <= 4096 else 0)
+        alone[r.rid] = res[0].x
+    srv = serve.Server(slots=6, batch_max_n=4096, batch_capacity=8, batch_wait=0.05)
+    got = {res.rid: res for res in srv.run(reqs)}
+    assert not srv.errors and len(got) == len(reqs)
+    assert max(srv.batches) > 1  # several small systems shared a launch
+    for r in reqs:
+        g = got[r.rid]
+        assert g.info["status"] == 0
+        assert np.array_equal(g.x.view(np.uint64), alone[r.rid].view(np.uint64)), r.rid
+        assert _rel_res(r.A, g.x, r.b) <= 1e-8

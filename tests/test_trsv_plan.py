@@ -59,6 +59,10 @@ def _cases():
     yield "tridiag_1000_k0", lambda: synth.CSR(*_tridiag(1000)), 0, {}
     yield "diagonal_300", lambda: synth.CSR(*_diagonal(300)), 0, {}
     yield "single_row", lambda: synth.CSR(*_diagonal(1)), 0, {}
+    yield "flat_tpfa3d_k1", lambda: synth.lognormal_tpfa((17, 13, 11), 2.0, np.random.default_rng(2)), 1, \
+        {"flat": True, "blocked": False}
+    yield "flat_powerlaw_3000", lambda: synth.powerlaw_random(3000, np.random.default_rng(34), lmax=64), 0, \
+        {"flat": True, "blocked": False}
 
 
 def _tridiag(n):
@@ -226,7 +230,7 @@ def test_plan_structure_and_replay(factors, name):
     y_o = O.trsv_lower(F, b)
     x_o = O.trsv_upper(F, y_o)
     for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
-        P = _plan.make_plan(F, upper, grid, lds_max=lds_max)
+        P = _plan.make_plan(F, upper, grid, lds_max=lds_max, flat=opt.get("flat", False))
         o = O.level_schedule(F.n, F.LUp, F.LUj, "upper" if upper else "lower")
         assert P["nlev"] == o.nlev
         assert np.array_equal(P["level_ptr"], o.level_ptr) and np.array_equal(P["perm"], o.perm)
