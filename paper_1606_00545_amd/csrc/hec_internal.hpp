@@ -203,8 +203,8 @@ struct hec_levels_s {
     int32_t n = 0;
     hec_tri lower, upper;
     hec::DevBuf<uint32_t> sync;            // part tickets + finished-workgroup counters
-    hec::DevBuf<double> y64, bp64, yp64;   // y = L^{-1} b (by row), b in lower order, y in upper order
-    hec::DevBuf<float> y32, bp32, yp32;
+    hec::DevBuf<double> y64, yp64;   // y = L^{-1} b by row (sentinel-filled between solves), y in upper order
+    hec::DevBuf<float> y32, yp32;
 };
 
 namespace hec {
@@ -220,6 +220,9 @@ void spmv_launch(const hec_matrix_s &A, double alpha, const XT *x, double beta, 
 template <class T>
 void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s,
                  const int32_t *skip = nullptr);
+
+// Sets the internal lower-solve outputs of lv to the sentinel (once, after allocation).
+void trsv_init_levels(hec_levels_s &lv, hipStream_t s);
 
 // Builds the level schedule and blocked solve plan of one triangle of M (the
 // upper plan must be built first: the lower plan records positions in it).

@@ -236,13 +236,12 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         lv->sync.alloc(4);
         HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, 4 * sizeof(uint32_t), s));
         lv->y64.alloc(M->n);
-        lv->bp64.alloc(M->n);
         lv->yp64.alloc(M->n);
         if (M->has_f32) {
             lv->y32.alloc(M->n);
-            lv->bp32.alloc(M->n);
             lv->yp32.alloc(M->n);
         }
+        trsv_init_levels(*lv, s);
         HEC_HIP(hipStreamSynchronize(s));
         *out = lv.release();
     });

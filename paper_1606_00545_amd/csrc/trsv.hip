@@ -2,11 +2,11 @@
 // launch per triangle in which rows of successive levels are solved inside a
 // workgroup with their dependencies held in LDS.
 //
-// Plan (built once per factor on the host, see build_tri):
-//  * the rows are cut into parts: contiguous row ranges in the order the
-//    triangle is solved (ascending rows for L, descending for U). Every
-//    dependency of a row lies in its own part or in an earlier part, so the
-//    parts form a chain that can be claimed in order from a ticket counter:
+// Plan (built once per factor on the host by plan.hpp's make_plan):
+//  * the rows are cut into parts: x-y tiles spanning all z for a recognised
+//    grid stencil, otherwise contiguous row ranges, numbered in the order the
+//    triangle is solved. Every dependency of a row lies in its own part or in an
+//    earlier part, so the parts can be claimed in order from a ticket counter:
 //    a part only ever waits for parts already claimed by running workgroups,
 //    hence no deadlock at any occupancy or grid size;
 //  * inside a part the rows are laid out by (level, row) (Alg. 3's order) and
@@ -15,9 +15,9 @@
 // Execution (k_trsv_blk): one workgroup per part, 1 solver wavefront and 15
 // prefetching wavefronts.
 //  * Prefetchers stream the next sub-segments into a ring of LDS slots: the
-//    right-hand side (already gathered into position order), the row's
-//    entries, and the values of dependencies in earlier parts, polled from
-//    global memory until final;
+//    right-hand side (gathered by row, or read in plan order for the upper
+//    solve of an L-then-U chain), the row's entries, and the values of
+//    dependencies in earlier parts, polled from global memory until final;
 //  * the solver takes sub-segments in order, reads dependencies inside the part
 //    from a small LDS ring of recent results and dependencies outside it from
 //    the slot, and publishes each result to global memory. It never waits on
@@ -26,7 +26,9 @@
 //    is pre-filled with a signalling-NaN bit pattern that arithmetic never
 //    produces; results are stored and polled with device-coherent (agent
 //    scope) accesses, so only single-location coherence is needed and no
-//    cache-wide fence is issued.
+//    cache-wide fence is issued. In an L-then-U chain the lower launch fills
+//    the upper solve's output and the upper launch refills the lower solve's
+//    internal output for the next chain, so the chain is exactly two launches.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -86,6 +88,28 @@ __device__ __forceinline__ T from_bits(typename Sentinel<T>::U u) {
     return v;
 }
 
+// Vectors of one triangular solve. b: right-hand side, by row (b_by_row) or
+// already in plan order; x: output by row (pre-filled with the sentinel);
+// yother: optional copy of the output in the other triangle's plan order;
+// fill: a vector of nfill elements the kernel sets to the sentinel for the
+// next solve (the output of the other triangle of an L-then-U chain).
+template <class T>
+struct SolveIO {
+    const T *b;
+    int32_t b_by_row;
+    T *x, *yother, *fill;
+    int64_t nfill;
+};
+
+// Sets io.fill to the sentinel: a grid-stride loop at kernel start.
+template <class T>
+__device__ __forceinline__ void fill_sentinel(const SolveIO<T> &io) {
+    if (!io.fill) return;
+    const T s = from_bits<T>(Sentinel<T>::bits);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < io.nfill; i += (int64_t)gridDim.x * blockDim.x)
+        io.fill[i] = s;
+}
+
 struct PlanArgs {
     int32_t nparts, K, ldq, W, D, S;  // S: most sub-segments in one part
     const int32_t *part_ss, *part_pos, *ss_pos, *grow, *other, *enc;
@@ -101,11 +125,14 @@ template <> __device__ __forceinline__ const float *zero_addr<float>() { return 
 
 template <class T, bool UPPER, int KC>
 __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *__restrict__ val,
-                                                          const T *__restrict__ piv, const T *__restrict__ bperm,
-                                                          T *x, T *yother, uint32_t *sync, const int32_t *skip) {
+                                                          const T *__restrict__ piv, SolveIO<T> io,
+                                                          uint32_t *sync, const int32_t *skip) {
     using U = typename Sentinel<T>::U;
     constexpr U SENT = Sentinel<T>::bits;
     if (skip && *skip) return;  // uniform: no workgroup touches the counters
+    fill_sentinel(io);
+    T *const x = io.x;
+    T *const yother = io.yother;
     extern __shared__ __align__(16) char smem[];
     const int D = P.D, K = P.K, W = P.W;
     int *filled = (int *)smem;
@@ -259,8 +286,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 char *sl = smem + so;
                 const bool live = lane < cnt;
                 const int q = q0 + (live ? lane : 0);
-                T bb = live ? bperm[q] : (T)0;
                 int gi = live ? P.grow[q] : 0;
+                T bb = live ? io.b[io.b_by_row ? gi : q] : (T)0;
                 int po = live && P.other ? P.other[q] : 0;
                 T dd = (T)1;
                 if constexpr (UPPER) dd = live ? piv[q] : (T)1;
@@ -335,11 +362,13 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
                                                  int32_t ldq, const int32_t *__restrict__ grow,
                                                  const int32_t *__restrict__ other, const int32_t *__restrict__ enc,
                                                  const T *__restrict__ val, const T *__restrict__ piv,
-                                                 const T *__restrict__ bperm, T *x, T *yother, uint32_t *sync,
-                                                 const int32_t *skip) {
+                                                 SolveIO<T> io, uint32_t *sync, const int32_t *skip) {
     using U = typename Sentinel<T>::U;
     constexpr U SENT = Sentinel<T>::bits;
     if (skip && *skip) return;
+    fill_sentinel(io);
+    T *const x = io.x;
+    T *const yother = io.yother;
     const int lane = threadIdx.x & 63;
     for (;;) {
         uint32_t t = 0;
@@ -348,7 +377,8 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
         if (t >= (uint32_t)nchunks) break;
         const int32_t q = chunk_ptr[t] + lane;
         if (q < chunk_ptr[t + 1]) {
-            T acc = bperm[q];
+            const int32_t gi = grow[q];
+            T acc = io.b[io.b_by_row ? gi : q];
             for (int32_t s0 = 0; s0 < K; s0 += kBatch) {
                 const int nb = min(kBatch, K - s0);
                 int es[kBatch];
@@ -383,7 +413,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
                     if (u < nb && es[u] != kPad) acc -= vs[u] * from_bits<T>(xs[u]);
             }
             if constexpr (UPPER) acc = acc / piv[q];
-            store_coherent(x + grow[q], acc);
+            store_coherent(x + gi, acc);
             if (yother) yother[other[q]] = acc;
         }
     }
@@ -397,19 +427,12 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
     }
 }
 
-// Before a solve: outputs filled with the sentinel, right-hand side gathered
-// into the plan's position order.
+// Before a single-triangle solve: the output filled with the sentinel.
 template <class T>
-__global__ __launch_bounds__(256) void k_trsv_prep(int64_t n, const int32_t *__restrict__ grow,
-                                                   const T *__restrict__ b, T *__restrict__ bperm, T *x1, T *x2,
-                                                   const int32_t *skip) {
+__global__ __launch_bounds__(256) void k_trsv_fill(int64_t n, T *x, const int32_t *skip) {
     if (skip && *skip) return;
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const T s = from_bits<T>(Sentinel<T>::bits);
-    bperm[q] = b[grow[q]];
-    x1[q] = s;
-    if (x2) x2[q] = s;
+    if (q < n) x[q] = from_bits<T>(Sentinel<T>::bits);
 }
 
 // dst[q] = src[map[q]] (0 where map[q] < 0), optional FP32 copy.
@@ -433,8 +456,8 @@ int max_lds_per_block() {
 }
 
 template <class T, bool UPPER>
-void launch_blk(const hec_tri &tri, uint32_t *sync, const T *bperm, T *x, T *yother, hipStream_t s,
-                const int32_t *skip) {
+void launch_blk(const hec_tri &tri, uint32_t *sync, const SolveIO<T> &io, hipStream_t s, const int32_t *skip) {
+    T *const yother = io.yother;
     if (tri.nparts == 0 && tri.nchunks == 0) return;
     const bool f64 = sizeof(T) == 8;
     if (!tri.blocked) {
@@ -443,7 +466,7 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, const T *bperm, T *x, T *yot
         int waves = std::min(tri.nchunks, 1024);
         k_trsv_sf<T, UPPER><<<(waves + 3) / 4, 256, 0, s>>>(tri.nchunks, tri.chunk_ptr.get(), tri.K, tri.ldq,
                                                           tri.grow.get(), yother ? tri.other.get() : nullptr,
-                                                          tri.enc.get(), val, piv, bperm, x, yother, sync, skip);
+                                                          tri.enc.get(), val, piv, io, sync, skip);
         HEC_CHECK_LAUNCH();
         return;
     }
@@ -468,7 +491,7 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, const T *bperm, T *x, T *yot
                                         hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_per_block()));
             attr_set = true;
         }
-        k_trsv_blk<T, UPPER, KC><<<grid, kBlkThreads, lds, s>>>(P, val, piv, bperm, x, yother, sync, skip);
+        k_trsv_blk<T, UPPER, KC><<<grid, kBlkThreads, lds, s>>>(P, val, piv, io, sync, skip);
     };
     switch (tri.KC) {
         case 4: go(std::integral_constant<int, 4>()); break;
@@ -485,31 +508,39 @@ template <class T>
 void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s, const int32_t *skip) {
     const int64_t n = lv.n;
     if (n == 0) return;
-    T *y, *bp, *yp;
+    T *y, *yp;
     if constexpr (sizeof(T) == 8) {
         y = lv.y64.get();
-        bp = lv.bp64.get();
         yp = lv.yp64.get();
     } else {
         y = lv.y32.get();
-        bp = lv.bp32.get();
         yp = lv.yp32.get();
     }
     uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
-    const unsigned g = ceil_div(n, 256);
     if (which == HEC_LU) {
-        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.lower.grow.get(), b, bp, y, x, skip);
+        // y (the lower solve's output) is sentinel-filled between calls: by
+        // level_schedule, then by every upper solve for the next call. The lower
+        // solve fills x for the upper one; no separate launch.
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, 1, y, yp, x, n}, s, skip);
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, 0, x, nullptr, y, n}, s, skip);
+        return;
+    }
+    k_trsv_fill<T><<<ceil_div(n, 256), 256, 0, s>>>(n, x, skip);
+    HEC_CHECK_LAUNCH();
+    if (which == HEC_LOWER)
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, 1, x, nullptr, nullptr, 0}, s, skip);
+    else
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{b, 1, x, nullptr, nullptr, 0}, s, skip);
+}
+
+void trsv_init_levels(hec_levels_s &lv, hipStream_t s) {
+    const int64_t n = lv.n;
+    if (n == 0) return;
+    k_trsv_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.y64.get(), nullptr);
+    HEC_CHECK_LAUNCH();
+    if (lv.y32.get()) {
+        k_trsv_fill<float><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.y32.get(), nullptr);
         HEC_CHECK_LAUNCH();
-        launch_blk<T, false>(lv.lower, sync, bp, y, yp, s, skip);  // y = L^{-1} b, also into upper order
-        launch_blk<T, true>(lv.upper, sync + 2, yp, x, nullptr, s, skip);
-    } else if (which == HEC_LOWER) {
-        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.lower.grow.get(), b, bp, x, (T *)nullptr, skip);
-        HEC_CHECK_LAUNCH();
-        launch_blk<T, false>(lv.lower, sync, bp, x, nullptr, s, skip);
-    } else {
-        k_trsv_prep<T><<<g, 256, 0, s>>>(n, lv.upper.grow.get(), b, bp, x, (T *)nullptr, skip);
-        HEC_CHECK_LAUNCH();
-        launch_blk<T, true>(lv.upper, sync + 2, bp, x, nullptr, s, skip);
     }
 }
 
