@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--cpu-sample-iters", type=int, default=30)
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
-                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "copy"],
+                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "copy"],
                    help="diffusion128 is the benchmark line; the others print extra records "
                         "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
@@ -181,10 +181,31 @@ def main():
             "us": round(t_trsv_lu * 1e6, 1),
             "note": f"latency-bound: {li['nlev_lower']} + {li['nlev_upper']} dependent levels; "
                     f"the two solves are {trsv_share * 100:.0f}% of the step"}
+    # the copy bandwidth of this machine in this run (1 GiB device-to-device), the practical HBM ceiling
+    csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    t_copy = time_launches(lambda: cdst.copy_(csrc), 10, stream)
+    copy_gbs = 2 * csrc.numel() * 8 / t_copy / 1e9
+    del csrc, cdst
     spmv_roof = {"kernel": "k_spmv_ell<double,double,double>", "bound": "hbm",
                  "achieved": round(spmv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(spmv_gbs / HBM_PEAK_GBS, 4), "us": round(t_spmv * 1e6, 2),
-                 "bytes": spmv_bytes, "gflops": round(2 * nnz / t_spmv / 1e9, 1)}
+                 "bytes": spmv_bytes, "gflops": round(2 * nnz / t_spmv / 1e9, 1),
+                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(spmv_gbs / copy_gbs, 4)}
+
+    # latency bound of the triangular solve: the cost of one level measured on a chain (a 1D
+    # Poisson factor: 4096 levels of one row in one part), times the levels of both triangles
+    Ac = synth.poisson1d(4096)
+    Fc = hec.ilu_factor(Ac, k=0)
+    lvc = hec.level_schedule(Fc)
+    bc = torch.ones(Ac.n, dtype=torch.float64, device=dev)
+    zc = torch.empty_like(bc)
+    t_chain = time_launches(lambda: hec.trsv_levels(Fc, lvc, bc, zc, hec.LOWER), 20, stream)
+    t_level = t_chain / hec.levels_info(lvc)["nlev_lower"]
+    lat_bound = (li["nlev_lower"] + li["nlev_upper"]) * t_level
+    roof["latency"] = {"t_level_us": round(t_level * 1e6, 4),
+                       "bound_us": round(lat_bound * 1e6, 1), "frac": round(lat_bound / t_trsv_lu, 4),
+                       "note": "t_level = lower solve of a 4096-row chain (one row per level, one part) / 4096"}
 
     # ---- CPU oracle on a bounded sample (one GMRES cycle) ----
     cpu = None
@@ -192,19 +213,30 @@ def main():
         import oracle as O
         Ah = A
         bh = b.cpu().numpy()
+        # the oracle is single-threaded; pin it to one core of this host for the sample
+        cores_avail = sorted(os.sched_getaffinity(0))
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        os.sched_setaffinity(0, {cores_avail[0]})
         ts = time.time()
         Fo = O.iluk(Ah.n, Ah.Ap, Ah.Aj, Ah.Ax, 0)
         t_orc_ilu = time.time() - ts
         ts = time.time()
         ro = O.gmres(Ah, Fo, bh, restart=30, maxit=args.cpu_sample_iters, rtol=1e-8)
         t_orc = time.time() - ts
+        os.sched_setaffinity(0, set(cores_avail))
         per_it = t_orc / max(ro.iterations, 1)
         est_solve = per_it * it_per_solve
         cpu = {"value": round(1.0 / est_solve, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"oracle GMRES(30) ILU(0), first {ro.iterations} iterations of the same "
                          f"{m}^3 system ({t_orc:.1f}s, {per_it * 1e3:.0f} ms/iteration), scaled to the "
                          f"{it_per_solve} iterations of one solve; oracle ILU(0) setup {t_orc_ilu:.2f}s "
-                         f"not included; single thread, -O3 -ffp-contract=off"}
+                         f"not included; single thread pinned to one core, -O3 -ffp-contract=off",
+               "cpu_model": cpu_model, "host_cores_available": len(cores_avail)}
         log(f"[bench] cpu oracle: {per_it * 1e3:.1f} ms/iteration -> {est_solve:.1f} s/solve")
 
     lat_ms = np.array(lat) * 1e3
@@ -228,6 +260,7 @@ def main():
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "iterations": it_per_solve,
+        "us_per_iteration": round(ms_per_step * 1e3 / it_per_solve, 1),
         "rel_res": rel_res,
         "err_vs_x_true": err_true,
         "setup_s": {"hec_from_csr": round(t_hec, 3), "ilu_factor": round(t_ilu, 3),
@@ -333,6 +366,38 @@ def extra(args):
                     "trsv_lu_us_f32": round(time_launches(lambda: hec.trsv_levels(F, lv, bf, zf, hec.LU), 10, stream) * 1e6, 1)})
     elif args.workload == "serving":
         out.update(serving(args))
+    elif args.workload == "ras":
+        # Sec. 2.5 inner RAS on the 128^3 system: blocks 1/8/128/1024, overlap 0/1 (Table 4-5 shape)
+        A, xt = synth.workload_diffusion3d(args.m, sigma=2.0, seed=2)
+        Mh = hec.hec_from_csr(A)
+        xd = torch.from_numpy(xt).to(dev)
+        b = torch.empty_like(xd)
+        hec.hec_spmv(Mh, xd, b)
+        rows = []
+        for nb, ov in ((1, 0), (8, 0), (8, 1), (128, 0), (128, 1), (1024, 0), (1024, 1)):
+            ts = time.time()
+            F = hec.ilu_factor_ras(A, nb, ov, k=0) if (nb, ov) != (1, 0) else hec.ilu_factor(A, 0)
+            lv = hec.level_schedule(F)
+            t_setup = time.time() - ts
+            li = hec.levels_info(lv)
+            x = torch.empty_like(b)
+            hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-8)
+            lat = []
+            for _ in range(max(3, min(args.steps, 5))):
+                t1 = time.time()
+                inf = hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-8)
+                lat.append(time.time() - t1)
+            z = torch.empty_like(b)
+            t_lu = time_launches(lambda: hec.trsv_levels(F, lv, b, z, hec.LU), 20, stream)
+            row = {"blocks": nb, "overlap": ov, "factor_rows": hec.ilu_info(F)["n"],
+                   "levels_lower": li["nlev_lower"], "levels_upper": li["nlev_upper"],
+                   "iterations": inf["iterations"], "rel_res": inf["rel_res_true"],
+                   "solve_ms": round(float(np.median(lat)) * 1e3, 2), "solves_per_s": round(1.0 / float(np.median(lat)), 3),
+                   "trsv_lu_us": round(t_lu * 1e6, 1), "setup_s": round(t_setup, 2)}
+            rows.append(row)
+            log(f"[bench] ras {row}")
+            del F, lv
+        out.update({"n": A.n, "nnz": A.nnz, "ras": rows})
     elif args.workload == "copy":
         nbytes = 1 << 30
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
@@ -349,8 +414,8 @@ def serving(args):
     requests: FP64 with every request on its own stream ("fp64"), FP64 with small
     systems batched into persistent launches ("fp64_batched"), and mixed precision
     with batching ("mixed_batched"). Closed loop (all requests queued at t=0) gives
-    throughput; open loop (Poisson arrivals at 0.7x the fp64 closed-loop rate)
-    gives p50/p99 latency at a stated load."""
+    throughput; open loop (Poisson arrivals at 0.7x the FP64 sequential-service
+    rate, measured first with one slot) gives p50/p99 latency at a stated load."""
     from paper_1606_00545_amd import serve, synth
 
     t0 = time.time()
@@ -363,10 +428,10 @@ def serving(args):
         f"batched route n <= {args.batch_max_n}: {sum(1 for _, A, _ in systems if A.n <= args.batch_max_n)}")
     configs = (("fp64", 0, 0), ("fp64_batched", 0, args.batch_max_n), ("mixed_batched", 1, args.batch_max_n))
 
-    def run(prec, bmax, arrivals):
+    def run(prec, bmax, arrivals, slots=args.slots):
         reqs = [serve.Request(rid, A, b, precision=prec, rtol=1e-8, arrival=float(t))
                 for (rid, A, b), t in zip(systems, arrivals)]
-        srv = serve.Server(slots=args.slots, batch_max_n=bmax)
+        srv = serve.Server(slots=slots, batch_max_n=bmax)
         t = time.perf_counter()
         res = srv.run(reqs, t0=t)
         span = max(r.done for r in res) if res else 0.0
@@ -379,17 +444,21 @@ def serving(args):
                 "mean_batch": round(float(np.mean(srv.batches)), 1) if srv.batches else 0}
 
     out = {"requests": len(systems), "slots": args.slots, "batch_max_n": args.batch_max_n}
+    # the FP64 sequential-service rate (one request at a time) sets the open-loop arrival rate
+    seq = run(0, 0, np.zeros(len(systems)), slots=1)
+    log(f"[bench] serving sequential fp64: {seq}")
     closed = {}
     for name, prec, bmax in configs:
         closed[name] = run(prec, bmax, np.zeros(len(systems)))
         log(f"[bench] serving closed-loop {name}: {closed[name]}")
-    rate = 0.7 * closed["fp64"]["solves_per_s"]
+    rate = 0.7 * seq["solves_per_s"]
     arrivals = synth.poisson_arrivals(len(systems), rate)
     opened = {}
     for name, prec, bmax in configs:
         opened[name] = run(prec, bmax, arrivals)
         log(f"[bench] serving open-loop {name} at {rate:.2f}/s: {opened[name]}")
-    out.update({"closed_loop": closed, "open_loop_rate_per_s": round(rate, 3), "open_loop": opened})
+    out.update({"sequential_fp64": seq, "closed_loop": closed, "open_loop_rate_per_s": round(rate, 3),
+                "open_loop": opened})
     return out
 
 

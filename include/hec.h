@@ -127,10 +127,35 @@ hec_status hec_destroy(hec_matrix A);
 hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k,
                       uint32_t flags, void *stream, hec_ilu *out);
 
+/* Sec. 2.5, restricted additive Schwarz inside one device ("inner RAS"): the rows
+ * are cut into nblocks contiguous blocks of ceil(n / nblocks) rows (the sequence
+ * partition); each block is extended by `overlap` layers of graph neighbours (the
+ * rows reached through A's stored entries, layer by layer); the entries of A outside
+ * every extended block's diagonal submatrix are dropped, and ILU(k) (as in
+ * ilu_factor) is computed for each extended block. The extended blocks are stacked
+ * into one block-diagonal factor of sum(|extended block|) rows, each block's rows in
+ * ascending system order. Its preconditioner solve (trsv_levels with HEC_LU, and the
+ * solvers) solves every block independently -- no dependency crosses a block, so the
+ * blocks run in parallel -- and keeps from each block only the rows it owns
+ * ("restricted"). nblocks = 1, overlap = 0 equals ilu_factor. Fewer dependencies
+ * mean shorter level chains and more solver iterations (Sec. 2.5, Tables 4-5).
+ * INVALID_ARG for nblocks < 1, overlap < 0, a missing diagonal, or stacked sizes
+ * beyond 32-bit indices. Not usable with gmres_solve_batched. */
+hec_status ilu_factor_ras(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k,
+                          int32_t nblocks, int32_t overlap, uint32_t flags, void *stream, hec_ilu *out);
+
+/* n: rows of the factor (the stacked extended blocks for a RAS factor); nnz: its entries. */
 hec_status ilu_info(hec_ilu M, int32_t *n, int64_t *nnz);
 
+/* The block structure of a factor: system size, number of blocks, first stacked row
+ * of each block (nblocks+1), the system row of each stacked row (factor rows), and the
+ * stacked row that owns each system row (n_sys). A factor from ilu_factor reports one
+ * block and identity maps. Any pointer may be NULL. */
+hec_status ilu_ras_export(hec_ilu M, int32_t *n_sys, int32_t *nblocks, int32_t *block_start, int32_t *ext_row,
+                          int32_t *own);
+
 /* Copy the factor to host CSR buffers (n+1, nnz, nnz): L strictly below the
- * diagonal, U on and above it, columns ascending. */
+ * diagonal, U on and above it, columns ascending (stacked rows for a RAS factor). */
 hec_status ilu_export(hec_ilu M, int32_t *LUp, int32_t *LUj, double *LUx);
 
 hec_status ilu_destroy(hec_ilu M);
@@ -153,7 +178,8 @@ hec_status levels_export(hec_levels lv, int32_t *lower_ptr, int32_t *lower_perm,
 
 hec_status levels_destroy(hec_levels lv);
 
-/* Alg. 3: solve with the factor level by level. which = HEC_LOWER: x = L^{-1} b
+/* Alg. 3: solve with the factor level by level. A RAS factor (ilu_factor_ras)
+ * accepts only HEC_LU, with b and x of the system size. which = HEC_LOWER: x = L^{-1} b
  * (unit diagonal); HEC_UPPER: x = U^{-1} b; HEC_LU: x = U^{-1} L^{-1} b (the
  * preconditioner solve M x = b of Eq. (7)-(8)). prec selects FP64 factor and
  * vectors, or the FP32 factor copy (ilu_factor with HEC_KEEP_F32) with FP32

@@ -491,7 +491,8 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
             hec_ilu f = M[i];
             hec_levels l = lv[i];
             if (!a || !f || !l) fail(HEC_ERR_INVALID_ARG, "null handle in the batch");
-            if (a->n != f->n || a->n != l->n) fail(HEC_ERR_INVALID_ARG, "matrix, factor and levels differ in size");
+            if (a->n != f->n || a->n != l->n || f->n != f->n_sys)
+                fail(HEC_ERR_INVALID_ARG, "matrix, factor and levels differ in size (or a RAS factor)");
             if (a->n > B->max_n) fail(HEC_ERR_INVALID_ARG, "system larger than the batch context's max_n");
             if (a->n > 0 && (!b[i] || !x[i])) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
             if (mixed && (!a->has_f32 || !f->has_f32))

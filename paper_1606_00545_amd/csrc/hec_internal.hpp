@@ -148,7 +148,12 @@ struct hec_matrix_s {
 };
 
 struct hec_ilu_s {
-    int32_t n = 0, k = 0;
+    int32_t n = 0, k = 0;   // n: size of the factor (the stacked extended blocks for RAS)
+    // restricted additive Schwarz (Sec. 2.5): system size, blocks of the stacked factor
+    // (rows hblocks[b] .. hblocks[b+1]-1), the system row of each stacked row, and the
+    // stacked row that owns each system row. Without RAS: n_sys == n, hblocks empty.
+    int32_t n_sys = 0, nblocks = 1, overlap = 0;
+    std::vector<int32_t> hblocks, hext_row, hown;
     int32_t gnx = 0, gny = 0, gnz = 0;  // natural-order grid of A's stencil, if recognised (0: none)
     int64_t nnz = 0;
     bool has_f32 = false;
@@ -191,7 +196,9 @@ struct hec_tri {
     hec::DevBuf<int32_t> ss_pos;    // nss+1: first position of each sub-segment
     hec::DevBuf<int32_t> grow;      // position -> row
     std::vector<int32_t> hgrow;     // host copy of grow
-    hec::DevBuf<int32_t> other;     // lower only: the row's position in the upper plan
+    hec::DevBuf<int32_t> other;     // lower: the row's position in the upper plan; upper with RAS: the
+                                    // system row an owned stacked row is written to (-1: overlap row)
+    hec::DevBuf<int32_t> bmap;      // lower with RAS: the system row whose right-hand side a position reads
     hec::DevBuf<int32_t> enc;       // K*ldq: -(local position+1) inside the part, row outside, INT_MIN pad
     hec::DevBuf<double> val;
     hec::DevBuf<float> val32;
@@ -200,7 +207,11 @@ struct hec_tri {
 };
 
 struct hec_levels_s {
-    int32_t n = 0;
+    int32_t n = 0;    // system size (vectors the caller passes)
+    int32_t nf = 0;   // factor size (the stacked extended blocks for RAS)
+    bool ras = false;
+    hec::DevBuf<double> xh64;  // RAS: the upper solve's output over the stacked rows
+    hec::DevBuf<float> xh32;
     hec_tri lower, upper;
     hec::DevBuf<uint32_t> sync;            // part tickets + finished-workgroup counters
     hec::DevBuf<double> y64, yp64;   // y = L^{-1} b by row (sentinel-filled between solves), y in upper order

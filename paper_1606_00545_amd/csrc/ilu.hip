@@ -115,6 +115,128 @@ __global__ __launch_bounds__(256) void k_convert(size_t n, const S *__restrict__
 
 using namespace hec;
 
+// ILU(k) of a CSR matrix (validated, every diagonal stored): host symbolic phase
+// (Eq. (9)-(10)), device numeric phase level by level (Alg. 2 restricted to S_k).
+static std::unique_ptr<hec_ilu_s> factor_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax,
+                                            int32_t k, uint32_t flags, hipStream_t s) {
+    auto M = std::make_unique<hec_ilu_s>();
+    M->n = n;
+    M->k = k;
+    M->has_f32 = (flags & HEC_KEEP_F32) != 0;
+    symbolic_iluk(n, Ap, Aj, k, M->hLUp, M->hLUj, M->hdiag);
+    plan::detect_grid(n, Ap, Aj, M->gnx, M->gny, M->gnz);
+    M->nnz = M->hLUp[n];
+    // A's values scattered into S_k, fill entries start at 0
+    std::vector<double> x0(M->nnz, 0.0);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t f = M->hLUp[i];
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+            while (M->hLUj[f] < Aj[e]) ++f;
+            x0[f] = Ax[e];
+        }
+    }
+    M->LUp.alloc(n + 1);
+    M->LUj.alloc(M->nnz);
+    M->diag.alloc(n);
+    M->LUx.alloc(M->nnz);
+    M->LUp.upload(M->hLUp.data(), n + 1, s);
+    M->LUj.upload(M->hLUj.data(), M->nnz, s);
+    M->diag.upload(M->hdiag.data(), n, s);
+    M->LUx.upload(x0.data(), M->nnz, s);
+    // numeric elimination, one launch per level of L
+    std::vector<int32_t> lptr, perm;
+    int32_t nlev = plan::compute_levels(n, M->hLUp.data(), M->hLUj.data(), M->hdiag.data(), false, lptr, perm);
+    DevBuf<int32_t> dperm(n), dflag(1);
+    dperm.upload(perm.data(), n, s);
+    HEC_HIP(hipMemsetAsync(dflag.get(), 0, sizeof(int32_t), s));
+    for (int32_t l = 1; l < nlev; ++l) {  // level 0 rows have no L entries: nothing to do
+        int32_t a = lptr[l], cnt = lptr[l + 1] - lptr[l];
+        k_ilu_level<<<ceil_div(cnt, 256), 256, 0, s>>>(cnt, dperm.get() + a, M->LUp.get(), M->LUj.get(),
+                                                       M->diag.get(), M->LUx.get(), dflag.get());
+        HEC_CHECK_LAUNCH();
+    }
+    int32_t zp = 0;
+    dflag.download(&zp, 1, s);
+    HEC_HIP(hipStreamSynchronize(s));
+    if (zp) fail(HEC_ERR_ZERO_PIVOT, "zero pivot in row " + std::to_string(zp - 1));
+    // every pivot u_ii must be nonzero for the backward substitution, also
+    // those of rows that no later row uses
+    if (n) {
+        k_check_diag<<<ceil_div(n, 256), 256, 0, s>>>(n, M->diag.get(), M->LUx.get(), dflag.get());
+        HEC_CHECK_LAUNCH();
+        dflag.download(&zp, 1, s);
+        HEC_HIP(hipStreamSynchronize(s));
+        if (zp) fail(HEC_ERR_ZERO_PIVOT, "zero pivot in row " + std::to_string(zp - 1));
+    }
+    if (M->has_f32) {
+        M->LUx32.alloc(M->nnz);
+        if (M->nnz)
+            k_convert<double, float><<<ceil_div(M->nnz, 256), 256, 0, s>>>(M->nnz, M->LUx.get(),
+                                                                           M->LUx32.get());
+        HEC_CHECK_LAUNCH();
+        HEC_HIP(hipStreamSynchronize(s));
+    }
+    M->n_sys = n;
+    return M;
+}
+
+// Sec. 2.5, restricted additive Schwarz on one device: the rows are cut into
+// nblocks contiguous blocks (the sequence partition), each block is extended by
+// `overlap` layers of graph neighbours (rows reached through A's stored
+// entries), and the extended blocks are stacked into one block-diagonal matrix
+// that keeps only the entries of A inside each extended block. ext_row: system
+// row of each stacked row; bstart: first stacked row of each block; own: the
+// stacked row (inside its own block) of each system row.
+static void ras_stack(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t nblocks,
+                      int32_t overlap, std::vector<int32_t> &Sp, std::vector<int32_t> &Sj, std::vector<double> &Sx,
+                      std::vector<int32_t> &ext_row, std::vector<int32_t> &bstart, std::vector<int32_t> &own) {
+    const int32_t R = (int32_t)(((int64_t)n + nblocks - 1) / nblocks);
+    const int32_t nb = n ? (n + R - 1) / R : 0;
+    std::vector<int32_t> stamp(n, -1), loc(n, 0);
+    own.assign(n, -1);
+    ext_row.clear();
+    bstart.assign(1, 0);
+    Sp.assign(1, 0);
+    Sj.clear();
+    Sx.clear();
+    std::vector<int32_t> cur, layer, next;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t s0 = b * R, e0 = std::min(n, s0 + R);
+        cur.clear();
+        for (int32_t i = s0; i < e0; ++i) {
+            stamp[i] = b;
+            cur.push_back(i);
+        }
+        layer = cur;
+        for (int32_t l = 0; l < overlap; ++l) {
+            next.clear();
+            for (int32_t i : layer)
+                for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e)
+                    if (stamp[Aj[e]] != b) {
+                        stamp[Aj[e]] = b;
+                        next.push_back(Aj[e]);
+                    }
+            cur.insert(cur.end(), next.begin(), next.end());
+            layer.swap(next);
+        }
+        std::sort(cur.begin(), cur.end());
+        const int32_t base = (int32_t)ext_row.size();
+        for (size_t t = 0; t < cur.size(); ++t) loc[cur[t]] = (int32_t)t;
+        for (size_t t = 0; t < cur.size(); ++t) {
+            const int32_t i = cur[t];
+            ext_row.push_back(i);
+            if (i >= s0 && i < e0) own[i] = base + (int32_t)t;
+            for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e)
+                if (stamp[Aj[e]] == b) {
+                    Sj.push_back(base + loc[Aj[e]]);
+                    Sx.push_back(Ax[e]);
+                }
+            Sp.push_back((int32_t)Sj.size());
+        }
+        bstart.push_back((int32_t)ext_row.size());
+    }
+}
+
 extern "C" {
 
 hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k, uint32_t flags,
@@ -132,63 +254,42 @@ hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const dou
         }
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
-        auto M = std::make_unique<hec_ilu_s>();
-        M->n = n;
-        M->k = k;
-        M->has_f32 = (flags & HEC_KEEP_F32) != 0;
-        symbolic_iluk(n, Ap, Aj, k, M->hLUp, M->hLUj, M->hdiag);
-        plan::detect_grid(n, Ap, Aj, M->gnx, M->gny, M->gnz);
-        M->nnz = M->hLUp[n];
-        // A's values scattered into S_k, fill entries start at 0
-        std::vector<double> x0(M->nnz, 0.0);
+        auto M = factor_csr(n, Ap, Aj, Ax, k, flags, s);
+        *out = M.release();
+    });
+}
+
+hec_status ilu_factor_ras(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k,
+                          int32_t nblocks, int32_t overlap, uint32_t flags, void *stream, hec_ilu *out) {
+    return guarded([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        validate_csr(n, Ap, Aj, Ax);
+        if (k < 0) fail(HEC_ERR_INVALID_ARG, "k < 0");
+        if (nblocks < 1) fail(HEC_ERR_INVALID_ARG, "nblocks < 1");
+        if (overlap < 0) fail(HEC_ERR_INVALID_ARG, "overlap < 0");
+        if (flags & ~HEC_KEEP_F32) fail(HEC_ERR_INVALID_ARG, "unknown flags");
         for (int32_t i = 0; i < n; ++i) {
-            int32_t f = M->hLUp[i];
-            for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
-                while (M->hLUj[f] < Aj[e]) ++f;
-                x0[f] = Ax[e];
-            }
+            bool d = false;
+            for (int32_t e = Ap[i]; e < Ap[i + 1] && !d; ++e) d = Aj[e] == i;
+            if (!d) fail(HEC_ERR_INVALID_ARG, "row " + std::to_string(i) + " has no stored diagonal");
         }
-        M->LUp.alloc(n + 1);
-        M->LUj.alloc(M->nnz);
-        M->diag.alloc(n);
-        M->LUx.alloc(M->nnz);
-        M->LUp.upload(M->hLUp.data(), n + 1, s);
-        M->LUj.upload(M->hLUj.data(), M->nnz, s);
-        M->diag.upload(M->hdiag.data(), n, s);
-        M->LUx.upload(x0.data(), M->nnz, s);
-        // numeric elimination, one launch per level of L
-        std::vector<int32_t> lptr, perm;
-        int32_t nlev = plan::compute_levels(n, M->hLUp.data(), M->hLUj.data(), M->hdiag.data(), false, lptr, perm);
-        DevBuf<int32_t> dperm(n), dflag(1);
-        dperm.upload(perm.data(), n, s);
-        HEC_HIP(hipMemsetAsync(dflag.get(), 0, sizeof(int32_t), s));
-        for (int32_t l = 1; l < nlev; ++l) {  // level 0 rows have no L entries: nothing to do
-            int32_t a = lptr[l], cnt = lptr[l + 1] - lptr[l];
-            k_ilu_level<<<ceil_div(cnt, 256), 256, 0, s>>>(cnt, dperm.get() + a, M->LUp.get(), M->LUj.get(),
-                                                           M->diag.get(), M->LUx.get(), dflag.get());
-            HEC_CHECK_LAUNCH();
-        }
-        int32_t zp = 0;
-        dflag.download(&zp, 1, s);
-        HEC_HIP(hipStreamSynchronize(s));
-        if (zp) fail(HEC_ERR_ZERO_PIVOT, "zero pivot in row " + std::to_string(zp - 1));
-        // every pivot u_ii must be nonzero for the backward substitution, also
-        // those of rows that no later row uses
-        if (n) {
-            k_check_diag<<<ceil_div(n, 256), 256, 0, s>>>(n, M->diag.get(), M->LUx.get(), dflag.get());
-            HEC_CHECK_LAUNCH();
-            dflag.download(&zp, 1, s);
-            HEC_HIP(hipStreamSynchronize(s));
-            if (zp) fail(HEC_ERR_ZERO_PIVOT, "zero pivot in row " + std::to_string(zp - 1));
-        }
-        if (M->has_f32) {
-            M->LUx32.alloc(M->nnz);
-            if (M->nnz)
-                k_convert<double, float><<<ceil_div(M->nnz, 256), 256, 0, s>>>(M->nnz, M->LUx.get(),
-                                                                               M->LUx32.get());
-            HEC_CHECK_LAUNCH();
-            HEC_HIP(hipStreamSynchronize(s));
-        }
+        std::vector<int32_t> Sp, Sj, ext_row, bstart, own;
+        std::vector<double> Sx;
+        ras_stack(n, Ap, Aj, Ax, nblocks, overlap, Sp, Sj, Sx, ext_row, bstart, own);
+        const int64_t nf = (int64_t)ext_row.size();
+        if (nf > INT32_MAX / 2 || (int64_t)Sj.size() > INT32_MAX)
+            fail(HEC_ERR_INVALID_ARG, "extended blocks too large for 32-bit indices");
+        hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
+        auto M = factor_csr((int32_t)nf, Sp.data(), Sj.data(), Sx.data(), k, flags, s);
+        M->n_sys = n;
+        M->nblocks = (int32_t)bstart.size() - 1;
+        M->overlap = overlap;
+        M->gnx = M->gny = M->gnz = 0;
+        M->hblocks.swap(bstart);
+        M->hext_row.swap(ext_row);
+        M->hown.swap(own);
         *out = M.release();
     });
 }
@@ -213,6 +314,32 @@ hec_status ilu_export(hec_ilu M, int32_t *LUp, int32_t *LUj, double *LUx) {
     });
 }
 
+hec_status ilu_ras_export(hec_ilu M, int32_t *n_sys, int32_t *nblocks, int32_t *block_start, int32_t *ext_row,
+                          int32_t *own) {
+    return guarded([&] {
+        if (!M) fail(HEC_ERR_INVALID_ARG, "null factor");
+        const bool ras = !M->hext_row.empty();
+        if (n_sys) *n_sys = M->n_sys;
+        if (nblocks) *nblocks = ras ? M->nblocks : 1;
+        if (block_start) {
+            if (ras) {
+                std::copy(M->hblocks.begin(), M->hblocks.end(), block_start);
+            } else {
+                block_start[0] = 0;
+                block_start[1] = M->n;
+            }
+        }
+        if (ext_row) {
+            if (ras) std::copy(M->hext_row.begin(), M->hext_row.end(), ext_row);
+            else for (int32_t i = 0; i < M->n; ++i) ext_row[i] = i;
+        }
+        if (own) {
+            if (ras) std::copy(M->hown.begin(), M->hown.end(), own);
+            else for (int32_t i = 0; i < M->n; ++i) own[i] = i;
+        }
+    });
+}
+
 hec_status ilu_destroy(hec_ilu M) {
     delete M;
     return HEC_OK;
@@ -226,10 +353,12 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
         auto lv = std::make_unique<hec_levels_s>();
-        lv->n = M->n;
+        lv->n = M->n_sys;
+        lv->nf = M->n;
+        lv->ras = !M->hext_row.empty();
         build_tri(*M, true, lv->upper, nullptr, s);
         build_tri(*M, false, lv->lower, &lv->upper, s);
-        if (M->n <= HEC_BATCH_MAX_N) {  // small enough for the batched solver
+        if (!lv->ras && M->n <= HEC_BATCH_MAX_N) {  // small enough for the batched solver
             build_flat(*M, false, lv->lower, s);
             build_flat(*M, true, lv->upper, s);
         }
@@ -237,9 +366,11 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, 4 * sizeof(uint32_t), s));
         lv->y64.alloc(M->n);
         lv->yp64.alloc(M->n);
+        if (lv->ras) lv->xh64.alloc(M->n);
         if (M->has_f32) {
             lv->y32.alloc(M->n);
             lv->yp32.alloc(M->n);
+            if (lv->ras) lv->xh32.alloc(M->n);
         }
         trsv_init_levels(*lv, s);
         HEC_HIP(hipStreamSynchronize(s));
@@ -276,8 +407,10 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
                        void *stream) {
     return guarded([&] {
         if (!M || !lv) fail(HEC_ERR_INVALID_ARG, "null factor or levels");
-        if (M->n != lv->n) fail(HEC_ERR_INVALID_ARG, "factor and levels differ in size");
+        if (M->n_sys != lv->n || M->n != lv->nf) fail(HEC_ERR_INVALID_ARG, "factor and levels differ in size");
         if (which != HEC_LOWER && which != HEC_UPPER && which != HEC_LU) fail(HEC_ERR_INVALID_ARG, "bad `which`");
+        if (lv->ras && which != HEC_LU)
+            fail(HEC_ERR_INVALID_ARG, "a RAS factor is applied as a whole (HEC_LU): its triangles are over the stacked blocks");
         if (lv->n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
         if (b == x && lv->n > 0) fail(HEC_ERR_INVALID_ARG, "b and x must not overlap");
         hipStream_t s = as_stream(stream);

@@ -705,7 +705,8 @@ static double vec_norm(KrylovWS &ws, int64_t n, const double *v, hipStream_t s) 
 static void check_solve_args(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
                              const hec_solve_opts *o) {
     if (!A || !M || !lv || !o) fail(HEC_ERR_INVALID_ARG, "null handle or options");
-    if (A->n != M->n || A->n != lv->n) fail(HEC_ERR_INVALID_ARG, "matrix, factor and levels differ in size");
+    if (A->n != M->n_sys || A->n != lv->n || M->n != lv->nf)
+        fail(HEC_ERR_INVALID_ARG, "matrix, factor and levels differ in size");
     if (A->n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "b or x is NULL");
     if (o->maxit < 0) fail(HEC_ERR_INVALID_ARG, "maxit < 0");
     if (!(o->rtol > 0.0)) fail(HEC_ERR_INVALID_ARG, "rtol must be > 0");

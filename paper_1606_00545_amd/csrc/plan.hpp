@@ -168,7 +168,7 @@ struct HostPlan {
 
 inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                       int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P,
-                      bool flat = false) {
+                      bool flat = false, const std::vector<int32_t> *blocks = nullptr) {
     P = HostPlan();
     P.n = n;
     P.nlev = compute_levels(n, LUp, LUj, diag, upper, P.level_ptr, P.perm, &P.lev);
@@ -192,7 +192,30 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
         R = std::min<int64_t>(R, n);
         bool tiled = false;
         int32_t ntiles = 0;
-        if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
+        // explicit blocks (rows blocks[b] .. blocks[b+1]-1, no dependency between blocks): enough
+        // of them make independent parts -- one block per part, or consecutive blocks grouped so
+        // that about kTileParts parts remain (grouped blocks share sub-segments level by level);
+        // a few large blocks are cut like any factor
+        const int32_t nbk = blocks && blocks->size() >= 2 && blocks->back() == n ? (int32_t)blocks->size() - 1 : 0;
+        const bool by_block = nbk >= kTileParts / 8;
+        if (by_block) {
+            const int32_t group = (nbk + kTileParts - 1) / kTileParts;
+            ntiles = (nbk + group - 1) / group;
+            for (int32_t b = 0; b < nbk; ++b) {
+                const int32_t t = b / group;
+                for (int32_t i = (*blocks)[b]; i < (*blocks)[b + 1]; ++i) part_of[i] = upper ? ntiles - 1 - t : t;
+            }
+            tiled = true;
+            for (int32_t i = 0; i < n && tiled; ++i) {
+                int32_t a, b2;
+                deps(i, a, b2);
+                for (int32_t e = a; e < b2; ++e)
+                    if (part_of[LUj[e]] > part_of[i]) {
+                        tiled = false;
+                        break;
+                    }
+            }
+        } else if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
             const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
             const int64_t plane = (int64_t)gnx * gny;
             int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));

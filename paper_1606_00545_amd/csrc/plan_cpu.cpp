@@ -14,14 +14,19 @@ extern "C" {
 // Builds the plan of the strict lower (upper == 0) or strict upper triangle of
 // the factor pattern (LUp, LUj, diag: row pointers, columns, diagonal
 // positions; 0-based) with the grid sizes detected from A (all 0: none) and
-// lds_max bytes of LDS per workgroup; flat != 0 asks for the level-order layout.
-// Returns NULL on allocation failure.
+// lds_max bytes of LDS per workgroup; flat != 0 asks for the level-order layout;
+// blocks (nbounds entries, may be NULL): first rows of independent row blocks
+// followed by n, to be used as parts. Returns NULL on allocation failure.
 void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
-                   int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max, int32_t flat) {
+                   int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max, int32_t flat,
+                   const int32_t *blocks, int32_t nbounds) {
     HostPlan *P = new (std::nothrow) HostPlan();
     if (!P) return nullptr;
     try {
-        hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P, flat != 0);
+        std::vector<int32_t> bv;
+        if (blocks && nbounds > 0) bv.assign(blocks, blocks + nbounds);
+        hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P, flat != 0,
+                             bv.empty() ? nullptr : &bv);
     } catch (...) {
         delete P;
         return nullptr;

@@ -88,14 +88,17 @@ __device__ __forceinline__ T from_bits(typename Sentinel<T>::U u) {
     return v;
 }
 
-// Vectors of one triangular solve. b: right-hand side, by row (b_by_row) or
-// already in plan order; x: output by row (pre-filled with the sentinel);
-// yother: optional copy of the output in the other triangle's plan order;
-// fill: a vector of nfill elements the kernel sets to the sentinel for the
-// next solve (the output of the other triangle of an L-then-U chain).
+// Vectors of one triangular solve. b: right-hand side, read at bmap[q] for
+// position q when bmap is given, else by row (b_by_row) or in plan order; x:
+// output by row (pre-filled with the sentinel); yother: optional second output,
+// written at the plan's per-position index (`other`, -1: not written) -- the
+// other triangle's plan order, or a caller's vector; fill: a vector of nfill
+// elements the kernel sets to the sentinel for the next solve (the output of the
+// other triangle of an L-then-U chain).
 template <class T>
 struct SolveIO {
     const T *b;
+    const int32_t *bmap;
     int32_t b_by_row;
     T *x, *yother, *fill;
     int64_t nfill;
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 if (lane < cur.cnt) {
                     sx[(cur.q0 - pos0 + lane) & (W - 1)] = acc;
                     store_coherent(x + cur.gi, acc);
-                    if (yother) yother[cur.po] = acc;
+                    if (yother && cur.po >= 0) yother[cur.po] = acc;
                 }
                 // release consumed slots to the prefetchers every 4 sub-segments (and at the end)
                 if ((rel & 3) == 3 || rel + 1 == nss) {
@@ -276,26 +279,84 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
             __builtin_amdgcn_s_setprio(0);
         } else {
             // ---------------- prefetchers: every lane of a slot is written (idle lanes get padding)
-            const int w = wave - 1;
-            for (int rel = w; rel < nss; rel += kPrefetchWaves) {
+            // Each prefetching wavefront keeps two of its sub-segments in flight: while
+            // the right-hand side and the polls of one are outstanding, the row data and
+            // first entries of its next one (kPrefetchWaves later) are already loading.
+            // Only the LDS writes wait for the solver to release the slot.
+            constexpr int B = KC < kBatch ? KC : kBatch;
+            constexpr bool kPfPipe = KC == 4;  // two register sets fit the 128-VGPR budget for short rows only
+            struct Pre {
+                int q0, cnt, gi, po;
+                T dd;
+                int es[B];
+                T vs[B];
+            };
+            auto issue = [&](int r, Pre &R) {  // everything indexed by position: one round trip
+                R.q0 = sspos[r];
+                R.cnt = sspos[r + 1] - R.q0;
+                const bool live = lane < R.cnt;
+                const int q = R.q0 + (live ? lane : 0);
+                R.gi = live ? P.grow[q] : 0;
+                R.po = live && P.other ? P.other[q] : -1;
+                R.dd = (T)1;
+                if constexpr (UPPER) R.dd = live ? piv[q] : (T)1;
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    R.es[u] = kPad;
+                    R.vs[u] = (T)0;
+                    if (live && u < K) {
+                        R.es[u] = P.enc[(size_t)u * P.ldq + q];
+                        R.vs[u] = val[(size_t)u * P.ldq + q];
+                    }
+                }
+            };
+            // every lane polls all its entries at once; entries without an outside
+            // dependency read a constant zero
+            auto poll = [&](const int (&es)[B], U (&xs)[B]) {
+                bool pend = false;
+#pragma unroll
+                for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
+                while (pend) {
+                    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                    for (int u = 0; u < B; ++u)
+                        if (xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
+                    pend = false;
+#pragma unroll
+                    for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
+                }
+            };
+            auto put = [&](char *sl, uint32_t so, int s0, const int (&es)[B], const T (&vs)[B], const U (&xs)[B]) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int s = s0 + u;
+                    const uint32_t xe_at = so + (uint32_t)(L.xe() + (size_t)(s * kSub + lane) * sizeof(T));
+                    uint32_t at = zero_off;  // padding: value 0 times a zero
+                    if (es[u] >= 0) at = xe_at;
+                    else if (es[u] != kPad) at = sx_off + (uint32_t)(((-1 - es[u]) & (W - 1)) * sizeof(T));
+                    ((uint32_t *)(sl + L.a()))[s * kSub + lane] = at;
+                    ((T *)(sl + L.v()))[s * kSub + lane] = vs[u];
+                    ((T *)(sl + L.xe()))[s * kSub + lane] = from_bits<T>(xs[u]);
+                }
+            };
+            auto process = [&](int rel, Pre &cur, Pre &nxt) {
                 const int slot = rel % D;
-                while (__hip_atomic_load(consumed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < rel - D + 1)
-                    __builtin_amdgcn_s_sleep(4);
-                const int q0 = sspos[rel], cnt = sspos[rel + 1] - q0;
                 const uint32_t so = slots_off + slot * sb;
                 char *sl = smem + so;
-                const bool live = lane < cnt;
-                const int q = q0 + (live ? lane : 0);
-                int gi = live ? P.grow[q] : 0;
-                T bb = live ? io.b[io.b_by_row ? gi : q] : (T)0;
-                int po = live && P.other ? P.other[q] : 0;
-                T dd = (T)1;
-                if constexpr (UPPER) dd = live ? piv[q] : (T)1;
-                constexpr int B = KC < kBatch ? KC : kBatch;
-                for (int s0 = 0; s0 < KC; s0 += B) {
+                const bool live = lane < cur.cnt;
+                const int q = cur.q0 + (live ? lane : 0);
+                const T bb = live ? io.b[io.bmap ? io.bmap[q] : io.b_by_row ? cur.gi : q] : (T)0;
+                U xs[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) xs[u] = load_coherent(cur.es[u] >= 0 ? x + cur.es[u] : zero_addr<T>());
+                if (kPfPipe && rel + kPrefetchWaves < nss) issue(rel + kPrefetchWaves, nxt);
+                poll(cur.es, xs);
+                while (__hip_atomic_load(consumed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < rel - D + 1)
+                    __builtin_amdgcn_s_sleep(4);
+                put(sl, so, 0, cur.es, cur.vs, xs);
+                for (int s0 = B; s0 < KC; s0 += B) {  // rows longer than one batch
                     int es[B];
                     T vs[B];
-                    U xs[B];
 #pragma unroll
                     for (int u = 0; u < B; ++u) {
                         es[u] = kPad;
@@ -305,42 +366,33 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                             vs[u] = val[(size_t)(s0 + u) * P.ldq + q];
                         }
                     }
-                    // every lane polls all its entries at once; entries without an
-                    // outside dependency read a constant zero
+                    U xs2[B];
 #pragma unroll
-                    for (int u = 0; u < B; ++u) xs[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
-                    bool pend = false;
-#pragma unroll
-                    for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
-                    while (pend) {
-                        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                        for (int u = 0; u < B; ++u)
-                            if (xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
-                        pend = false;
-#pragma unroll
-                        for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
-                    }
-#pragma unroll
-                    for (int u = 0; u < B; ++u) {
-                        const int s = s0 + u;
-                        {
-                            const uint32_t xe_at = so + (uint32_t)(L.xe() + (size_t)(s * kSub + lane) * sizeof(T));
-                            uint32_t at = zero_off;  // padding: value 0 times a zero
-                            if (es[u] >= 0) at = xe_at;
-                            else if (es[u] != kPad) at = sx_off + (uint32_t)(((-1 - es[u]) & (W - 1)) * sizeof(T));
-                            ((uint32_t *)(sl + L.a()))[s * kSub + lane] = at;
-                            ((T *)(sl + L.v()))[s * kSub + lane] = vs[u];
-                            ((T *)(sl + L.xe()))[s * kSub + lane] = from_bits<T>(xs[u]);
-                        }
-                    }
+                    for (int u = 0; u < B; ++u) xs2[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
+                    poll(es, xs2);
+                    put(sl, so, s0, es, vs, xs2);
                 }
                 ((T *)(sl + L.b()))[lane] = bb;
-                ((int *)(sl + L.gi()))[lane] = gi;
-                ((int *)(sl + L.po()))[lane] = po;
-                if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = dd;
+                ((int *)(sl + L.gi()))[lane] = cur.gi;
+                ((int *)(sl + L.po()))[lane] = cur.po;
+                if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = cur.dd;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (lane == 0) __hip_atomic_store(&filled[slot], rel, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            const int w = wave - 1;
+            if constexpr (kPfPipe) {
+                Pre p0, p1;
+                if (w < nss) issue(w, p0);
+                for (int rel = w; rel < nss; rel += 2 * kPrefetchWaves) {
+                    process(rel, p0, p1);
+                    if (rel + kPrefetchWaves < nss) process(rel + kPrefetchWaves, p1, p0);
+                }
+            } else {
+                for (int rel = w; rel < nss; rel += kPrefetchWaves) {
+                    Pre p0;
+                    issue(rel, p0);
+                    process(rel, p0, p0);
+                }
             }
         }
     }
@@ -378,7 +430,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
         const int32_t q = chunk_ptr[t] + lane;
         if (q < chunk_ptr[t + 1]) {
             const int32_t gi = grow[q];
-            T acc = io.b[io.b_by_row ? gi : q];
+            T acc = io.b[io.bmap ? io.bmap[q] : io.b_by_row ? gi : q];
             for (int32_t s0 = 0; s0 < K; s0 += kBatch) {
                 const int nb = min(kBatch, K - s0);
                 int es[kBatch];
@@ -414,7 +466,10 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
             }
             if constexpr (UPPER) acc = acc / piv[q];
             store_coherent(x + gi, acc);
-            if (yother) yother[other[q]] = acc;
+            if (yother) {
+                const int32_t o = other[q];
+                if (o >= 0) yother[o] = acc;
+            }
         }
     }
     if (lane == 0) {
@@ -517,24 +572,37 @@ void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipSt
         yp = lv.yp32.get();
     }
     uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
+    if (lv.ras) {
+        // restricted additive Schwarz: the lower solve reads b through the stacked rows' system
+        // rows, the upper solve writes each owned row's result to x; stacked vectors are internal
+        const int64_t nf = lv.nf;
+        T *xh;
+        if constexpr (sizeof(T) == 8)
+            xh = lv.xh64.get();
+        else
+            xh = lv.xh32.get();
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, lv.lower.bmap.get(), 0, y, yp, xh, nf}, s, skip);
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, xh, x, y, nf}, s, skip);
+        return;
+    }
     if (which == HEC_LU) {
         // y (the lower solve's output) is sentinel-filled between calls: by
         // level_schedule, then by every upper solve for the next call. The lower
         // solve fills x for the upper one; no separate launch.
-        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, 1, y, yp, x, n}, s, skip);
-        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, 0, x, nullptr, y, n}, s, skip);
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, y, yp, x, n}, s, skip);
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, x, nullptr, y, n}, s, skip);
         return;
     }
     k_trsv_fill<T><<<ceil_div(n, 256), 256, 0, s>>>(n, x, skip);
     HEC_CHECK_LAUNCH();
     if (which == HEC_LOWER)
-        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, 1, x, nullptr, nullptr, 0}, s, skip);
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, x, nullptr, nullptr, 0}, s, skip);
     else
-        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{b, 1, x, nullptr, nullptr, 0}, s, skip);
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{b, nullptr, 1, x, nullptr, nullptr, 0}, s, skip);
 }
 
 void trsv_init_levels(hec_levels_s &lv, hipStream_t s) {
-    const int64_t n = lv.n;
+    const int64_t n = lv.nf;
     if (n == 0) return;
     k_trsv_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.y64.get(), nullptr);
     HEC_CHECK_LAUNCH();
@@ -553,7 +621,7 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     const int32_t n = M.n;
     plan::HostPlan P;
     plan::make_plan(n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, M.has_f32,
-                    max_lds_per_block() - 256, P);
+                    max_lds_per_block() - 256, P, false, M.hblocks.empty() ? nullptr : &M.hblocks);
     tri.nlev = P.nlev;
     tri.hlevel_ptr = std::move(P.level_ptr);
     tri.hperm = std::move(P.perm);
@@ -583,6 +651,24 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     tri.ss_pos.upload(P.ss_pos.data(), P.ss_pos.size(), s);
     tri.grow.alloc(n);
     tri.grow.upload(P.grow.data(), n, s);
+    const bool ras = !M.hext_row.empty();
+    if (ras && !upper) {  // right-hand side of each position: the system row of its stacked row
+        std::vector<int32_t> bm(n);
+        for (int32_t q = 0; q < n; ++q) bm[q] = M.hext_row[P.grow[q]];
+        tri.bmap.alloc(n);
+        tri.bmap.upload(bm.data(), n, s);
+        HEC_HIP(hipStreamSynchronize(s));
+    }
+    if (ras && upper) {  // owned rows write their result to the system vector, overlap rows nowhere
+        std::vector<int32_t> om(n);
+        for (int32_t q = 0; q < n; ++q) {
+            const int32_t row = P.grow[q], sys = M.hext_row[row];
+            om[q] = M.hown[sys] == row ? sys : -1;
+        }
+        tri.other.alloc(n);
+        tri.other.upload(om.data(), n, s);
+        HEC_HIP(hipStreamSynchronize(s));
+    }
     if (!upper && upper_plan) {
         // position of each lower-plan row in the upper plan
         std::vector<int32_t> up_pos(n), other(n);

@@ -23,7 +23,7 @@ KEEP_F32 = 1
 LOWER, UPPER, LU = 1, 2, 3
 
 EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
-            "ilu_factor", "ilu_info", "ilu_export", "ilu_destroy",
+            "ilu_factor", "ilu_factor_ras", "ilu_info", "ilu_ras_export", "ilu_export", "ilu_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched", "hec_last_error")
@@ -76,7 +76,10 @@ def load(path: str = LIB_PATH):
     L.hec_spmv.argtypes = [_vp, C.c_int, C.c_double, _vp, C.c_int, C.c_double, _vp, C.c_int, _vp]
     L.hec_destroy.argtypes = [_vp]
     L.ilu_factor.argtypes = [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_uint32, _vp, C.POINTER(_vp)]
+    L.ilu_factor_ras.argtypes = [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _vp,
+                                 C.POINTER(_vp)]
     L.ilu_info.argtypes = [_vp, _i32p, _i64p]
+    L.ilu_ras_export.argtypes = [_vp, _i32p, _i32p, _vp, _vp, _vp]
     L.ilu_export.argtypes = [_vp, _vp, _vp, _vp]
     L.ilu_destroy.argtypes = [_vp]
     L.level_schedule.argtypes = [_vp, _vp, C.POINTER(_vp)]
@@ -234,6 +237,28 @@ def ilu_factor(A, k: int = 0, keep_f32: bool = False, stream=None) -> Factor:
     _check(load().ilu_factor(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, k, KEEP_F32 if keep_f32 else 0,
                              _stream_or_null(stream), C.byref(out)), "ilu_factor")
     return Factor(out.value)
+
+
+def ilu_factor_ras(A, nblocks: int, overlap: int = 0, k: int = 0, keep_f32: bool = False, stream=None) -> Factor:
+    """Restricted additive Schwarz ILU(k): nblocks contiguous blocks, `overlap` neighbour layers."""
+    n, Ap, Aj, Ax = _csr(A)
+    out = _vp()
+    _check(load().ilu_factor_ras(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, k, nblocks, overlap,
+                                 KEEP_F32 if keep_f32 else 0, _stream_or_null(stream), C.byref(out)),
+           "ilu_factor_ras")
+    return Factor(out.value)
+
+
+def ilu_ras_export(M: Factor) -> dict:
+    nf = ilu_info(M)["n"]
+    n_sys, nb = C.c_int32(), C.c_int32()
+    _check(load().ilu_ras_export(M.ptr, C.byref(n_sys), C.byref(nb), None, None, None), "ilu_ras_export")
+    bs = np.empty(nb.value + 1, np.int32)
+    ext = np.empty(nf, np.int32)
+    own = np.empty(n_sys.value, np.int32)
+    _check(load().ilu_ras_export(M.ptr, None, None, bs.ctypes.data, ext.ctypes.data, own.ctypes.data),
+           "ilu_ras_export")
+    return {"n_sys": n_sys.value, "nblocks": nb.value, "block_start": bs, "ext_row": ext, "own": own}
 
 
 def ilu_info(M: Factor) -> dict:

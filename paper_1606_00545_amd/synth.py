@@ -75,6 +75,13 @@ def _grid(nx, ny, nz):
     return c % nx, (c // nx) % ny, c // (nx * ny)
 
 
+def poisson1d(m: int) -> CSR:
+    """3-point Dirichlet Poisson on m interior points: 2 on the diagonal, -1 off it."""
+    x, _, _ = _grid(m, 1, 1)
+    valid = [x > 0, np.ones(m, bool), x < m - 1]
+    return _assemble(m, [-1, 0, 1], valid, [-1.0, 2.0, -1.0])
+
+
 def poisson2d(m: int) -> CSR:
     """5-point Dirichlet Poisson on an m x m interior grid: 4 on the diagonal, -1 off it."""
     n = m * m

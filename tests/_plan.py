@@ -24,7 +24,7 @@ def lib():
         ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         L.hecplan_make.restype = C.c_void_p
         L.hecplan_make.argtypes = [C.c_int32, ip, ip, ip, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                   C.c_int32, C.c_int64, C.c_int32]
+                                   C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int32]
         L.hecplan_meta.argtypes = [C.c_void_p, np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
         L.hecplan_array.restype = C.c_int64
         L.hecplan_array.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p]
@@ -53,12 +53,14 @@ def diag_positions(F):
     return d
 
 
-def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=False):
+def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=False, blocks=None):
     """Plan of one triangle of the factor F (oracle Factor) as a dict of meta values and arrays."""
     L = lib()
     diag = diag_positions(F)
+    bl = None if blocks is None else _i32(blocks)
     h = L.hecplan_make(F.n, _i32(F.LUp), _i32(F.LUj), diag, grid[0], grid[1], grid[2], int(upper),
-                       int(has_f32), lds_max, int(flat))
+                       int(has_f32), lds_max, int(flat), None if bl is None else bl.ctypes.data,
+                       0 if bl is None else bl.size)
     assert h, "planner failed"
     try:
         meta = np.zeros(16, np.int64)

@@ -221,6 +221,45 @@ def replay(P, F, b, upper):
     return x
 
 
+def _stacked(blocks):
+    """One block-diagonal factor from the oracle's per-block RAS factors (stacked rows)."""
+    LUp, LUj, LUx, starts = [0], [], [], [0]
+    for B in blocks:
+        F = B.factor
+        base = starts[-1]
+        for i in range(F.n):
+            for e in range(F.LUp[i], F.LUp[i + 1]):
+                LUj.append(base + F.LUj[e])
+                LUx.append(F.LUx[e])
+            LUp.append(len(LUj))
+        starts.append(base + F.n)
+    n = starts[-1]
+    return O.Factor(n, np.array(LUp, np.int32), np.array(LUj, np.int32), np.array(LUx), np.zeros(len(LUj), np.int32)), \
+        np.array(starts, np.int32)
+
+
+@pytest.mark.parametrize("nb,ov,k", [(8, 0, 0), (16, 1, 0), (5, 2, 1), (64, 1, 0), (40, 0, 0), (600, 0, 0),
+                                     (300, 1, 0)])
+def test_block_plans_have_independent_parts(nb, ov, k):
+    A = synth.lognormal_tpfa((21, 17, 13), 2.0, np.random.default_rng(12))
+    F, starts = _stacked(O.ras_factor(A, nb, ov, k))
+    b = np.random.default_rng(13).uniform(-1, 1, F.n)
+    y_o = O.trsv_lower(F, b)
+    x_o = O.trsv_upper(F, y_o)
+    nbk = len(starts) - 1
+    for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
+        P = _plan.make_plan(F, upper, blocks=starts)
+        assert P["blocked"]
+        if nbk >= 32:  # enough blocks: independent parts, consecutive blocks grouped to ~256 parts
+            group = -(-nbk // 256)
+            assert P["nparts"] == -(-nbk // group)
+            enc = P["enc"].reshape(P["K"], P["ldq"])[:, :F.n]
+            assert not (enc >= 0).any(), "a dependency crosses a part"
+        check_structure(P, F, upper, _plan.LDS_MAX)
+        x = replay(P, F, rhs, upper)
+        assert np.array_equal(x.view(np.uint64), ref.view(np.uint64))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_plan_structure_and_replay(factors, name):
     A, F, opt = factors(name)
