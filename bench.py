@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes moved by one preconditioner solve (lower + upper k_trsv_blk) on the 128^3 system, measured with
+# rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
+# as they are -- reset to None whenever the solve kernels change until the counters are taken again.
+TRSV_PAIR_TRAFFIC = int((276.0 + 92.9 + 279.5 + 83.4) * 1e6)
 
 
 def parse():
@@ -177,7 +181,10 @@ def main():
     roof = {"kernel": "k_trsv_blk<double,false,4> + k_trsv_blk<double,true,4> "
                       "(one preconditioner solve: the lower and the upper launch)",
             "bound": "hbm", "achieved": round(trsv_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(trsv_gbs / HBM_PEAK_GBS, 5), "traffic": None, "bytes": trsv_bytes,
+            "frac": round(trsv_gbs / HBM_PEAK_GBS, 5), "traffic": TRSV_PAIR_TRAFFIC if m == 128 else None,
+            "traffic_note": "HBM bytes of one lower + one upper launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                            "scaled by a plain copy's counts (profiles/gmres_ilu0_tpfa128_hbm_counters.md)",
+            "bytes": trsv_bytes,
             "us": round(t_trsv_lu * 1e6, 1),
             "note": f"latency-bound: {li['nlev_lower']} + {li['nlev_upper']} dependent levels; "
                     f"the two solves are {trsv_share * 100:.0f}% of the step"}
