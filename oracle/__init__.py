@@ -14,6 +14,7 @@ Functions, each following the passage cited in ``oracle.c``:
 * :func:`trsv_lower`, :func:`trsv_upper` -- Sec. 2.6 substitution
 * :func:`gmres`           -- Sec. 2.7 restarted right-preconditioned GMRES(m)
 * :func:`bicgstab`        -- Sec. 2.7, Alg. 4
+* :func:`cg`              -- Sec. 2.7 preconditioned conjugate gradient
 * :func:`ras_blocks`, :func:`ras_factor`, :func:`ras_apply` -- Sec. 2.5 restricted
   additive Schwarz (sequence partition, overlap layers, per-block ILU(k), restricted
   solve), written out block by block from the definition
@@ -77,6 +78,8 @@ def lib():
         L.orc_bicgstab.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
                                    C.c_int, C.c_double, _ip, _dp]
         L.orc_bicgstab.restype = C.c_int
+        L.orc_cg.argtypes = L.orc_bicgstab.argtypes
+        L.orc_cg.restype = C.c_int
         _lib = L
     return _lib
 
@@ -218,6 +221,16 @@ def bicgstab(A, F: Factor, b, x0=None, maxit=10000, rtol=1e-8) -> SolveResult:
     rr = C.c_double()
     st = lib().orc_bicgstab(A.n, _i32(A.Ap), _i32(A.Aj), _f64(A.Ax), F.LUp, F.LUj, F.LUx, _f64(b), x,
                             maxit, rtol, C.byref(it), C.byref(rr))
+    return SolveResult(st, x, it.value, rr.value)
+
+
+def cg(A, F: Factor, b, x0=None, maxit=10000, rtol=1e-8) -> SolveResult:
+    """Preconditioned conjugate gradient (Sec. 2.7), M = LU symmetric positive definite."""
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    it = C.c_int()
+    rr = C.c_double()
+    st = lib().orc_cg(A.n, _i32(A.Ap), _i32(A.Aj), _f64(A.Ax), F.LUp, F.LUj, F.LUx, _f64(b), x,
+                      maxit, rtol, C.byref(it), C.byref(rr))
     return SolveResult(st, x, it.value, rr.value)
 
 

@@ -501,3 +501,71 @@ int orc_bicgstab(int n, const int *Ap, const int *Aj, const double *Ax,
     free(r0); free(r); free(p); free(ps); free(v); free(s); free(ss); free(t); free(tmp);
     return status;
 }
+
+/* Sec. 2.7 names CG among the implemented Krylov solvers (its steps are the
+ * textbook preconditioned conjugate gradient the paper defers to): with
+ * r = b - A x, z = M^{-1} r, p = z, rho = (r, z), repeat: q = A p,
+ * alpha = rho / (p, q), x += alpha p, r -= alpha q, stop when ||r|| / ||b|| <=
+ * rtol, z = M^{-1} r, rho' = (r, z), p = z + (rho'/rho) p. M = LU must be
+ * symmetric positive definite (an ILU(k) of an SPD M-matrix with a symmetric
+ * pattern is). rho <= 0 or (p, q) <= 0 (or non-finite) is a breakdown. After the
+ * recurrence stops the true residual decides; if it is above rtol the method
+ * restarts from x, at most 3 times, within maxit iterations. */
+int orc_cg(int n, const int *Ap, const int *Aj, const double *Ax,
+           const int *LUp, const int *LUj, const double *LUx,
+           const double *b, double *x, int maxit, double rtol,
+           int *iters_out, double *relres_out)
+{
+    *iters_out = 0;
+    double bnorm = nrm2(n, b);
+    if (bnorm == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        *relres_out = 0.0;
+        return ORC_OK;
+    }
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(sizeof(double) * N);
+    double *z = (double *)malloc(sizeof(double) * N);
+    double *p = (double *)malloc(sizeof(double) * N);
+    double *q = (double *)malloc(sizeof(double) * N);
+    double *tmp = (double *)malloc(sizeof(double) * N);
+    if (!r || !z || !p || !q || !tmp) {
+        free(r); free(z); free(p); free(q); free(tmp);
+        return ORC_NOMEM;
+    }
+    int it = 0, restarts = 0, broke = 0;
+    double relres = residual(n, Ap, Aj, Ax, b, x, r) / bnorm;
+    while (relres > rtol && it < maxit && restarts <= 3) {
+        broke = 0;
+        apply_prec(n, LUp, LUj, LUx, r, z, tmp);
+        for (int i = 0; i < n; ++i) p[i] = z[i];
+        double rho = dot(n, r, z);
+        if (!(rho > 0.0) || !isfinite(rho)) { broke = 1; break; }
+        while (it < maxit) {
+            orc_csr_spmv(n, Ap, Aj, Ax, 1.0, p, 0.0, q);
+            double pq = dot(n, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { broke = 1; break; }
+            double alpha = rho / pq;
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            ++it;
+            if (nrm2(n, r) / bnorm <= rtol) break;
+            apply_prec(n, LUp, LUj, LUx, r, z, tmp);
+            double rho_new = dot(n, r, z);
+            if (!(rho_new > 0.0) || !isfinite(rho_new)) { broke = 1; break; }
+            double beta = rho_new / rho;
+            for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            rho = rho_new;
+        }
+        relres = residual(n, Ap, Aj, Ax, b, x, r) / bnorm;
+        if (relres > rtol) {
+            if (broke) break;
+            ++restarts;
+        }
+    }
+    int status = relres <= rtol ? ORC_OK : broke ? ORC_BREAKDOWN : ORC_NOT_CONVERGED;
+    *iters_out = it;
+    *relres_out = relres;
+    free(r); free(z); free(p); free(q); free(tmp);
+    return status;
+}
