@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--cpu-sample-iters", type=int, default=30)
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
-                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "copy"],
+                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "iluk", "copy"],
                    help="diffusion128 is the benchmark line; the others print extra records "
                         "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
@@ -405,6 +405,39 @@ def extra(args):
             log(f"[bench] ras {row}")
             del F, lv
         out.update({"n": A.n, "nnz": A.nnz, "ras": rows})
+    elif args.workload == "iluk":
+        # Table 4 shape: 3D Poisson 150^3 (3,375,000 rows, 23,490,000 nonzeros), ILU(k) for k = 0..3,
+        # GMRES(30), BiCGSTAB and CG to 1e-8 from x0 = 0, b = A x_true
+        A = synth.poisson3d(150)
+        xt = np.random.default_rng(7).uniform(-1, 1, A.n)
+        Mh = hec.hec_from_csr(A)
+        xd = torch.from_numpy(xt).to(dev)
+        b = torch.empty_like(xd)
+        hec.hec_spmv(Mh, xd, b)
+        rows = []
+        for k in range(4):
+            ts = time.time()
+            F = hec.ilu_factor(A, k=k)
+            lv = hec.level_schedule(F)
+            t_setup = time.time() - ts
+            li = hec.levels_info(lv)
+            z = torch.empty_like(b)
+            t_lu = time_launches(lambda: hec.trsv_levels(F, lv, b, z, hec.LU), 10, stream)
+            row = {"k": k, "nnz_lu": hec.ilu_info(F)["nnz"], "levels": li["nlev_lower"], "setup_s": round(t_setup, 2),
+                   "trsv_lu_us": round(t_lu * 1e6, 1)}
+            for name, fn in (("gmres", lambda xx: hec.gmres_solve(Mh, F, lv, b, xx, restart=30, rtol=1e-8)),
+                             ("bicgstab", lambda xx: hec.bicgstab_solve(Mh, F, lv, b, xx, rtol=1e-8)),
+                             ("cg", lambda xx: hec.cg_solve(Mh, F, lv, b, xx, rtol=1e-8))):
+                x = torch.empty_like(b)
+                fn(x)
+                t1 = time.time()
+                inf = fn(x)
+                row[name] = {"iterations": inf["iterations"], "seconds": round(time.time() - t1, 4),
+                             "rel_res": inf["rel_res_true"]}
+            rows.append(row)
+            log(f"[bench] iluk {row}")
+            del F, lv
+        out.update({"n": A.n, "nnz": A.nnz, "iluk": rows})
     elif args.workload == "copy":
         nbytes = 1 << 30
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)

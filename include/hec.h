@@ -247,6 +247,18 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
                                const hec_levels *lv, const double *const *b, double *const *x,
                                const hec_solve_opts *opts, hec_solve_info *info, void *stream);
 
+/* Preconditioned conjugate gradient (Sec. 2.7 lists CG among the Krylov solvers;
+ * the steps are the textbook ones): r = b - A x, z = M^{-1} r, p = z, then per
+ * iteration q = A p, alpha = (r, z) / (p, q), x += alpha p, r -= alpha q,
+ * z = M^{-1} r, p = z + beta p with beta = (r, z)_new / (r, z)_old. For symmetric
+ * positive definite A and M = LU (an ILU(k) of an SPD M-matrix with a symmetric
+ * pattern, e.g. a 3D Poisson matrix). Stops when ||r|| / ||b|| <= rtol by the
+ * recurrence, confirmed by the FP64 true residual (restarting from x, at most 3
+ * times, if it disagrees). (r, z) <= 0 or (p, A p) <= 0 is HEC_ERR_BREAKDOWN.
+ * FP64 only (precision must be 0); opts->restart is ignored. */
+hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                    const hec_solve_opts *opts, hec_solve_info *info, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *hec_last_error(void);
 

@@ -42,7 +42,7 @@ enum : int { SI_DONE = 0, SI_JDONE = 1, SI_BREAK = 2, SI_STOP_S = 3, SI_ITERS = 
 enum : int {
     SD_BNORM = 0, SD_TOL = 1, SD_BETA = 2, SD_HNEXT = 3, SD_RES = 4,  // GMRES
     SD_RHO = 5, SD_RHO_PREV = 6, SD_ALPHA = 7, SD_OMEGA = 8,       // BiCGSTAB
-    SD_SNORM2 = 9, SD_RNORM2 = 10,
+    SD_SNORM2 = 9, SD_RNORM2 = 10, SD_CGBETA = 11,                 // CG: beta
     SD_SCALARS = 16
 };
 
@@ -514,6 +514,108 @@ struct OpBiXR : NoInit {
 
 // Mapped pinned flag blocks are recycled: freeing pinned host memory can
 // synchronise the whole device, which would stall other streams' solves.
+// ---------------------------------------------------------------- CG ops (Sec. 2.7, preconditioned CG)
+
+// p = z, rho = (r, z), ||r||^2; start / restart. A non-positive rho (M not SPD) is a breakdown.
+struct OpCgStart : NoInit {
+    const double *r, *z;
+    double *p;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[2], double *) const {
+        const double zi = z[i], ri = r[i];
+        p[i] = zi;
+        acc[0] += ri * zi;
+        acc[1] += ri * ri;
+    }
+    __device__ void finish(const double *t) const {
+        sd[SD_RHO] = t[0];
+        sd[SD_RNORM2] = t[1];
+        int done = !(sqrt(t[1]) > sd[SD_TOL]);
+        si[SI_DONE] = done;
+        si[SI_BREAK] = 0;
+        si[SI_JDONE] = 0;  // iterations in this run
+        mirror(hf, SI_DONE, done);
+        mirror(hf, SI_BREAK, 0);
+        mirror(hf, SI_JDONE, 0);
+        if (!done && !(t[0] > 0.0 && isfinite(t[0]))) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+        }
+    }
+};
+
+// alpha = rho / (p, q); (p, q) <= 0 is a breakdown (A not SPD)
+struct OpCgAlpha : NoInit {
+    const double *p, *q;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const { acc[0] += p[i] * q[i]; }
+    __device__ void finish(const double *t) const {
+        if (!(t[0] > 0.0 && isfinite(t[0]))) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+            return;
+        }
+        sd[SD_ALPHA] = sd[SD_RHO] / t[0];
+    }
+};
+
+// x += alpha p, r -= alpha q, ||r||^2: stop when ||r|| <= tol
+struct OpCgUpdate : NoInit {
+    const double *p, *q;
+    double *x, *r;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const {
+        const double a = sd[SD_ALPHA];
+        x[i] = x[i] + a * p[i];
+        const double ri = r[i] - a * q[i];
+        r[i] = ri;
+        acc[0] += ri * ri;
+    }
+    __device__ void finish(const double *t) const {
+        sd[SD_RNORM2] = t[0];
+        si[SI_JDONE] += 1;
+        mirror(hf, SI_JDONE, si[SI_JDONE]);
+        if (!(sqrt(t[0]) > sd[SD_TOL]) || !isfinite(t[0])) {
+            si[SI_DONE] = 1;
+            mirror(hf, SI_DONE, 1);
+        }
+    }
+};
+
+// rho' = (r, z), beta = rho' / rho, rho = rho'
+struct OpCgRho : NoInit {
+    const double *r, *z;
+    double *sd;
+    int32_t *si, *hf;
+    __device__ void row(int64_t i, double (&acc)[1], double *) const { acc[0] += r[i] * z[i]; }
+    __device__ void finish(const double *t) const {
+        if (!(t[0] > 0.0 && isfinite(t[0]))) {
+            si[SI_DONE] = 1;
+            si[SI_BREAK] = 1;
+            mirror(hf, SI_DONE, 1);
+            mirror(hf, SI_BREAK, 1);
+            return;
+        }
+        sd[SD_CGBETA] = t[0] / sd[SD_RHO];
+        sd[SD_RHO] = t[0];
+    }
+};
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *z, double *p, const double *sd,
+                                              const int32_t *si) {
+    if (si[SI_DONE]) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + sd[SD_CGBETA] * p[i];
+}
+
 static std::mutex g_flag_mu;
 static std::vector<int32_t *> g_flag_pool;
 
@@ -856,6 +958,84 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
         if (!(res / bnorm <= o->rtol)) {
             if (broke) fail(HEC_ERR_BREAKDOWN, "BiCGSTAB breakdown (rho or (r0,v) == 0)");
             fail(HEC_ERR_NOT_CONVERGED, "BiCGSTAB did not reach the tolerance");
+        }
+    });
+    inf.status = st;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
+}
+
+hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x, const hec_solve_opts *o,
+                    hec_solve_info *info, void *stream) {
+    hec_solve_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+    hec_status st = guarded([&] {
+        check_solve_args(A, M, lv, b, x, o);
+        if (o->precision != 0) fail(HEC_ERR_INVALID_ARG, "CG runs in FP64 only");
+        hipStream_t s = as_stream(stream);
+        StreamScope scope(s);
+        const int64_t n = A->n;
+        if (n == 0) return;
+        KrylovWS &ws = get_ws(*A, 0, false, true, s);
+        const int64_t ldv = ws.ldv;
+        double *r = ws.r.get(), *z = ws.v6.get(), *p = z + ldv, *q = p + ldv;
+        double *sd = ws.sd.get();
+        int32_t *si = ws.si.get();
+        const double bnorm = vec_norm(ws, n, b, s);
+        if (bnorm == 0.0) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+            HEC_HIP(hipStreamSynchronize(s));
+            return;
+        }
+        if (o->x0_zero) {
+            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+            HEC_CHECK_LAUNCH();
+        }
+        set_scalar(ws, SD_TOL, o->rtol * bnorm, s);
+        double res = true_residual(*A, ws, b, x, s);  // r = b - A x
+        int it = 0, restarts = 0;
+        bool broke = false;
+        const unsigned g = ceil_div(n, 256);
+        while (res / bnorm > o->rtol && it < o->maxit && restarts <= 3) {
+            trsv_launch<double>(*lv, HEC_LU, r, z, s, nullptr);
+            launch_pass<2>(ws, n, OpCgStart{{}, r, z, p, sd, si, ws.dflags}, 2, s, nullptr);
+            HEC_HIP(hipStreamSynchronize(s));
+            broke = hf(ws)[SI_BREAK] != 0;
+            if (!hf(ws)[SI_DONE]) {
+                const int32_t *done = si + SI_DONE;
+                for (int k = 0; it + k < o->maxit; ++k) {
+                    if (k >= 2) {  // wait for iteration k-2, keep k-1 queued
+                        HEC_HIP(hipEventSynchronize(ws.ev[k % 2]));
+                        if (hf(ws)[SI_DONE]) break;
+                    }
+                    spmv_launch<double, double, double>(*A, 1.0, p, 0.0, q, q, s, done);
+                    launch_pass<1>(ws, n, OpCgAlpha{{}, p, q, sd, si, ws.dflags}, 1, s, done);
+                    launch_pass<1>(ws, n, OpCgUpdate{{}, p, q, x, r, sd, si, ws.dflags}, 1, s, done);
+                    trsv_launch<double>(*lv, HEC_LU, r, z, s, done);
+                    launch_pass<1>(ws, n, OpCgRho{{}, r, z, sd, si, ws.dflags}, 1, s, done);
+                    k_cg_p<<<g, 256, 0, s>>>(n, z, p, sd, si);
+                    HEC_CHECK_LAUNCH();
+                    HEC_HIP(hipEventRecord(ws.ev[k % 2], s));
+                }
+                HEC_HIP(hipStreamSynchronize(s));
+                it += hf(ws)[SI_JDONE];
+                broke = hf(ws)[SI_BREAK] != 0;
+            }
+            inf.rel_res_est = std::sqrt(read_scalar(ws, SD_RNORM2, s)) / bnorm;
+            res = true_residual(*A, ws, b, x, s);
+            if (res / bnorm > o->rtol) {
+                if (broke) break;
+                ++restarts;
+            }
+        }
+        inf.iterations = it;
+        inf.restarts = restarts;
+        inf.rel_res_true = res / bnorm;
+        if (!(res / bnorm <= o->rtol)) {
+            if (broke) fail(HEC_ERR_BREAKDOWN, "CG breakdown ((r, z) or (p, A p) not positive)");
+            fail(HEC_ERR_NOT_CONVERGED, "CG did not reach the tolerance");
         }
     });
     inf.status = st;

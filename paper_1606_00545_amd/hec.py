@@ -25,7 +25,7 @@ LOWER, UPPER, LU = 1, 2, 3
 EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "ilu_factor", "ilu_factor_ras", "ilu_info", "ilu_ras_export", "ilu_export", "ilu_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
-            "trsv_levels", "gmres_solve", "bicgstab_solve",
+            "trsv_levels", "gmres_solve", "bicgstab_solve", "cg_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched", "hec_last_error")
 BATCH_MAX_N = 8192
 
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
     L.trsv_levels.argtypes = [_vp, _vp, C.c_uint32, C.c_int, _vp, _vp, _vp]
     L.gmres_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _vp]
     L.bicgstab_solve.argtypes = L.gmres_solve.argtypes
+    L.cg_solve.argtypes = L.gmres_solve.argtypes
     L.batch_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_vp)]
     L.batch_destroy.argtypes = [_vp]
     L.gmres_solve_batched.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts),
@@ -335,6 +336,18 @@ def bicgstab_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, r
                                  C.byref(o), C.byref(info), _stream(stream))
     if check and code != OK:
         _check(code, "bicgstab_solve")
+    return info.as_dict()
+
+
+def cg_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, rtol: float = 1e-8,
+             x0_zero: bool = True, stream=None, check: bool = True) -> dict:
+    import torch
+    o = _opts(1, maxit, rtol, 0, x0_zero, 0.0, 0.0)
+    info = SolveInfo()
+    code = load().cg_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+                           C.byref(o), C.byref(info), _stream(stream))
+    if check and code != OK:
+        _check(code, "cg_solve")
     return info.as_dict()
 
 

@@ -139,3 +139,34 @@ def test_solves_are_deterministic():
         hec.gmres_solve(Mh, F, lv, dev(b), x)
         outs.append(host(x))
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+
+
+@pytest.mark.parametrize("kind,k", [("poisson3d_24", 0), ("poisson3d_24", 2), ("tpfa3d_24", 1), ("poisson2d_64", 0)])
+def test_cg_matches_oracle(kind, k):
+    if kind == "poisson3d_24":
+        A = synth.poisson3d(24)
+        xt = np.random.default_rng(31).uniform(-1, 1, A.n)
+        b = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, xt)
+    else:
+        A, xt, b = _system(kind)
+    Fo = O.iluk(A.n, A.Ap, A.Aj, A.Ax, k)
+    ro = O.cg(A, Fo, b, rtol=1e-8)
+    Mh, F, lv = _setup(A, k)
+    x = empty(A.n)
+    info = hec.cg_solve(Mh, F, lv, dev(b), x, rtol=1e-8)
+    x = host(x)
+    rr = _rel_res(A, x, b)
+    print(f"cg {kind} k={k}: gpu it={info['iterations']} oracle it={ro.iterations} res={rr:.2e}")
+    assert ro.status == O.OK and info["status"] == hec.OK and rr <= 1e-8
+    assert abs(info["iterations"] - ro.iterations) <= max(2, ro.iterations // 20)
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-5
+
+
+def test_cg_breakdown_on_indefinite_system():
+    from tests._mats import from_dense
+    D = np.diag(np.r_[np.full(50, 2.0), np.full(50, -2.0)])  # symmetric indefinite, exact LU = D
+    A = from_dense(D)
+    Mh, F, lv = _setup(A, 0)
+    b = np.ones(100)
+    with pytest.raises(hec.HecError):
+        hec.cg_solve(Mh, F, lv, dev(b), empty(100), rtol=1e-10)
