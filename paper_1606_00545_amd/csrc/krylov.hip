@@ -1,17 +1,17 @@
-// Krylov solvers (Sec. 2.7): restarted right-preconditioned GMRES(m) and
-// BiCGSTAB (Alg. 4), built from the vector operations of Sec. 2.3 (Eq. (2)-(6)),
-// the HEC SpMV and the level-scheduled preconditioner solve.
+// Krylov solvers (Sec. 2.7): restarted right-preconditioned GMRES(m),
+// BiCGSTAB (Alg. 4) and preconditioned CG, built from the vector operations of
+// Sec. 2.3 (Eq. (2)-(6)), the HEC SpMV and the level-scheduled preconditioner solve.
 //
 // Every scalar of the methods (rho, alpha, omega, the Hessenberg matrix, the
 // Givens rotations, the residual estimate, the convergence flags) lives in
-// device memory and is produced by the last workgroup of the reduction that
-// needs it, so an iteration is a fixed sequence of stream-ordered launches with
-// no host round trip. Once the device sets the "done" flag, the remaining
+// device memory and is produced by the one-workgroup finishing launch of the
+// reduction that needs it, so an iteration is a fixed sequence of stream-ordered
+// launches with no host round trip. Once the device sets the "done" flag, the remaining
 // launches of the sequence return at entry. The host looks at the flag through
 // mapped pinned memory one iteration behind the device.
 //
 // Reductions are deterministic: the grid size depends only on n, each
-// workgroup sums a fixed set of rows in a fixed order, and the last workgroup
+// workgroup sums a fixed set of rows in a fixed order, and the finishing launch
 // combines the per-workgroup partial sums in a fixed order.
 #include <algorithm>
 #include <chrono>
@@ -88,16 +88,17 @@ __device__ __forceinline__ void block_sum(const double (&acc)[NV], int nv, doubl
 }
 
 // Generic fused pass: every row i runs op.row(i, acc) (which may also update
-// vectors), the NV sums are reduced deterministically and the last workgroup
-// calls op.finish(totals) on one thread.
+// vectors) and each workgroup writes its NV partial sums; k_pass_finish (one
+// workgroup, launched right after) adds them in a fixed order and calls
+// op.finish(totals) on one thread. Two launches instead of a last-workgroup
+// handshake: a device-scope fence and counter per workgroup costs about 20 ns
+// each, serialised over the grid.
 template <int NV, class Op>
-__global__ __launch_bounds__(RB) void k_pass(int64_t n, Op op, int nv, double *part, uint32_t *counter,
-                                             const int32_t *skip) {
+__global__ __launch_bounds__(RB) void k_pass(int64_t n, Op op, int nv, double *part, const int32_t *skip) {
     if (skip && *skip) return;
     __shared__ double red[4 * NV];
     __shared__ double tot[NV];
     __shared__ double sh[kMaxRestart + 1];
-    __shared__ bool last;
     op.init(sh);
     __syncthreads();
     double acc[NV];
@@ -106,27 +107,25 @@ __global__ __launch_bounds__(RB) void k_pass(int64_t n, Op op, int nv, double *p
     const int64_t stride = (int64_t)gridDim.x * RB;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) op.row(i, acc, sh);
     block_sum<NV>(acc, nv, red, tot);
-    if (threadIdx.x < nv) {
-        part[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
-        __threadfence();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (threadIdx.x < nv) part[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
+}
+
+template <int NV, class Op>
+__global__ __launch_bounds__(RB) void k_pass_finish(Op op, int nv, const double *part, int nblocks,
+                                                    const int32_t *skip) {
+    if (skip && *skip) return;
+    __shared__ double red[4 * NV];
+    __shared__ double tot[NV];
+    double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB) {
+    for (int b = threadIdx.x; b < nblocks; b += RB) {
 #pragma unroll
         for (int k = 0; k < NV; ++k)
             if (k < nv) acc[k] += part[(size_t)b * NV + k];
     }
     block_sum<NV>(acc, nv, red, tot);
-    if (threadIdx.x == 0) {
-        op.finish(tot);
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) op.finish(tot);
 }
 
 __device__ __forceinline__ void mirror(int32_t *hostflags, int idx, int32_t v) {
@@ -217,17 +216,13 @@ __device__ void givens_finish(int j, double hn, double *sd, int32_t *si, int32_t
 // through LDS; every sum is reduced in a fixed order (deterministic).
 template <class VT, int MODE>
 __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V, int64_t ldv, VT *w, int nv,
-                                            const double *__restrict__ hin, double *hout, double *part,
-                                            uint32_t *counter, const int32_t *skip, double *sd, int32_t *si,
-                                            int32_t *hf, GLayout L) {
+                                            const double *__restrict__ hin, double *part, const int32_t *skip) {
     constexpr int KW = kMaxRestart / 4;  // vectors per wavefront
     constexpr int NS = kMaxRestart + 1;  // sums per workgroup: nv dots (+ the norm)
     if (skip && *skip) return;
     __shared__ double sh[kMaxRestart];
     __shared__ double px[4][64];
     __shared__ double red[NS];
-    __shared__ double wred[4][NS];
-    __shared__ bool last;
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     if (MODE != 1 && (int)threadIdx.x < nv) sh[threadIdx.x] = hin[threadIdx.x];
     __syncthreads();
@@ -283,30 +278,58 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
     }
     __syncthreads();
     const int lo = MODE == 3 ? kMaxRestart : 0, hi = MODE == 3 ? kMaxRestart + 1 : nv;
-    if ((int)threadIdx.x >= lo && (int)threadIdx.x < hi) {
-        part[(size_t)blockIdx.x * NS + threadIdx.x] = red[threadIdx.x];
-        __threadfence();
+    // partial sums stored sum-major (part[k * grid + block]) so the finishing launch reads them coalesced
+    if ((int)threadIdx.x >= lo && (int)threadIdx.x < hi)
+        part[(size_t)(threadIdx.x - lo) * gridDim.x + blockIdx.x] = red[threadIdx.x];
+}
+
+// The grid's sums of a k_cgs pass in a fixed order (one workgroup, launched right
+// after it): MODE 1/2 write the nv dot products, MODE 3 takes the Givens step.
+template <int MODE>
+__global__ __launch_bounds__(RB) void k_cgs_finish(int nv, const double *part, int nblocks, double *hout,
+                                                   const int32_t *skip, double *sd, int32_t *si, int32_t *hf,
+                                                   GLayout L) {
+    constexpr int KW = kMaxRestart / 4;           // sums per wavefront
+    constexpr int NR = kMaxRedBlocks / 64;        // partials per lane and sum
+    if (skip && *skip) return;
+    __shared__ double tot[kMaxRestart];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int cnt = MODE == 3 ? 1 : nv;
+    // wavefront q adds sums k = q, q+4, ...; its lanes stride over the workgroups'
+    // partials (contiguous per sum), all loads issued before the additions
+    double acc[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = q + 4 * u;
+        double a = 0.0;
+        // unconditional loads from clamped (in-bounds) addresses, so that all of them
+        // are in flight together; out-of-range terms add zero
+        const int kc = k < cnt ? k : 0;
+        double v[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int b = lane + 64 * r;
+            v[r] = part[(size_t)kc * nblocks + (b < nblocks ? b : 0)];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) a += (k < cnt && lane + 64 * r < nblocks) ? v[r] : 0.0;
+        acc[u] = a;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // the last workgroup: sum the partial sums over workgroups in a fixed order
-    for (int k = lo + q; k < hi; k += 4) {
-        double s = 0.0;
-        for (int b = lane; b < (int)gridDim.x; b += 64) s += part[(size_t)b * NS + k];
-        s = wave_sum(s);
-        if (lane == 0) wred[0][k] = s;
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = q + 4 * u;
+        if (k < cnt) {
+            const double v = wave_sum(acc[u]);
+            if (lane == 0) tot[k] = v;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         if constexpr (MODE == 3) {
-            givens_finish(nv - 1, sqrt(wred[0][kMaxRestart]), sd, si, hf, L);
+            givens_finish(nv - 1, sqrt(tot[0]), sd, si, hf, L);
         } else {
-            for (int k = 0; k < nv; ++k) hout[k] = wred[0][k];
+            for (int k = 0; k < nv; ++k) hout[k] = tot[k];
         }
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -650,7 +673,6 @@ struct KrylovWS {
     DevBuf<double> sd;           // scalars + Hessenberg
     DevBuf<int32_t> si;
     DevBuf<double> part;         // partial sums, nred x kMaxRestart
-    DevBuf<uint32_t> counter;
     int32_t *hflags = nullptr;   // mapped pinned mirror of si
     int32_t *dflags = nullptr;   // its device address
     std::vector<hipEvent_t> ev;
@@ -694,8 +716,6 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     nw->sd.alloc(std::max(L.total, SD_SCALARS + 8));
     nw->si.alloc(SI_COUNT);
     nw->part.alloc((size_t)nw->nred * (kMaxRestart + 1));
-    nw->counter.alloc(1);
-    HEC_HIP(hipMemsetAsync(nw->counter.get(), 0, sizeof(uint32_t), s));
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
     nw->hflags = take_flags();
     std::memset(nw->hflags, 0, SI_COUNT * sizeof(int32_t));
@@ -709,7 +729,9 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
 
 template <int NV, class Op>
 static void launch_pass(KrylovWS &ws, int64_t n, const Op &op, int nv, hipStream_t s, const int32_t *skip) {
-    k_pass<NV, Op><<<ws.nred, RB, 0, s>>>(n, op, nv, ws.part.get(), ws.counter.get(), skip);
+    k_pass<NV, Op><<<ws.nred, RB, 0, s>>>(n, op, nv, ws.part.get(), skip);
+    HEC_CHECK_LAUNCH();
+    k_pass_finish<NV, Op><<<1, RB, 0, s>>>(op, nv, ws.part.get(), ws.nred, skip);
     HEC_CHECK_LAUNCH();
 }
 
@@ -755,14 +777,18 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
         spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
         const int nv = j + 1;
         const unsigned g = ws.nred;
-        k_cgs<VT, 1><<<g, RB, 0, s>>>(n, V, ldv, w, nv, nullptr, sd + L.h1, ws.part.get(), ws.counter.get(),
-                                      done, sd, si, ws.dflags, L);
+        double *part = ws.part.get();
+        k_cgs<VT, 1><<<g, RB, 0, s>>>(n, V, ldv, w, nv, nullptr, part, done);
         HEC_CHECK_LAUNCH();
-        k_cgs<VT, 2><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h1, sd + L.h2, ws.part.get(), ws.counter.get(),
-                                      done, sd, si, ws.dflags, L);
+        k_cgs_finish<1><<<1, RB, 0, s>>>(nv, part, g, sd + L.h1, done, sd, si, ws.dflags, L);
         HEC_CHECK_LAUNCH();
-        k_cgs<VT, 3><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h2, nullptr, ws.part.get(), ws.counter.get(),
-                                      done, sd, si, ws.dflags, L);
+        k_cgs<VT, 2><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h1, part, done);
+        HEC_CHECK_LAUNCH();
+        k_cgs_finish<2><<<1, RB, 0, s>>>(nv, part, g, sd + L.h2, done, sd, si, ws.dflags, L);
+        HEC_CHECK_LAUNCH();
+        k_cgs<VT, 3><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h2, part, done);
+        HEC_CHECK_LAUNCH();
+        k_cgs_finish<3><<<1, RB, 0, s>>>(nv, part, g, nullptr, done, sd, si, ws.dflags, L);
         HEC_CHECK_LAUNCH();
         if (j + 1 < mcyc) {
             k_scale_next<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, w, V + (j + 1) * ldv, sd, done);
