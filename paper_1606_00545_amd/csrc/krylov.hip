@@ -116,13 +116,22 @@ __global__ __launch_bounds__(RB) void k_pass_finish(Op op, int nv, const double 
     if (skip && *skip) return;
     __shared__ double red[4 * NV];
     __shared__ double tot[NV];
+    // all partials of this thread loaded at once from in-bounds addresses, then added in order
+    constexpr int NR = kMaxRedBlocks / RB;
+    double v[NR][NV];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int b = threadIdx.x + r * RB;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[r][k] = part[(size_t)(b < nblocks ? b : 0) * NV + k];
+    }
     double acc[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += RB) {
+    for (int k = 0; k < NV; ++k) {
+        acc[k] = 0.0;
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) acc[k] += part[(size_t)b * NV + k];
+        for (int r = 0; r < NR; ++r)
+            if (threadIdx.x + r * RB < nblocks && k < nv) acc[k] += v[r][k];
     }
     block_sum<NV>(acc, nv, red, tot);
     if (threadIdx.x == 0) op.finish(tot);
