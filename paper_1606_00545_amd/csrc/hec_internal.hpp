@@ -186,6 +186,7 @@ struct hec_tri {
     std::vector<int32_t> hlevel_ptr, hperm;  // Alg. 3: level start pointers, rows by (level, row)
     hec_flat flat;                           // small systems only: level-ordered copy for the batched solver
     int32_t K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 0, S = 0;  // KC: K padded to 4/8/16/32
+    int32_t NS = 1;                          // solver wavefronts per workgroup
     int32_t D64 = 0, D32 = 0;                // ring depths for the FP64 / FP32 solve
     bool blocked = true;                     // false: rows too long for LDS slots, per-row polling kernel
     int32_t nchunks = 0;                     // fallback plan: 64-row chunks of one level
@@ -194,12 +195,13 @@ struct hec_tri {
     hec::DevBuf<int32_t> part_ss;   // nparts+1: sub-segment range of each part
     hec::DevBuf<int32_t> part_pos;  // nparts+1: first position of each part
     hec::DevBuf<int32_t> ss_pos;    // nss+1: first position of each sub-segment
+    hec::DevBuf<int32_t> ss_need;   // nss (NS > 1): dependency bound of each sub-segment in its part
     hec::DevBuf<int32_t> grow;      // position -> row
     std::vector<int32_t> hgrow;     // host copy of grow
     hec::DevBuf<int32_t> other;     // lower: the row's position in the upper plan; upper with RAS: the
                                     // system row an owned stacked row is written to (-1: overlap row)
     hec::DevBuf<int32_t> bmap;      // lower with RAS: the system row whose right-hand side a position reads
-    hec::DevBuf<int32_t> enc;       // K*ldq: -(local position+1) inside the part, row outside, INT_MIN pad
+    hec::DevBuf<int32_t> enc;       // K*ldq: -(local position+1) inside the part, position outside, INT_MIN pad
     hec::DevBuf<double> val;
     hec::DevBuf<float> val32;
     hec::DevBuf<double> piv;        // upper only: u_ii per position
@@ -210,12 +212,14 @@ struct hec_levels_s {
     int32_t n = 0;    // system size (vectors the caller passes)
     int32_t nf = 0;   // factor size (the stacked extended blocks for RAS)
     bool ras = false;
-    hec::DevBuf<double> xh64;  // RAS: the upper solve's output over the stacked rows
-    hec::DevBuf<float> xh32;
     hec_tri lower, upper;
-    hec::DevBuf<uint32_t> sync;            // part tickets + finished-workgroup counters
-    hec::DevBuf<double> y64, yp64;   // y = L^{-1} b by row (sentinel-filled between solves), y in upper order
-    hec::DevBuf<float> y32, yp32;
+    hec::DevBuf<uint32_t> sync;  // part tickets + finished-workgroup counters
+    // Internal vectors over the factor's rows. qL/qU: each triangle's results in its own
+    // plan's position order, the copy dependent rows poll (qL is sentinel-filled between
+    // solves; qU is filled by every lower launch, or before a lone upper solve). yp:
+    // L^{-1} b in the upper plan's order, the upper solve's right-hand side.
+    hec::DevBuf<double> qL64, qU64, yp64;
+    hec::DevBuf<float> qL32, qU32, yp32;
 };
 
 namespace hec {

@@ -364,13 +364,13 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         }
         lv->sync.alloc(4);
         HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, 4 * sizeof(uint32_t), s));
-        lv->y64.alloc(M->n);
+        lv->qL64.alloc(M->n);
+        lv->qU64.alloc(M->n);
         lv->yp64.alloc(M->n);
-        if (lv->ras) lv->xh64.alloc(M->n);
         if (M->has_f32) {
-            lv->y32.alloc(M->n);
+            lv->qL32.alloc(M->n);
+            lv->qU32.alloc(M->n);
             lv->yp32.alloc(M->n);
-            if (lv->ras) lv->xh32.alloc(M->n);
         }
         trsv_init_levels(*lv, s);
         HEC_HIP(hipStreamSynchronize(s));
@@ -418,7 +418,7 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
         if (prec == HEC_F64) {
             trsv_launch<double>(*lv, which, (const double *)b, (double *)x, s);
         } else if (prec == HEC_F32) {
-            if (!M->has_f32 || (!lv->y32.get() && lv->n > 0))
+            if (!M->has_f32 || (!lv->qL32.get() && lv->n > 0))
                 fail(HEC_ERR_INVALID_ARG, "factor has no FP32 copy (HEC_KEEP_F32)");
             trsv_launch<float>(*lv, which, (const float *)b, (float *)x, s);
         } else {

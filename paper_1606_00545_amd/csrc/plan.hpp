@@ -36,10 +36,20 @@ constexpr int kPad = INT_MIN;     // padding entry of a row shorter than K
 #ifndef HEC_TRSV_MAX_RING
 #define HEC_TRSV_MAX_RING 32
 #endif
+#ifndef HEC_TRSV_SOLVERS
+#define HEC_TRSV_SOLVERS 1
+#endif
+#ifndef HEC_TRSV_TILE
+#define HEC_TRSV_TILE 0
+#endif
 constexpr int kTargetParts = HEC_TRSV_TARGET_PARTS;  // contiguous parts: about this many ...
 constexpr int kMinPartRows = HEC_TRSV_MIN_PART_ROWS;  // ... of at least this many rows
-constexpr int kTileParts = HEC_TRSV_TILE_PARTS;      // grid tiles: about one per compute unit
+constexpr int kTileParts = HEC_TRSV_TILE_PARTS;      // grid tiles: at most about this many
 constexpr int kMaxRing = HEC_TRSV_MAX_RING;          // most LDS slots in the ring
+constexpr int kMaxSolvers = 8;                       // solver wavefronts per workgroup: 1, 2, 4 or 8 ...
+constexpr int kSolvers = HEC_TRSV_SOLVERS;           // ... the kernels are built for (the planner's default)
+constexpr int kTile = HEC_TRSV_TILE;                 // grid tile side (0: from the solver count)
+static_assert(kSolvers == 1 || kSolvers == 2 || kSolvers == 4 || kSolvers == 8, "solver count");
 
 HEC_HD constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
@@ -58,14 +68,16 @@ struct Slot {
     HEC_HD size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
 };
 
-// LDS: [filled[D] | consumed | part | zero (16 B)] [part's sub-segment starts,
-//      S+1] [ring of recent results, W] [D slots]
-HEC_HD inline size_t ctrl_head(int D) { return align16((size_t)(D + 2) * sizeof(int)) + 16; }
-HEC_HD inline size_t ctrl_bytes(int D, int S) { return ctrl_head(D) + align16((size_t)(S + 1) * sizeof(int)); }
+// LDS: [done[kMaxSolvers] | filled[D] | part | zero (16 B)] [part's sub-segment
+//      starts, S+1] [their dependency bounds, S+1, with NS > 1 only] [ring of
+//      recent results, W] [D slots]
+HEC_HD inline size_t ctrl_head(int D) { return align16((size_t)(kMaxSolvers + D + 1) * sizeof(int)) + 16; }
+HEC_HD inline size_t ss_bytes(int S) { return align16((size_t)(S + 1) * sizeof(int)); }
+HEC_HD inline size_t ctrl_bytes(int D, int S, int NS) { return ctrl_head(D) + (NS > 1 ? 2 : 1) * ss_bytes(S); }
 
 template <class T, bool UPPER>
-size_t lds_bytes(int KC, int W, int D, int S) {
-    return ctrl_bytes(D, S) + align16((size_t)W * sizeof(T)) + (size_t)D * Slot<T, UPPER>{KC}.bytes();
+size_t lds_bytes(int KC, int W, int D, int S, int NS) {
+    return ctrl_bytes(D, S, NS) + align16((size_t)W * sizeof(T)) + (size_t)D * Slot<T, UPPER>{KC}.bytes();
 }
 
 // Eq. (11): level of each row, 0-based, for the strict lower (upper == false)
@@ -150,25 +162,33 @@ inline void detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t
 //  * Positions: each part's rows at consecutive positions, by (level, row).
 //  * Sub-segments: runs of one level inside a part, at most kSub rows.
 //  * enc[s*ldq + q]: the dependency of entry s of position q: -(local position
-//    + 1) inside the part, the row itself outside it, kPad for padding.
-//  * W: size of the ring of recent results (a power of two that spans the
-//    longest distance from a row to an in-part dependency, plus kSub).
+//    + 1) inside the part, its position outside it (its row in a flat plan),
+//    kPad for padding.
+//  * NS: solver wavefronts per workgroup. With NS > 1 they take a part's
+//    sub-segments round-robin, and sub-segment t starts once every sub-segment
+//    of its part below ss_need[t] (relative to the part's first one, one past
+//    the last holding a dependency of t) is solved. NS > 1 is chosen when a
+//    part's levels span several sub-segments on average.
+//  * W: size of the ring of recent results, a power of two that spans the
+//    longest distance from a row to an in-part dependency, plus kSub; with
+//    NS > 1 also wide enough that the results of a sub-segment never replace
+//    an entry that a sub-segment which may still run reads.
 //  * D64/D32: LDS ring depth for the FP64/FP32 solves; 0 when the plan does not
 //    fit in LDS (more than 32 entries per row): then blocked == false and the
 //    solve polls every dependency (level-order positions in 64-row chunks).
 //    flat == true asks for that level-order layout directly.
 struct HostPlan {
-    int32_t n = 0, nlev = 0, K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 64, S = 0, D64 = 0, D32 = 0;
+    int32_t n = 0, nlev = 0, K = 0, KC = 4, ldq = 0, nparts = 0, nss = 0, W = 64, S = 0, D64 = 0, D32 = 0, NS = 1;
     bool blocked = false;
     size_t lds64 = 0, lds32 = 0;
     std::vector<int32_t> level_ptr, perm, lev;
-    std::vector<int32_t> part_ss, part_pos, ss_pos, grow, part_of, pos, chunks;
+    std::vector<int32_t> part_ss, part_pos, ss_pos, ss_need, grow, part_of, pos, chunks;
     std::vector<int32_t> enc, src, psrc;  // src/psrc: index into the factor's value array
 };
 
 inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                       int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P,
-                      bool flat = false, const std::vector<int32_t> *blocks = nullptr) {
+                      bool flat = false, const std::vector<int32_t> *blocks = nullptr, int solvers = kSolvers) {
     P = HostPlan();
     P.n = n;
     P.nlev = compute_levels(n, LUp, LUj, diag, upper, P.level_ptr, P.perm, &P.lev);
@@ -219,6 +239,9 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
             const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
             const int64_t plane = (int64_t)gnx * gny;
             int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
+            // a tile's levels (x + y + z = const inside it) hold up to T*T rows: about one
+            // sub-segment per solver wavefront
+            T = kTile > 0 ? kTile : std::max<int64_t>(T, std::lround(std::sqrt((double)kSub * solvers)));
             const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
             const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
             ntiles = PX * PY;
@@ -271,24 +294,64 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
             }
             P.part_ss[nparts] = (int32_t)P.ss_pos.size();
             P.ss_pos.push_back(n);
+            const int32_t nss = (int32_t)P.ss_pos.size() - 1;
+            std::vector<int32_t> ss_of(n);
+            for (int32_t t = 0; t < nss; ++t)
+                for (int32_t q = P.ss_pos[t]; q < P.ss_pos[t + 1]; ++q) ss_of[q] = t;
+            // in-part dependencies: longest distance, and per sub-segment the dependency
+            // bound and the lowest position read
+            P.ss_need.assign(nss, 0);
+            std::vector<int32_t> mindep(nss, INT_MAX);
             int64_t maxd = 0;
             for (int32_t i = 0; i < n; ++i) {
                 int32_t a, b;
                 deps(i, a, b);
+                const int32_t t = ss_of[pos[i]], t0 = P.part_ss[part_of[i]];
                 for (int32_t e = a; e < b; ++e) {
                     int32_t j = LUj[e];
-                    if (part_of[j] == part_of[i]) maxd = std::max<int64_t>(maxd, (int64_t)pos[i] - pos[j]);
+                    if (part_of[j] != part_of[i]) continue;
+                    maxd = std::max<int64_t>(maxd, (int64_t)pos[i] - pos[j]);
+                    P.ss_need[t] = std::max(P.ss_need[t], ss_of[pos[j]] - t0 + 1);
+                    mindep[t] = std::min(mindep[t], pos[j]);
                 }
             }
+            int64_t groups = 0;  // (part, level) pairs
+            for (int32_t p = 0; p < nparts; ++p)
+                for (int32_t t = P.part_ss[p]; t < P.part_ss[p + 1]; ++t)
+                    if (t == P.part_ss[p] || P.lev[grow[P.ss_pos[t]]] != P.lev[grow[P.ss_pos[t - 1]]]) ++groups;
+            P.NS = solvers > 1 && 2 * (int64_t)nss >= 3 * groups ? solvers : 1;
+            int64_t span = maxd + kSub;
+            if (P.NS > 1) {
+                // sub-segment t starts when all below its bound are solved, so those from
+                // the bound up to t - 1 may still run and read down to their lowest
+                // dependency: t's results must not wrap onto it (range minima by a sparse table)
+                std::vector<std::vector<int32_t>> mn(1, mindep);
+                for (int32_t h = 1; (2 << (h - 1)) <= nss; ++h) {
+                    const std::vector<int32_t> &lo = mn[h - 1];
+                    std::vector<int32_t> nx(nss - (1 << h) + 1);
+                    for (size_t t = 0; t < nx.size(); ++t) nx[t] = std::min(lo[t], lo[t + (1 << (h - 1))]);
+                    mn.push_back(std::move(nx));
+                }
+                for (int32_t p = 0; p < nparts; ++p)
+                    for (int32_t t = P.part_ss[p]; t < P.part_ss[p + 1]; ++t) {
+                        const int32_t a = P.part_ss[p] + P.ss_need[t];
+                        if (a >= t) continue;
+                        int h = 0;
+                        while ((2 << h) <= t - a) ++h;
+                        const int32_t lo = std::min(mn[h][a], mn[h][t - (1 << h)]);
+                        if (lo != INT_MAX) span = std::max<int64_t>(span, (int64_t)P.ss_pos[t + 1] - lo);
+                    }
+            }
             P.W = 64;
-            while (P.W < maxd + kSub) P.W *= 2;
+            while (P.W < span) P.W *= 2;
             P.S = 0;
             for (int32_t p = 0; p < nparts; ++p) P.S = std::max(P.S, P.part_ss[p + 1] - P.part_ss[p]);
             auto fit = [&](auto tag) {
                 using T = decltype(tag);
                 int best = 0;
-                for (int D = 4; D <= kMaxRing; ++D) {
-                    size_t bb = upper ? lds_bytes<T, true>(P.KC, P.W, D, P.S) : lds_bytes<T, false>(P.KC, P.W, D, P.S);
+                for (int D = std::max(4, P.NS); D <= kMaxRing; ++D) {
+                    size_t bb = upper ? lds_bytes<T, true>(P.KC, P.W, D, P.S, P.NS)
+                                      : lds_bytes<T, false>(P.KC, P.W, D, P.S, P.NS);
                     if ((int64_t)bb <= lds_max) best = D;
                 }
                 return best;
@@ -316,11 +379,15 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
                 P.chunks.push_back(std::min(q + kSub, P.level_ptr[l + 1]));
         P.part_ss.assign(2, 0);
         P.ss_pos.assign(1, 0);
+        P.ss_need.clear();
         P.nparts = 0;
+        P.NS = 1;
     }
     P.nss = (int32_t)P.ss_pos.size() - 1;
-    P.lds64 = upper ? lds_bytes<double, true>(P.KC, P.W, P.D64, P.S) : lds_bytes<double, false>(P.KC, P.W, P.D64, P.S);
-    P.lds32 = upper ? lds_bytes<float, true>(P.KC, P.W, P.D32, P.S) : lds_bytes<float, false>(P.KC, P.W, P.D32, P.S);
+    P.lds64 = upper ? lds_bytes<double, true>(P.KC, P.W, P.D64, P.S, P.NS)
+                    : lds_bytes<double, false>(P.KC, P.W, P.D64, P.S, P.NS);
+    P.lds32 = upper ? lds_bytes<float, true>(P.KC, P.W, P.D32, P.S, P.NS)
+                    : lds_bytes<float, false>(P.KC, P.W, P.D32, P.S, P.NS);
     const size_t slab = (size_t)K * P.ldq;
     P.enc.assign(slab, kPad);
     P.src.assign(slab, -1);
@@ -332,7 +399,9 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
         int32_t pstart = P.blocked ? P.part_pos[part_of[i]] : 0;
         for (int32_t e = a, s2 = 0; e < b; ++e, ++s2) {
             int32_t j = LUj[e];
-            P.enc[(size_t)s2 * P.ldq + q] = P.blocked && part_of[j] == part_of[i] ? -(pos[j] - pstart + 1) : j;
+            P.enc[(size_t)s2 * P.ldq + q] = P.blocked && part_of[j] == part_of[i] ? -(pos[j] - pstart + 1)
+                                             : flat                                   ? j
+                                                                                      : pos[j];
             P.src[(size_t)s2 * P.ldq + q] = e;
         }
         if (upper) P.psrc[q] = diag[i];

@@ -16,17 +16,21 @@ extern "C" {
 // positions; 0-based) with the grid sizes detected from A (all 0: none) and
 // lds_max bytes of LDS per workgroup; flat != 0 asks for the level-order layout;
 // blocks (nbounds entries, may be NULL): first rows of independent row blocks
-// followed by n, to be used as parts. Returns NULL on allocation failure.
+// followed by n, to be used as parts; solvers: solver wavefronts per workgroup
+// for parts with wide levels (1, 2, 4 or 8; 0: the library's default). Returns
+// NULL on allocation failure or a bad solver count.
 void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                    int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max, int32_t flat,
-                   const int32_t *blocks, int32_t nbounds) {
+                   const int32_t *blocks, int32_t nbounds, int32_t solvers) {
+    if (solvers == 0) solvers = hec::plan::kSolvers;
+    if (solvers != 1 && solvers != 2 && solvers != 4 && solvers != 8) return nullptr;
     HostPlan *P = new (std::nothrow) HostPlan();
     if (!P) return nullptr;
     try {
         std::vector<int32_t> bv;
         if (blocks && nbounds > 0) bv.assign(blocks, blocks + nbounds);
         hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P, flat != 0,
-                             bv.empty() ? nullptr : &bv);
+                             bv.empty() ? nullptr : &bv, solvers);
     } catch (...) {
         delete P;
         return nullptr;
@@ -34,18 +38,18 @@ void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int3
     return P;
 }
 
-// meta[0..15] = n, nlev, K, KC, ldq, nparts, nss, W, S, D64, D32, blocked,
-// lds64, lds32, kSub, kPad.
+// meta[0..16] = n, nlev, K, KC, ldq, nparts, nss, W, S, D64, D32, blocked,
+// lds64, lds32, kSub, kPad, NS.
 void hecplan_meta(const void *h, int64_t *meta) {
     const HostPlan &P = *(const HostPlan *)h;
-    const int64_t m[16] = {P.n, P.nlev, P.K, P.KC, P.ldq, P.nparts, P.nss, P.W, P.S, P.D64, P.D32,
+    const int64_t m[17] = {P.n, P.nlev, P.K, P.KC, P.ldq, P.nparts, P.nss, P.W, P.S, P.D64, P.D32,
                            P.blocked ? 1 : 0, (int64_t)P.lds64, (int64_t)P.lds32, hec::plan::kSub,
-                           hec::plan::kPad};
+                           hec::plan::kPad, P.NS};
     std::memcpy(meta, m, sizeof(m));
 }
 
 // Copies the named array (level_ptr, perm, lev, part_ss, part_pos, ss_pos,
-// grow, part_of, pos, chunks, enc, src, psrc) into dst when dst != NULL.
+// ss_need, grow, part_of, pos, chunks, enc, src, psrc) into dst when dst != NULL.
 // Returns its length, or -1 for an unknown name.
 int64_t hecplan_array(const void *h, const char *name, int32_t *dst) {
     const HostPlan &P = *(const HostPlan *)h;
@@ -56,6 +60,7 @@ int64_t hecplan_array(const void *h, const char *name, int32_t *dst) {
     else if (!std::strcmp(name, "part_ss")) v = &P.part_ss;
     else if (!std::strcmp(name, "part_pos")) v = &P.part_pos;
     else if (!std::strcmp(name, "ss_pos")) v = &P.ss_pos;
+    else if (!std::strcmp(name, "ss_need")) v = &P.ss_need;
     else if (!std::strcmp(name, "grow")) v = &P.grow;
     else if (!std::strcmp(name, "part_of")) v = &P.part_of;
     else if (!std::strcmp(name, "pos")) v = &P.pos;

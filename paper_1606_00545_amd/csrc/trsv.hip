@@ -22,13 +22,16 @@
 //    from a small LDS ring of recent results and dependencies outside it from
 //    the slot, and publishes each result to global memory. It never waits on
 //    global memory itself.
-//  * Readiness of a value across parts is the value itself: the output vector
-//    is pre-filled with a signalling-NaN bit pattern that arithmetic never
-//    produces; results are stored and polled with device-coherent (agent
-//    scope) accesses, so only single-location coherence is needed and no
-//    cache-wide fence is issued. In an L-then-U chain the lower launch fills
-//    the upper solve's output and the upper launch refills the lower solve's
-//    internal output for the next chain, so the chain is exactly two launches.
+//  * Readiness of a value across parts is the value itself: each triangle
+//    keeps an internal copy of its results in plan order, pre-filled with a
+//    signalling-NaN bit pattern that arithmetic never produces; results are
+//    stored to it and polled from it with device-coherent (agent scope)
+//    accesses, so only single-location coherence is needed and no cache-wide
+//    fence is issued. A sub-segment's results are 64 consecutive positions, so
+//    these stores are whole cache lines; the outputs by row (or in the other
+//    triangle's order) are plain stores. In an L-then-U chain the lower launch
+//    fills the upper solve's copy and the upper launch refills the lower one
+//    for the next chain, so the chain is exactly two launches.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -40,8 +43,8 @@ namespace hec {
 
 namespace {
 
-constexpr int kPrefetchWaves = 15;
-constexpr int kBlkThreads = 64 * (1 + kPrefetchWaves);
+constexpr int kWaves = 16;  // solver wavefronts first, then prefetching wavefronts
+constexpr int kBlkThreads = 64 * kWaves;
 constexpr int kBatch = 8;           // entries loaded per batch by a prefetcher lane
 using plan::kPad;
 using plan::kSub;
@@ -89,18 +92,19 @@ __device__ __forceinline__ T from_bits(typename Sentinel<T>::U u) {
 }
 
 // Vectors of one triangular solve. b: right-hand side, read at bmap[q] for
-// position q when bmap is given, else by row (b_by_row) or in plan order; x:
-// output by row (pre-filled with the sentinel); yother: optional second output,
-// written at the plan's per-position index (`other`, -1: not written) -- the
-// other triangle's plan order, or a caller's vector; fill: a vector of nfill
-// elements the kernel sets to the sentinel for the next solve (the output of the
-// other triangle of an L-then-U chain).
+// position q when bmap is given, else by row (b_by_row) or in plan order; xq:
+// the results in plan order, the copy dependent rows poll (pre-filled with the
+// sentinel); x: optional output by row; yother: optional output at the plan's
+// per-position index (`other`, -1: not written) -- the other triangle's plan
+// order, or a caller's vector; fill: a vector of nfill elements the kernel sets
+// to the sentinel for the next solve (the polled copy of the other triangle of
+// an L-then-U chain).
 template <class T>
 struct SolveIO {
     const T *b;
     const int32_t *bmap;
     int32_t b_by_row;
-    T *x, *yother, *fill;
+    T *xq, *x, *yother, *fill;
     int64_t nfill;
 };
 
@@ -115,18 +119,20 @@ __device__ __forceinline__ void fill_sentinel(const SolveIO<T> &io) {
 
 struct PlanArgs {
     int32_t nparts, K, ldq, W, D, S;  // S: most sub-segments in one part
-    const int32_t *part_ss, *part_pos, *ss_pos, *grow, *other, *enc;
+    const int32_t *part_ss, *part_pos, *ss_pos, *ss_need, *grow, *other, *enc;
 };
 
-// A value that is never the sentinel: the target of the polls of entries that
-// need none, so that every lane issues its loads together.
-__device__ double g_zero64 = 0.0;
-__device__ float g_zero32 = 0.0f;
-template <class T> __device__ __forceinline__ const T *zero_addr();
-template <> __device__ __forceinline__ const double *zero_addr<double>() { return &g_zero64; }
-template <> __device__ __forceinline__ const float *zero_addr<float>() { return &g_zero32; }
+// First poll of a dependency outside the part: only lanes whose entry has one
+// load (a lane-masked load); the others get 0, which is never the sentinel. (A
+// shared dummy address for those lanes would send a device-coherent load per
+// wavefront and entry to one cache line from every compute unit: a hot spot that
+// slows every access mapped to the same memory channel.)
+template <class T>
+__device__ __forceinline__ typename Sentinel<T>::U first_poll(const T *x, int e) {
+    return e >= 0 ? load_coherent(x + e) : (typename Sentinel<T>::U)0;
+}
 
-template <class T, bool UPPER, int KC>
+template <class T, bool UPPER, int KC, int NS>
 __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *__restrict__ val,
                                                           const T *__restrict__ piv, SolveIO<T> io,
                                                           uint32_t *sync, const int32_t *skip) {
@@ -134,79 +140,106 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
     constexpr U SENT = Sentinel<T>::bits;
     if (skip && *skip) return;  // uniform: no workgroup touches the counters
     fill_sentinel(io);
+    T *const xq = io.xq;
     T *const x = io.x;
     T *const yother = io.yother;
     extern __shared__ __align__(16) char smem[];
+    constexpr int NP = kWaves - NS;
     const int D = P.D, K = P.K, W = P.W;
-    int *filled = (int *)smem;
-    int *consumed = filled + D;
-    int *s_part = consumed + 1;
+    int *done = (int *)smem;  // per solver wavefront: the next sub-segment it solves
+    int *filled = done + plan::kMaxSolvers;
+    int *s_part = filled + D;
     const uint32_t zero_off = (uint32_t)(ctrl_head(D) - 16);
     int *sspos = (int *)(smem + ctrl_head(D));
-    const uint32_t sx_off = (uint32_t)ctrl_bytes(D, P.S);
+    int *ssneed = (int *)(smem + ctrl_head(D) + plan::ss_bytes(P.S));
+    const uint32_t sx_off = (uint32_t)ctrl_bytes(D, P.S, NS);
     T *sx = (T *)(smem + sx_off);
     const uint32_t slots_off = sx_off + (uint32_t)align16((size_t)W * sizeof(T));
     const Slot<T, UPPER> L{KC};
     const uint32_t sb = (uint32_t)L.bytes();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     if (threadIdx.x < 4) ((int *)(smem + zero_off))[threadIdx.x] = 0;
 
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) {
-            *s_part = (int)atomicAdd(&sync[0], 1u);
-            *consumed = 0;
-        }
+        if (threadIdx.x == 0) *s_part = (int)atomicAdd(&sync[0], 1u);
+        if ((int)threadIdx.x < plan::kMaxSolvers) done[threadIdx.x] = (int)threadIdx.x < NS ? (int)threadIdx.x : INT_MAX;
         if ((int)threadIdx.x < D) filled[threadIdx.x] = -1;
         __syncthreads();
         const int p = *s_part;
         if (p >= P.nparts) break;
         const int kb = P.part_ss[p], nss = P.part_ss[p + 1] - kb, pos0 = P.part_pos[p];
-        for (int t = threadIdx.x; t <= nss; t += blockDim.x) sspos[t] = P.ss_pos[kb + t];
+        for (int t = threadIdx.x; t <= nss; t += blockDim.x) {
+            sspos[t] = P.ss_pos[kb + t];
+            if constexpr (NS > 1)
+                if (t < nss) ssneed[t] = P.ss_need[kb + t];
+        }
         __syncthreads();
 
-        if (wave == 0) {
-            // ---------------- solver: one LDS round trip and KC fused multiply-adds per row.
-            // The next sub-segment's header and dependency addresses are read while the
-            // current one is computed (two register sets used alternately), so the only
-            // dependent LDS access of a step is the read of its dependencies' values.
+        if (wave < NS) {
+            // ---------------- solvers: one LDS round trip and KC fused multiply-adds per row.
+            // Solver wavefront w takes the part's sub-segments w, w + NS, ...; with NS > 1 a
+            // sub-segment first waits until every sub-segment below its dependency bound is
+            // solved (the `done` counters), which orders its reads of the ring of results
+            // after their writes. The next own sub-segment's header and dependency
+            // addresses are read while the current one is computed (two register sets used
+            // alternately), so the only dependent LDS access of a step is the read of its
+            // dependencies' values.
             __builtin_amdgcn_s_setprio(3);
             struct Head {
                 T b, d;
-                int gi, po, q0, cnt;
+                int gi, po, q0, cnt, need;
                 uint32_t ad[KC];
             };
-            int ready = 0;  // sub-segments [.., ready) are known to be filled
-            // Waits until sub-segment r (in slot sl) is filled; returns the end of the
-            // run of consecutive filled sub-segments starting at r (at most 8 looked at).
-            // The flags are read with relaxed loads in one round trip: a slot's contents
-            // are complete before its flag is written (the prefetcher waits for its LDS
+            const int w0 = wave;
+            auto adv = [&](int sl) {  // slot of the next own sub-segment (NS <= D)
+                sl += NS;
+                return sl >= D ? sl - D : sl;
+            };
+            int ready = w0;  // own sub-segments below `ready` are known to be filled
+            // Waits until own sub-segment r (in slot sl) is filled; returns one past the
+            // run of consecutive own filled sub-segments starting at r (at most 8 looked
+            // at). Lane u reads the flag of own sub-segment r + u*NS, so the eight flags
+            // take one LDS round trip; relaxed loads suffice: a slot's contents are
+            // complete before its flag is written (the prefetcher waits for its LDS
             // writes first), LDS accesses of one wavefront complete in order, and the
             // signal fence keeps the compiler from moving slot reads above the check.
             auto scan = [&](int r, int sl) -> int {
+                const int u = lane & 7, want = r + u * NS;
+                int s2 = sl + u * NS;
+                s2 -= D * (int)((unsigned)s2 / (unsigned)D);
                 for (;;) {
-                    int f[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        int s2 = sl + u;
-                        s2 = s2 >= D ? s2 - D : s2;  // in bounds of the control block for every D >= 4
-                        f[u] = __hip_atomic_load(&filled[s2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                    uint32_t m = 0;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) m |= (u < D && r + u < nss && f[u] == r + u) ? 1u << u : 0u;
-                    const int ok = __builtin_ctz(~m);  // filled sub-segments r, r+1, ... in a row
+                    const int f = __hip_atomic_load(&filled[s2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint64_t m = __ballot(lane < 8 && want < nss && f == want);
+                    const int ok = __builtin_ctzll(~m);  // own filled sub-segments r, r + NS, ... in a row
                     if (ok > 0) {
                         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                        return r + ok;
+                        return r + ok * NS;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
+            };
+            // With several solvers: waits until every sub-segment below `need` is solved.
+            // done[v] only grows and holds the next sub-segment solver v takes, so all below
+            // `need` are solved once every counter reaches it (unused counters hold
+            // INT_MAX; lane v reads counter v & 7). Relaxed loads suffice as in scan.
+            auto wait_need = [&](int need) {
+                if constexpr (NS == 1) return;  // one solver: its own earlier sub-segments are solved
+                const int v = lane & (plan::kMaxSolvers - 1);
+                for (;;) {
+                    const int dv = __hip_atomic_load(&done[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (__ballot(dv < need) == 0) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
             };
             auto load_head = [&](int r, int sl, Head &H) {
                 const char *p2 = smem + slots_off + sl * sb;
                 H.q0 = sspos[r];
                 H.cnt = sspos[r + 1] - H.q0;
+                H.need = 0;
+                if constexpr (NS > 1) H.need = ssneed[r];
                 H.b = ((const T *)(p2 + L.b()))[lane];
                 H.gi = ((const int *)(p2 + L.gi()))[lane];
                 H.po = ((const int *)(p2 + L.po()))[lane];
@@ -219,11 +252,11 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
             // rows of up to 64 bytes of values; longer rows load the next header after
             // the step instead (nxt is then cur).
             constexpr bool kPipe = KC * sizeof(T) <= 64;
-            // One sub-segment: cur is loaded; nxt receives sub-segment rel + 1.
+            // One sub-segment: cur is loaded; nxt receives own sub-segment rel + NS.
             auto step = [&](int rel, int slot, Head &cur, Head &nxt) {
-                const int nslot = slot + 1 == D ? 0 : slot + 1;
+                const int nslot = adv(slot);
                 const char *p2 = smem + slots_off + slot * sb;
-                const bool pre = kPipe && rel + 1 < ready;
+                const bool pre = kPipe && rel + NS < ready;
                 T acc = cur.b;
                 // entries in chunks of at most 8 (bounds the live registers of long rows)
                 constexpr int CH = KC < 8 ? KC : 8;
@@ -231,45 +264,46 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 for (int c0 = 0; c0 < KC; c0 += CH) {
                     T xv[CH], av[CH];
 #pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        xv[u] = *(const T *)(smem + cur.ad[c0 + u]);
-                        av[u] = ((const T *)(p2 + L.v()))[(c0 + u) * kSub + lane];
-                    }
-                    if (c0 == 0 && pre) load_head(rel + 1, nslot, nxt);
+                    for (int u = 0; u < CH; ++u) av[u] = ((const T *)(p2 + L.v()))[(c0 + u) * kSub + lane];
+                    if (c0 == 0) wait_need(cur.need);
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) xv[u] = *(const T *)(smem + cur.ad[c0 + u]);
+                    if (c0 == 0 && pre) load_head(rel + NS, nslot, nxt);
 #pragma unroll
                     for (int u = 0; u < CH; ++u) acc -= av[u] * xv[u];
                 }
                 if constexpr (UPPER) acc = acc / cur.d;
                 if (lane < cur.cnt) {
                     sx[(cur.q0 - pos0 + lane) & (W - 1)] = acc;
-                    store_coherent(x + cur.gi, acc);
+                    store_coherent(xq + cur.q0 + lane, acc);
+                    if (x) x[cur.gi] = acc;
                     if (yother && cur.po >= 0) yother[cur.po] = acc;
                 }
-                // release consumed slots to the prefetchers every 4 sub-segments (and at the end)
-                if ((rel & 3) == 3 || rel + 1 == nss) {
+                // publish: the results in the ring are readable and the slot is free. A lone
+                // solver releases every 4 sub-segments (only prefetchers wait on it).
+                if (NS > 1 || (rel & 3) == 3 || rel + NS >= nss) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    if (lane == 0)
-                        __hip_atomic_store(consumed, rel + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (lane == 0) __hip_atomic_store(&done[w0], rel + NS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
-                if (kPipe && !pre && rel + 1 < nss) {
-                    ready = scan(rel + 1, nslot);
-                    load_head(rel + 1, nslot, nxt);
+                if (kPipe && !pre && rel + NS < nss) {
+                    ready = scan(rel + NS, nslot);
+                    load_head(rel + NS, nslot, nxt);
                 }
                 return nslot;
             };
-            int slot = 0;
+            int slot = w0 % D;
             if constexpr (kPipe) {
                 Head h0, h1;
-                if (nss > 0) {
-                    ready = scan(0, 0);
-                    load_head(0, 0, h0);
+                if (w0 < nss) {
+                    ready = scan(w0, slot);
+                    load_head(w0, slot, h0);
                 }
-                for (int rel = 0; rel < nss; rel += 2) {
+                for (int rel = w0; rel < nss; rel += 2 * NS) {
                     slot = step(rel, slot, h0, h1);
-                    if (rel + 1 < nss) slot = step(rel + 1, slot, h1, h0);
+                    if (rel + NS < nss) slot = step(rel + NS, slot, h1, h0);
                 }
             } else {
-                for (int rel = 0; rel < nss; ++rel) {
+                for (int rel = w0; rel < nss; rel += NS) {
                     if (rel >= ready) ready = scan(rel, slot);
                     Head h;
                     load_head(rel, slot, h);
@@ -281,7 +315,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
             // ---------------- prefetchers: every lane of a slot is written (idle lanes get padding)
             // Each prefetching wavefront keeps two of its sub-segments in flight: while
             // the right-hand side and the polls of one are outstanding, the row data and
-            // first entries of its next one (kPrefetchWaves later) are already loading.
+            // first entries of its next one (NP later) are already loading.
             // Only the LDS writes wait for the solver to release the slot.
             constexpr int B = KC < kBatch ? KC : kBatch;
             constexpr bool kPfPipe = KC == 4;  // two register sets fit the 128-VGPR budget for short rows only
@@ -320,7 +354,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     __builtin_amdgcn_s_sleep(1);
 #pragma unroll
                     for (int u = 0; u < B; ++u)
-                        if (xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
+                        if (xs[u] == SENT) xs[u] = load_coherent(xq + es[u]);
                     pend = false;
 #pragma unroll
                     for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
@@ -348,11 +382,14 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 const T bb = live ? io.b[io.bmap ? io.bmap[q] : io.b_by_row ? cur.gi : q] : (T)0;
                 U xs[B];
 #pragma unroll
-                for (int u = 0; u < B; ++u) xs[u] = load_coherent(cur.es[u] >= 0 ? x + cur.es[u] : zero_addr<T>());
-                if (kPfPipe && rel + kPrefetchWaves < nss) issue(rel + kPrefetchWaves, nxt);
+                for (int u = 0; u < B; ++u) xs[u] = first_poll(xq, cur.es[u]);
+                if (kPfPipe && rel + NP < nss) issue(rel + NP, nxt);
                 poll(cur.es, xs);
-                while (__hip_atomic_load(consumed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < rel - D + 1)
-                    __builtin_amdgcn_s_sleep(4);
+                // the slot's previous sub-segment, rel - D, must be solved
+                const int prev = rel - D;
+                if (prev >= 0)
+                    while (__hip_atomic_load(&done[prev & (NS - 1)], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= prev)
+                        __builtin_amdgcn_s_sleep(4);
                 put(sl, so, 0, cur.es, cur.vs, xs);
                 for (int s0 = B; s0 < KC; s0 += B) {  // rows longer than one batch
                     int es[B];
@@ -368,7 +405,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     }
                     U xs2[B];
 #pragma unroll
-                    for (int u = 0; u < B; ++u) xs2[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
+                    for (int u = 0; u < B; ++u) xs2[u] = first_poll(xq, es[u]);
                     poll(es, xs2);
                     put(sl, so, s0, es, vs, xs2);
                 }
@@ -379,16 +416,16 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (lane == 0) __hip_atomic_store(&filled[slot], rel, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             };
-            const int w = wave - 1;
+            const int w = wave - NS;
             if constexpr (kPfPipe) {
                 Pre p0, p1;
                 if (w < nss) issue(w, p0);
-                for (int rel = w; rel < nss; rel += 2 * kPrefetchWaves) {
+                for (int rel = w; rel < nss; rel += 2 * NP) {
                     process(rel, p0, p1);
-                    if (rel + kPrefetchWaves < nss) process(rel + kPrefetchWaves, p1, p0);
+                    if (rel + NP < nss) process(rel + NP, p1, p0);
                 }
             } else {
-                for (int rel = w; rel < nss; rel += kPrefetchWaves) {
+                for (int rel = w; rel < nss; rel += NP) {
                     Pre p0;
                     issue(rel, p0);
                     process(rel, p0, p0);
@@ -419,6 +456,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
     constexpr U SENT = Sentinel<T>::bits;
     if (skip && *skip) return;
     fill_sentinel(io);
+    T *const xq = io.xq;
     T *const x = io.x;
     T *const yother = io.yother;
     const int lane = threadIdx.x & 63;
@@ -447,7 +485,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u)
-                    if (u < nb) xs[u] = load_coherent(es[u] >= 0 ? x + es[u] : zero_addr<T>());
+                    if (u < nb) xs[u] = first_poll(xq, es[u]);
                 bool pend = false;
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) pend |= u < nb && xs[u] == SENT;
@@ -455,7 +493,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
                     __builtin_amdgcn_s_sleep(1);
 #pragma unroll
                     for (int u = 0; u < kBatch; ++u)
-                        if (u < nb && xs[u] == SENT) xs[u] = load_coherent(x + es[u]);
+                        if (u < nb && xs[u] == SENT) xs[u] = load_coherent(xq + es[u]);
                     pend = false;
 #pragma unroll
                     for (int u = 0; u < kBatch; ++u) pend |= u < nb && xs[u] == SENT;
@@ -465,7 +503,8 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
                     if (u < nb && es[u] != kPad) acc -= vs[u] * from_bits<T>(xs[u]);
             }
             if constexpr (UPPER) acc = acc / piv[q];
-            store_coherent(x + gi, acc);
+            store_coherent(xq + q, acc);
+            if (x) x[gi] = acc;
             if (yother) {
                 const int32_t o = other[q];
                 if (o >= 0) yother[o] = acc;
@@ -527,7 +566,7 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, const SolveIO<T> &io, hipStr
     }
     const size_t lds = f64 ? tri.lds64 : tri.lds32;
     PlanArgs P{tri.nparts, tri.K, tri.ldq, tri.W, f64 ? tri.D64 : tri.D32, tri.S,
-               tri.part_ss.get(), tri.part_pos.get(), tri.ss_pos.get(), tri.grow.get(),
+               tri.part_ss.get(), tri.part_pos.get(), tri.ss_pos.get(), tri.ss_need.get(), tri.grow.get(),
                yother ? tri.other.get() : nullptr, tri.enc.get()};
     const T *val, *piv = nullptr;
     if constexpr (sizeof(T) == 8) {
@@ -538,22 +577,29 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, const SolveIO<T> &io, hipStr
         if (UPPER) piv = tri.piv32.get();
     }
     const int grid = std::min(tri.nparts, 256);
-    auto go = [&](auto kc) {
-        constexpr int KC = decltype(kc)::value;
+    auto go = [&](auto kc, auto ns) {
+        constexpr int KC = decltype(kc)::value, NS = decltype(ns)::value;
         static bool attr_set = false;  // one per instantiation
         if (!attr_set) {
-            HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_blk<T, UPPER, KC>,
+            HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_blk<T, UPPER, KC, NS>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_per_block()));
             attr_set = true;
         }
-        k_trsv_blk<T, UPPER, KC><<<grid, kBlkThreads, lds, s>>>(P, val, piv, io, sync, skip);
+        k_trsv_blk<T, UPPER, KC, NS><<<grid, kBlkThreads, lds, s>>>(P, val, piv, io, sync, skip);
     };
-    switch (tri.KC) {
-        case 4: go(std::integral_constant<int, 4>()); break;
-        case 8: go(std::integral_constant<int, 8>()); break;
-        case 16: go(std::integral_constant<int, 16>()); break;
-        default: go(std::integral_constant<int, 32>()); break;
-    }
+    // the planner gives 1 or plan::kSolvers solver wavefronts
+    auto go_kc = [&](auto ns) {
+        switch (tri.KC) {
+            case 4: go(std::integral_constant<int, 4>(), ns); break;
+            case 8: go(std::integral_constant<int, 8>(), ns); break;
+            case 16: go(std::integral_constant<int, 16>(), ns); break;
+            default: go(std::integral_constant<int, 32>(), ns); break;
+        }
+    };
+    if (tri.NS == 1)
+        go_kc(std::integral_constant<int, 1>());
+    else if constexpr (plan::kSolvers > 1)
+        go_kc(std::integral_constant<int, plan::kSolvers>());
     HEC_CHECK_LAUNCH();
 }
 
@@ -561,53 +607,51 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, const SolveIO<T> &io, hipStr
 
 template <class T>
 void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s, const int32_t *skip) {
-    const int64_t n = lv.n;
+    const int64_t n = lv.n, nf = lv.nf;
     if (n == 0) return;
-    T *y, *yp;
+    T *qL, *qU, *yp;
     if constexpr (sizeof(T) == 8) {
-        y = lv.y64.get();
+        qL = lv.qL64.get();
+        qU = lv.qU64.get();
         yp = lv.yp64.get();
     } else {
-        y = lv.y32.get();
+        qL = lv.qL32.get();
+        qU = lv.qU32.get();
         yp = lv.yp32.get();
     }
     uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
-    if (lv.ras) {
-        // restricted additive Schwarz: the lower solve reads b through the stacked rows' system
-        // rows, the upper solve writes each owned row's result to x; stacked vectors are internal
-        const int64_t nf = lv.nf;
-        T *xh;
-        if constexpr (sizeof(T) == 8)
-            xh = lv.xh64.get();
-        else
-            xh = lv.xh32.get();
-        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, lv.lower.bmap.get(), 0, y, yp, xh, nf}, s, skip);
-        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, xh, x, y, nf}, s, skip);
-        return;
-    }
     if (which == HEC_LU) {
-        // y (the lower solve's output) is sentinel-filled between calls: by
-        // level_schedule, then by every upper solve for the next call. The lower
-        // solve fills x for the upper one; no separate launch.
-        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, y, yp, x, n}, s, skip);
-        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, x, nullptr, y, n}, s, skip);
+        // qL is sentinel-filled between calls (by level_schedule, then by every upper
+        // launch); the lower launch fills qU for the upper one: two launches in all.
+        // Restricted additive Schwarz: the lower solve reads b through the stacked
+        // rows' system rows (bmap); the upper solve writes each owned row's result to
+        // x through `other`, overlap rows nowhere.
+        if (lv.ras) {
+            launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, lv.lower.bmap.get(), 0, qL, nullptr, yp, qU, nf}, s,
+                                 skip);
+            launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, qU, nullptr, x, qL, nf}, s, skip);
+        } else {
+            launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, qL, nullptr, yp, qU, nf}, s, skip);
+            launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{yp, nullptr, 0, qU, x, nullptr, qL, nf}, s, skip);
+        }
         return;
     }
-    k_trsv_fill<T><<<ceil_div(n, 256), 256, 0, s>>>(n, x, skip);
+    // one triangle: qU, free between calls, holds the polled copy; qL keeps its fill
+    k_trsv_fill<T><<<ceil_div(nf, 256), 256, 0, s>>>(nf, qU, skip);
     HEC_CHECK_LAUNCH();
     if (which == HEC_LOWER)
-        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, x, nullptr, nullptr, 0}, s, skip);
+        launch_blk<T, false>(lv.lower, sync, SolveIO<T>{b, nullptr, 1, qU, x, nullptr, nullptr, 0}, s, skip);
     else
-        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{b, nullptr, 1, x, nullptr, nullptr, 0}, s, skip);
+        launch_blk<T, true>(lv.upper, sync + 2, SolveIO<T>{b, nullptr, 1, qU, x, nullptr, nullptr, 0}, s, skip);
 }
 
 void trsv_init_levels(hec_levels_s &lv, hipStream_t s) {
     const int64_t n = lv.nf;
     if (n == 0) return;
-    k_trsv_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.y64.get(), nullptr);
+    k_trsv_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.qL64.get(), nullptr);
     HEC_CHECK_LAUNCH();
-    if (lv.y32.get()) {
-        k_trsv_fill<float><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.y32.get(), nullptr);
+    if (lv.qL32.get()) {
+        k_trsv_fill<float><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.qL32.get(), nullptr);
         HEC_CHECK_LAUNCH();
     }
 }
@@ -649,6 +693,11 @@ void build_tri(const hec_ilu_s &M, bool upper, hec_tri &tri, const hec_tri *uppe
     tri.part_pos.upload(P.part_pos.data(), P.part_pos.size(), s);
     tri.ss_pos.alloc(P.ss_pos.size());
     tri.ss_pos.upload(P.ss_pos.data(), P.ss_pos.size(), s);
+    tri.NS = P.NS;
+    if (!P.ss_need.empty()) {
+        tri.ss_need.alloc(P.ss_need.size());
+        tri.ss_need.upload(P.ss_need.data(), P.ss_need.size(), s);
+    }
     tri.grow.alloc(n);
     tri.grow.upload(P.grow.data(), n, s);
     const bool ras = !M.hext_row.empty();

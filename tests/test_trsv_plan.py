@@ -151,24 +151,43 @@ def check_structure(P, F, upper, lds_max):
         assert np.array_equal(lv, first)
     assert S == P["S"]
     assert P["W"] >= 64 and P["W"] & (P["W"] - 1) == 0
-    assert 4 <= P["D64"] <= 32 and 4 <= P["D32"] <= 32
+    NS = P["NS"]
+    assert NS in (1, 2, 4, 8)
+    assert max(4, NS) <= P["D64"] <= 32 and max(4, NS) <= P["D32"] <= 32
     assert P["lds64"] <= lds_max and P["lds32"] <= lds_max
     # dependencies: inside the part by local position, otherwise in an earlier part
     qs = np.arange(n)
     for s in range(K):
         e = enc[s, :n]
         outer = e >= 0
-        assert (part_of[e[outer]] < part_of[grow[qs[outer]]]).all(), "dependency in a later part"
+        dep = grow[e[outer]]  # outside the part: the dependency's position
+        assert (part_of[dep] < part_of[grow[qs[outer]]]).all(), "dependency in a later part"
         inner = (e < 0) & (e != kPad)
         lp = -e[inner] - 1
         owner = part_of[grow[qs[inner]]]
         j = grow[pp[owner] + lp]
         assert np.array_equal(j, F.LUj[src[s, :n][inner]])
-        assert np.array_equal(e[outer], F.LUj[src[s, :n][outer]])
+        assert np.array_equal(dep, F.LUj[src[s, :n][outer]])
+    # dependency bounds: one past the last sub-segment of the part holding a dependency
+    need = P["ss_need"]
+    assert need.size == P["nss"]
+    ss_of = np.repeat(np.arange(P["nss"]), np.diff(ssp))
+    want = np.zeros(P["nss"], np.int64)
+    for s in range(K):
+        e = enc[s, :n]
+        inner = (e < 0) & (e != kPad)
+        t = ss_of[qs[inner]]
+        owner = part_of[grow[qs[inner]]]
+        dep_t = ss_of[pp[owner] + (-e[inner] - 1)]
+        np.maximum.at(want, t, dep_t - pss[owner] + 1)
+    assert np.array_equal(need, want)
+    t_rel = np.arange(P["nss"]) - pss[part_of[grow[ssp[:-1]]]]
+    assert (need <= t_rel).all(), "a sub-segment depends on itself or a later one"
 
 
-def replay(P, F, b, upper):
-    """Runs the plan on the host in kernel order; returns x (by row)."""
+def replay(P, F, b, upper, flat=False):
+    """Runs the plan on the host in kernel order; returns x (by row). A dependency
+    outside the part is read through its position (its row in a flat plan)."""
     n, K, ldq, W, kPad = P["n"], P["K"], P["ldq"], P["W"], P["kPad"]
     grow = P["grow"]
     enc = P["enc"].reshape(K, ldq)
@@ -192,9 +211,10 @@ def replay(P, F, b, upper):
                 assert (ring_pos[slot] == lp).all(), "ring no longer holds a dependency"
                 xv[inner] = ring[slot]
             if outer.any():
-                assert done[e[outer]].all(), "dependency not solved before its reader"
-                assert earlier(e[outer]).all()
-                xv[outer] = x[e[outer]]
+                dep = e[outer] if flat else grow[e[outer]]
+                assert done[dep].all(), "dependency not solved before its reader"
+                assert earlier(dep).all()
+                xv[outer] = x[dep]
             v = np.where(pad, 0.0, F.LUx[np.where(pad, 0, sr)])
             acc = acc - v * xv
         if upper:
@@ -218,6 +238,93 @@ def replay(P, F, b, upper):
         for c in range(len(ch) - 1):
             segment(ch[c], ch[c + 1], None, None, 0, lambda j, c=c: pos[j] < ch[c])
     assert done.all()
+    return x
+
+
+def replay_concurrent(P, F, b, upper, policy, seed=0):
+    """Runs a blocked plan with P["NS"] solver wavefronts on the host under an
+    adversarial schedule; returns x (by row).
+
+    Solver w takes the part's sub-segments w, w + NS, ... A sub-segment starts
+    (reads its dependencies from the ring of results) once every sub-segment of
+    the part below its dependency bound is solved, and finishes later (reads them
+    again, writes its results); between the two, other solvers start and finish.
+    policy "random" picks the next event at random; "late" starts whatever can
+    start and finishes the newest started sub-segment first, "early" the oldest,
+    so that readers stay in flight as long as the plan allows. A result replacing
+    a ring entry that a started sub-segment still reads fails the check."""
+    n, K, ldq, W, kPad, NS = P["n"], P["K"], P["ldq"], P["W"], P["kPad"], P["NS"]
+    grow = P["grow"]
+    enc = P["enc"].reshape(K, ldq)
+    src = P["src"].reshape(K, ldq)
+    pp, pss, ssp, need = P["part_pos"], P["part_ss"], P["ss_pos"], P["ss_need"]
+    rng = np.random.default_rng(seed)
+    x = np.full(n, np.nan)
+    done_row = np.zeros(n, bool)
+    for p in range(P["nparts"]):
+        ring = np.zeros(W)
+        ring_pos = np.full(W, -1, np.int64)
+        t0, nss = pss[p], pss[p + 1] - pss[p]
+        nxt = list(range(NS))          # next sub-segment of each solver
+        started = [False] * NS
+        done = list(range(NS))         # the kernel's counters
+
+        def reads(t):
+            q0, q1 = ssp[t0 + t], ssp[t0 + t + 1]
+            out = []
+            for s in range(K):
+                e = enc[s, q0:q1]
+                inner = (e < 0) & (e != kPad)
+                lp = -e[inner] - 1
+                assert (ring_pos[lp & (W - 1)] == lp).all(), "ring no longer holds a dependency"
+                out.append((inner, lp))
+            return out
+
+        def finish(t):
+            q0, q1 = ssp[t0 + t], ssp[t0 + t + 1]
+            rows = grow[q0:q1]
+            acc = b[rows].copy()
+            rd = reads(t)
+            for s in range(K):
+                e = enc[s, q0:q1]
+                pad = e == kPad
+                outer = e >= 0
+                inner, lp = rd[s]
+                xv = np.zeros(q1 - q0)
+                xv[inner] = ring[lp & (W - 1)]
+                if outer.any():
+                    dep = grow[e[outer]]
+                    assert done_row[dep].all()
+                    xv[outer] = x[dep]
+                v = np.where(pad, 0.0, F.LUx[np.where(pad, 0, src[s, q0:q1])])
+                acc = acc - v * xv
+            if upper:
+                acc = acc / F.LUx[P["psrc"][q0:q1]]
+            loc = np.arange(q0, q1) - pp[p]
+            ring[loc & (W - 1)] = acc
+            ring_pos[loc & (W - 1)] = loc
+            x[rows] = acc
+            done_row[rows] = True
+
+        while any(t < nss for t in nxt):
+            can_start = [w for w in range(NS) if nxt[w] < nss and not started[w] and min(done) >= need[t0 + nxt[w]]]
+            running = [w for w in range(NS) if started[w]]
+            assert can_start or running, "no solver can proceed"
+            if policy == "random":
+                w = rng.choice(can_start + running)
+            elif can_start:
+                w = can_start[0]
+            else:
+                w = (max if policy == "late" else min)(running, key=lambda v: nxt[v])
+            t = nxt[w]
+            if not started[w]:
+                reads(t)
+                started[w] = True
+            else:
+                finish(t)
+                started[w] = False
+                nxt[w] = done[w] = t + NS
+    assert done_row.all()
     return x
 
 
@@ -283,8 +390,39 @@ def test_plan_structure_and_replay(factors, name):
             rows = P["grow"][pp[0]:pp[1]]
             assert rows.max() - rows.min() + 1 > rows.size
         check_structure(P, F, upper, lds_max)
-        x = replay(P, F, rhs, upper)
+        x = replay(P, F, rhs, upper, flat=opt.get("flat", False))
         assert np.array_equal(x.view(np.uint64), ref.view(np.uint64)), "replay differs from the oracle"
+        if P["blocked"] and P["NS"] > 1:
+            for policy, seed in (("late", 0), ("early", 0), ("random", 1), ("random", 2)):
+                x = replay_concurrent(P, F, rhs, upper, policy, seed)
+                assert np.array_equal(x.view(np.uint64), ref.view(np.uint64)), policy
+
+
+@pytest.mark.parametrize("name,solvers", [("poisson3d_32_k0", 2), ("poisson3d_32_k0", 4), ("poisson3d_32_k0", 8),
+                                          ("tpfa3d_41x37x23_k0", 4), ("tpfa3d_41x37x23_k1", 4),
+                                          ("random_20000_k1", 4), ("poisson2d_64_k0", 4)])
+def test_multi_solver_plans(factors, name, solvers):
+    """Plans with several solver wavefronts per workgroup: tiles sized for them on a
+    3D grid, the dependency bounds and ring size checked, and the solve replayed
+    under adversarial interleavings of the solvers, bit for bit against the oracle."""
+    A, F, opt = factors(name)
+    grid = _plan.detect_grid(A)
+    b = np.random.default_rng(11).uniform(-1, 1, A.n)
+    y_o = O.trsv_lower(F, b)
+    x_o = O.trsv_upper(F, y_o)
+    for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
+        P = _plan.make_plan(F, upper, grid, solvers=solvers)
+        if name.startswith(("poisson3d", "tpfa3d")) and name.endswith("k0"):
+            assert P["NS"] == solvers  # 3D 7-point tiles: levels span several sub-segments
+        if name.startswith("poisson2d"):
+            assert P["NS"] == 1  # 2D: one sub-segment per level, a single solver
+        check_structure(P, F, upper, _plan.LDS_MAX)
+        x = replay(P, F, rhs, upper)
+        assert np.array_equal(x.view(np.uint64), ref.view(np.uint64))
+        if P["NS"] > 1:
+            for policy, seed in (("late", 0), ("early", 0), ("random", 1), ("random", 2)):
+                x = replay_concurrent(P, F, rhs, upper, policy, seed)
+                assert np.array_equal(x.view(np.uint64), ref.view(np.uint64)), policy
 
 
 def test_detect_grid():
