@@ -12,16 +12,19 @@
 //  * inside a part the rows are laid out by (level, row) (Alg. 3's order) and
 //    cut into sub-segments of at most 64 rows of one level.
 //
-// Execution (k_trsv_blk): one workgroup per part, 1 solver wavefront and 15
-// prefetching wavefronts.
+// Execution (k_trsv_blk): one workgroup per part: solver wavefronts (one by
+// default), a writer wavefront and prefetching wavefronts.
 //  * Prefetchers stream the next sub-segments into a ring of LDS slots: the
 //    right-hand side (gathered by row, or read in plan order for the upper
 //    solve of an L-then-U chain), the row's entries, and the values of
 //    dependencies in earlier parts, polled from global memory until final;
 //  * the solver takes sub-segments in order, reads dependencies inside the part
 //    from a small LDS ring of recent results and dependencies outside it from
-//    the slot, and publishes each result to global memory. It never waits on
-//    global memory itself.
+//    the slot, and publishes each result to the polled copy (below). It never
+//    waits on global memory itself;
+//  * the writer copies the part's results from the polled copy to the outputs
+//    by row or in the other triangle's order, scattered stores kept off the
+//    solver's path.
 //  * Readiness of a value across parts is the value itself: each triangle
 //    keeps an internal copy of its results in plan order, pre-filled with a
 //    signalling-NaN bit pattern that arithmetic never produces; results are
@@ -43,7 +46,8 @@ namespace hec {
 
 namespace {
 
-constexpr int kWaves = 16;  // solver wavefronts first, then prefetching wavefronts
+constexpr int kWaves = 16;  // solver wavefronts first, then prefetching wavefronts, the writer last
+constexpr int kWriterBatch = 8;  // sub-segments' worth of positions the writer copies at a time
 constexpr int kBlkThreads = 64 * kWaves;
 constexpr int kBatch = 8;           // entries loaded per batch by a prefetcher lane
 using plan::kPad;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
     T *const x = io.x;
     T *const yother = io.yother;
     extern __shared__ __align__(16) char smem[];
-    constexpr int NP = kWaves - NS;
+    constexpr int NP = kWaves - NS - 1;
     const int D = P.D, K = P.K, W = P.W;
     int *done = (int *)smem;  // per solver wavefront: the next sub-segment it solves
     int *filled = done + plan::kMaxSolvers;
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
             __builtin_amdgcn_s_setprio(3);
             struct Head {
                 T b, d;
-                int gi, po, q0, cnt, need;
+                int q0, cnt, need;
                 uint32_t ad[KC];
             };
             const int w0 = wave;
@@ -241,8 +245,6 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 H.need = 0;
                 if constexpr (NS > 1) H.need = ssneed[r];
                 H.b = ((const T *)(p2 + L.b()))[lane];
-                H.gi = ((const int *)(p2 + L.gi()))[lane];
-                H.po = ((const int *)(p2 + L.po()))[lane];
                 H.d = (T)1;
                 if constexpr (UPPER) H.d = ((const T *)(p2 + L.d()))[lane];
 #pragma unroll
@@ -276,8 +278,6 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 if (lane < cur.cnt) {
                     sx[(cur.q0 - pos0 + lane) & (W - 1)] = acc;
                     store_coherent(xq + cur.q0 + lane, acc);
-                    if (x) x[cur.gi] = acc;
-                    if (yother && cur.po >= 0) yother[cur.po] = acc;
                 }
                 // publish: the results in the ring are readable and the slot is free. A lone
                 // solver releases every 4 sub-segments (only prefetchers wait on it).
@@ -311,6 +311,53 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 }
             }
             __builtin_amdgcn_s_setprio(0);
+        } else if (wave == kWaves - 1) {
+            // ---------------- writer: the part's results go to the outputs by row (x) and in the
+            // other order (yother), read back from the polled copy, where a final value is
+            // its own ready flag. The part's positions are consecutive; each lane takes
+            // every 64th of kWriterBatch * 64 at a time, once the solvers' progress counters
+            // have passed them.
+            if (x || yother) {
+                const int pend_part = P.part_pos[p + 1];
+                constexpr int WB = kWriterBatch;
+                for (int c = pos0; c < pend_part; c += WB * kSub) {
+                    const int cend = min(c + WB * kSub, pend_part);
+                    U v[WB];
+                    int gi[WB], po[WB];
+#pragma unroll
+                    for (int k = 0; k < WB; ++k) {
+                        const int q = c + k * kSub + lane;
+                        const bool live = q < cend;
+                        gi[k] = live && x ? P.grow[q] : -1;
+                        po[k] = live && yother && P.other ? P.other[q] : -1;
+                        v[k] = live ? SENT : (U)0;
+                    }
+                    for (;;) {  // all sub-segments below the smallest counter are solved
+                        int m = INT_MAX;
+#pragma unroll
+                        for (int u = 0; u < plan::kMaxSolvers; ++u)
+                            m = min(m, __hip_atomic_load(&done[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                        if (sspos[min(m, nss)] >= cend) break;
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                    bool pend = true;
+                    while (pend) {  // the solvers' coherent stores may still be on their way
+#pragma unroll
+                        for (int k = 0; k < WB; ++k)
+                            if (v[k] == SENT) v[k] = load_coherent(xq + c + k * kSub + lane);
+                        pend = false;
+#pragma unroll
+                        for (int k = 0; k < WB; ++k) pend |= v[k] == SENT;
+                        if (pend) __builtin_amdgcn_s_sleep(2);
+                    }
+#pragma unroll
+                    for (int k = 0; k < WB; ++k) {
+                        const T r = from_bits<T>(v[k]);
+                        if (gi[k] >= 0) x[gi[k]] = r;
+                        if (po[k] >= 0) yother[po[k]] = r;
+                    }
+                }
+            }
         } else {
             // ---------------- prefetchers: every lane of a slot is written (idle lanes get padding)
             // Each prefetching wavefront keeps two of its sub-segments in flight: while
@@ -330,8 +377,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 R.cnt = sspos[r + 1] - R.q0;
                 const bool live = lane < R.cnt;
                 const int q = R.q0 + (live ? lane : 0);
-                R.gi = live ? P.grow[q] : 0;
-                R.po = live && P.other ? P.other[q] : -1;
+                R.gi = live && io.b_by_row && !io.bmap ? P.grow[q] : 0;
                 R.dd = (T)1;
                 if constexpr (UPPER) R.dd = live ? piv[q] : (T)1;
 #pragma unroll
@@ -410,8 +456,6 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     put(sl, so, s0, es, vs, xs2);
                 }
                 ((T *)(sl + L.b()))[lane] = bb;
-                ((int *)(sl + L.gi()))[lane] = cur.gi;
-                ((int *)(sl + L.po()))[lane] = cur.po;
                 if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = cur.dd;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (lane == 0) __hip_atomic_store(&filled[slot], rel, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
