@@ -219,8 +219,10 @@ __device__ void givens_finish(int j, double hn, double *sd, int32_t *si, int32_t
 //   MODE 1: hout[k] = <V_k, w>                                  k < nv
 //   MODE 2: w -= V hin;  hout[k] = <V_k, w>
 //   MODE 3: w -= V hin;  ||w||^2, then the Givens step of column nv-1
-// A workgroup's 4 wavefronts take the same 64 rows at a time; wavefront q owns
-// the vectors k = q, q+4, q+8, ... (8 sums per thread for up to 32 vectors).
+// A workgroup's 4 wavefronts take the same 64 R rows at a time, R consecutive rows
+// per lane (R = 16 bytes / element size: one 16-byte load per vector and lane);
+// wavefront q owns the vectors k = q, q+4, q+8, ... (8 sums per thread for up to
+// 32 vectors).
 // The update w -= V hin adds the 4 wavefronts' partial sums in a fixed order
 // through LDS; every sum is reduced in a fixed order (deterministic).
 template <class VT, int MODE>
@@ -228,9 +230,12 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
                                             const double *__restrict__ hin, double *part, const int32_t *skip) {
     constexpr int KW = kMaxRestart / 4;  // vectors per wavefront
     constexpr int NS = kMaxRestart + 1;  // sums per workgroup: nv dots (+ the norm)
+    constexpr int R = 16 / (int)sizeof(VT);  // consecutive rows per lane: one 16-byte load per vector
+    constexpr int64_t TR = 64 * R;            // rows per tile
+    using VV = VT __attribute__((ext_vector_type(R)));
     if (skip && *skip) return;
     __shared__ double sh[kMaxRestart];
-    __shared__ double px[4][64];
+    __shared__ double px[4][R][64];
     __shared__ double red[NS];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     if (MODE != 1 && (int)threadIdx.x < nv) sh[threadIdx.x] = hin[threadIdx.x];
@@ -239,37 +244,75 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
 #pragma unroll
     for (int u = 0; u < KW; ++u) acc[u] = 0.0;
     double nrm = 0.0;
-    const int64_t ntiles = (n + 63) / 64;
+    const int64_t ntiles = (n + TR - 1) / TR;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t i = t * 64 + lane;
-        const bool in = i < n;
-        double vk[KW];
+        const int64_t i0 = t * TR + (int64_t)lane * R;
+        const bool full = i0 + R <= n;  // V's columns and w are 16-byte aligned (ldv is a multiple of 64)
+        VT vk[KW][R];
 #pragma unroll
         for (int u = 0; u < KW; ++u) {
             const int k = q + 4 * u;
-            vk[u] = (in && k < nv) ? (double)V[k * ldv + i] : 0.0;
+            if (k < nv && full) {
+                const VV x = *(const VV *)(V + k * ldv + i0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) vk[u][r] = x[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) vk[u][r] = (k < nv && i0 + r < n) ? V[k * ldv + i0 + r] : (VT)0;
+            }
         }
-        double wi = in ? (double)w[i] : 0.0;
+        double wi[R];
+        if (full) {
+            const VV x = *(const VV *)(w + i0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) wi[r] = (double)x[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) wi[r] = i0 + r < n ? (double)w[i0 + r] : 0.0;
+        }
         if constexpr (MODE != 1) {
-            double ps = 0.0;
+            double ps[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ps[r] = 0.0;
 #pragma unroll
             for (int u = 0; u < KW; ++u) {
                 const int k = q + 4 * u;
-                if (k < nv) ps += sh[k] * vk[u];
+                if (k < nv) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) ps[r] += sh[k] * (double)vk[u][r];
+                }
             }
-            px[q][lane] = ps;
+#pragma unroll
+            for (int r = 0; r < R; ++r) px[q][r][lane] = ps[r];
             __syncthreads();
-            wi -= ((px[0][lane] + px[1][lane]) + px[2][lane]) + px[3][lane];
-            const VT ws = (VT)wi;
-            wi = (double)ws;
-            if (q == 0 && in) w[i] = ws;
+            VV wv;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                wi[r] -= ((px[0][r][lane] + px[1][r][lane]) + px[2][r][lane]) + px[3][r][lane];
+                wv[r] = (VT)wi[r];
+                wi[r] = (double)wv[r];
+            }
+            if (q == 0) {
+                if (full) {
+                    *(VV *)(w + i0) = wv;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (i0 + r < n) w[i0 + r] = wv[r];
+                }
+            }
             __syncthreads();
         }
         if constexpr (MODE == 3) {
-            if (q == 0) nrm += wi * wi;
+            if (q == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) nrm += wi[r] * wi[r];
+            }
         } else {
 #pragma unroll
-            for (int u = 0; u < KW; ++u) acc[u] += vk[u] * wi;
+            for (int u = 0; u < KW; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[u] += (double)vk[u][r] * wi[r];
         }
     }
     // per-workgroup sums: wavefront q reduces its own vectors; the norm lives in slot kMaxRestart
