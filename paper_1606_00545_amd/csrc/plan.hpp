@@ -61,7 +61,7 @@ struct Slot {
     HEC_HD size_t b() const { return 0; }                                       // T[64]
     HEC_HD size_t xe() const { return b() + kSub * sizeof(T); }                 // T[KC][64]
     HEC_HD size_t v() const { return xe() + (size_t)KC * kSub * sizeof(T); }    // T[KC][64]
-    HEC_HD size_t d() const { return v() + (size_t)KC * kSub * sizeof(T); }     // T[64] (U)
+    HEC_HD size_t d() const { return v() + (size_t)KC * kSub * sizeof(T); }     // T[64] (U: 1 / u_ii)
     HEC_HD size_t a() const { return d() + (UPPER ? kSub * sizeof(T) : 0); }    // int[KC][64]
     HEC_HD size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
 };

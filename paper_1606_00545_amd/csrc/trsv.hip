@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
 #pragma unroll
                     for (int u = 0; u < CH; ++u) acc -= av[u] * xv[u];
                 }
-                if constexpr (UPPER) acc = acc / cur.d;
+                if constexpr (UPPER) acc = acc * cur.d;  // the pivot's reciprocal, formed by the prefetcher
                 if (lane < cur.cnt) {
                     sx[(cur.q0 - pos0 + lane) & (W - 1)] = acc;
                     store_coherent(xq + cur.q0 + lane, acc);
@@ -378,8 +378,11 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 const bool live = lane < R.cnt;
                 const int q = R.q0 + (live ? lane : 0);
                 R.gi = live && io.b_by_row && !io.bmap ? P.grow[q] : 0;
+                // upper: the reciprocal of u_ii (correctly rounded), so that the solver's
+                // step multiplies instead of dividing; the result is within about one
+                // rounding of the quotient
                 R.dd = (T)1;
-                if constexpr (UPPER) R.dd = live ? piv[q] : (T)1;
+                if constexpr (UPPER) R.dd = live ? (T)1 / piv[q] : (T)1;
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
                     R.es[u] = kPad;
