@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes moved by one preconditioner solve (lower + upper k_trsv_blk) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
-TRSV_PAIR_TRAFFIC = None
+TRSV_PAIR_TRAFFIC = int((157.2 + 48.5 + 166.5 + 59.3) * 1e6)
 
 
 def parse():
@@ -45,7 +45,8 @@ def parse():
     p.add_argument("--cpu-sample-iters", type=int, default=30)
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
-                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "iluk", "copy"],
+                   choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "iluk", "formats",
+                            "copy"],
                    help="diffusion128 is the benchmark line; the others print extra records "
                         "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
@@ -71,6 +72,62 @@ def time_launches(fn, reps, stream):
     e.record(stream)
     e.synchronize()
     return s.elapsed_time(e) / 1e3 / reps
+
+
+def formats_table():
+    """Table 3 of the paper (SpMV speedup of ELL, HYB and HEC over a sequential CPU
+    product) on synthetic stand-ins, with CSR beside them: FP64 SpMV time and GB/s on
+    algorithmic bytes (12 nnz + 16 n) for each format, and the speedup over the
+    oracle's CSR product on one pinned host core."""
+    import torch
+    import oracle as O
+    from paper_1606_00545_amd import hec, synth
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    mats = [("3D Poisson 150^3 (the paper's 3D_Poisson)", lambda: synth.poisson3d(150)),
+            ("power-law 4M (row lengths 4..512, mean 12)", lambda: synth.workload_powerlaw()[0]),
+            ("circuit-like 2M (banded + 200 rows of 2000..20000)",
+             lambda: synth.circuit_like(2_000_000, np.random.default_rng(6)))]
+    res = []
+    try:
+        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+    except (AttributeError, OSError):
+        pass
+    for name, mk in mats:
+        t0 = time.time()
+        A = mk()
+        n, nnz = A.n, A.nnz
+        maxrow = int(np.diff(A.Ap).max())
+        log(f"[bench] formats: {name}: n={n} nnz={nnz} max row {maxrow} ({time.time() - t0:.1f}s)")
+        x = np.random.default_rng(7).uniform(-1, 1, n)
+        cpu = []
+        for _ in range(3):
+            tc = time.perf_counter()
+            O.csr_spmv(n, A.Ap, A.Aj, A.Ax, x)
+            cpu.append(time.perf_counter() - tc)
+        t_cpu = min(cpu)
+        alg = 12 * nnz + 16 * n
+        row = {"matrix": name, "n": n, "nnz": nnz, "max_row": maxrow, "cpu_oracle_us": round(t_cpu * 1e6, 1)}
+        xd = torch.from_numpy(x).to(dev)
+        yd = torch.empty(n, dtype=torch.float64, device=dev)
+        for fmt, width, coo in (("CSR", 0, False), ("ELL", maxrow, False), ("HYB", hec.WIDTH_HYB, True),
+                                ("HEC", -1, False)):
+            ld = (n + 255) // 256 * 256
+            if fmt == "ELL" and 12 * maxrow * ld > 40e9:
+                row[fmt] = {"skipped": f"the slab would hold {12 * maxrow * ld / 1e9:.0f} GB"}
+                continue
+            Mh = hec.hec_from_csr(A, ell_width=width, coo=coo)
+            inf = hec.hec_info(Mh)
+            t = time_launches(lambda: hec.hec_spmv(Mh, xd, yd), 20, stream)
+            stored = 12 * inf["K"] * inf["ld"] + (16 if coo else 12) * inf["nnz_rem"] + 16 * n
+            row[fmt] = {"K": inf["K"], "nnz_rem": inf["nnz_rem"], "us": round(t * 1e6, 1),
+                        "alg_GBps": round(alg / t / 1e9, 1), "stored_GBps": round(stored / t / 1e9, 1),
+                        "speedup_vs_cpu": round(t_cpu / t, 1)}
+            log(f"[bench] formats {fmt}: {row[fmt]}")
+            del Mh
+        res.append(row)
+        del A
+    return {"formats": res, "note": "FP64 values and vectors; speedup = one-core oracle CSR SpMV time / GPU time"}
 
 
 def main():
@@ -438,6 +495,8 @@ def extra(args):
             log(f"[bench] iluk {row}")
             del F, lv
         out.update({"n": A.n, "nnz": A.nnz, "iluk": rows})
+    elif args.workload == "formats":
+        out.update(formats_table())
     elif args.workload == "copy":
         nbytes = 1 << 30
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)

@@ -52,6 +52,15 @@ typedef enum { HEC_F64 = 0, HEC_F32 = 1 } hec_dtype;
  * (rounded to nearest even from the FP64 values) for mixed precision. */
 #define HEC_KEEP_F32 1u
 
+/* hec_from_csr flag: keep the remainder as COO (the row of every entry, entries in
+ * row order) and multiply it entry-parallel: with the ELL part this is the HYB
+ * format of Sec. 2.1 (ELL + COO) instead of HEC (ELL + CSR). */
+#define HEC_COO_REMAINDER 2u
+
+/* hec_from_csr ell_width: choose the ELL width by the HYB rule, the largest K such
+ * that at least max(4096, n/3) rows hold K or more entries (0 when none). */
+#define HEC_WIDTH_HYB (-2)
+
 /* trsv_levels `which` */
 #define HEC_LOWER 1u
 #define HEC_UPPER 2u
@@ -87,12 +96,16 @@ typedef struct {
 /* Sec. 2.1: build the HEC form of A on the device -- an ELL slab of width K
  * stored column-major with leading dimension ld = n rounded up to 256 (entry s
  * of row i at s*ld + i), plus the rest of every longer row in CSR (rem_ptr[n+1],
- * rem_col, rem_val). K = ell_width if ell_width >= 0, else min(20, longest row)
- * (the paper's recommended boundary), never above the longest row; the first K
- * entries of each row go to the slab. Empty slab slots of row i hold (col i,
- * value 0); rows n..ld-1 hold (col 0, value 0). ell_width = 0 gives plain CSR.
- * flags: HEC_KEEP_F32. Errors: INVALID_ARG for n < 0, null pointers or a
- * malformed CSR (unsorted or duplicate columns, out-of-range index). */
+ * rem_col, rem_val). K = ell_width if ell_width >= 0, the HYB rule for
+ * HEC_WIDTH_HYB, else min(20, longest row) (the paper's recommended boundary),
+ * never above the longest row; the first K entries of each row go to the slab.
+ * Empty slab slots of row i hold (col i, value 0); rows n..ld-1 hold (col 0,
+ * value 0). ell_width = 0 gives plain CSR; ell_width >= the longest row gives
+ * plain ELL (Sec. 2.1's ELL format). flags: HEC_KEEP_F32, HEC_COO_REMAINDER
+ * (HYB). The matrix owns scratch for the COO remainder's partial sums, so SpMVs
+ * with one HYB matrix must not overlap in time on different streams. Errors:
+ * INVALID_ARG for n < 0, null pointers, unknown flags or a malformed CSR
+ * (unsorted or duplicate columns, out-of-range index). */
 hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax,
                         int32_t ell_width, uint32_t flags, void *stream, hec_matrix *out);
 

@@ -129,6 +129,39 @@ def hec_from_csr(n, Ap, Aj, Ax, ell_width=-1) -> HEC:
     return HEC(n, K, ld, ell_col[:K * ld], ell_val[:K * ld], rem_ptr, rem_col[:nr], rem_val[:nr])
 
 
+def hyb_width(n, Ap):
+    """ELL width of the HYB format (Sec. 2.1's ELL + COO, after Bell and Garland):
+    the largest K such that at least max(4096, n // 3) rows hold K or more entries,
+    0 when no K qualifies. A plain count over the row lengths."""
+    lens = np.diff(np.asarray(Ap, np.int64))
+    need = max(4096, n // 3)
+    K = 0
+    for k in range(1, int(lens.max(initial=0)) + 1):
+        if int((lens >= k).sum()) >= need:
+            K = k
+    return K
+
+
+@dataclass
+class HYB:
+    """HYB form (Sec. 2.1): the ELL part of width K as in HEC, the rest as COO
+    (row, column, value) triplets in row order."""
+    ell: HEC
+    coo_row: np.ndarray
+    coo_col: np.ndarray
+    coo_val: np.ndarray
+
+
+def hyb_from_csr(n, Ap, Aj, Ax, ell_width=None) -> HYB:
+    """HYB arrays: the ELL part of hec_from_csr with the HYB width (or ell_width),
+    and the remaining entries of every row as COO triplets, rows ascending, each
+    row's entries in column order."""
+    K = hyb_width(n, Ap) if ell_width is None else ell_width
+    H = hec_from_csr(n, Ap, Aj, Ax, K)
+    rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(H.rem_ptr))
+    return HYB(H, rows, H.rem_col.copy(), H.rem_val.copy())
+
+
 @dataclass
 class Factor:
     """In-place ILU(k) factor: L strict lower (unit diagonal implied), U upper with diagonal."""

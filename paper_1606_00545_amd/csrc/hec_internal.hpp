@@ -144,6 +144,14 @@ struct hec_matrix_s {
     hec::DevBuf<double> rem_val;
     hec::DevBuf<float> rem_val32;
     hec::DevBuf<int32_t> rem_rows;  // ascending rows with remainder entries (all rows when K == 0)
+    // COO remainder (HEC_COO_REMAINDER: the HYB layout): the row of every remainder
+    // entry, multiplied entry-parallel in tiles; partial sums of the rows cut by tile
+    // boundaries (2 per tile: row, then value) are finished by a second launch
+    bool coo = false;
+    int64_t coo_tiles = 0;
+    hec::DevBuf<int32_t> rem_row;
+    hec::DevBuf<int32_t> carry_row;  // 2 * coo_tiles
+    hec::DevBuf<double> carry_val;   // 2 * coo_tiles slots of 8 bytes (holds FP32 sums for FP32 values)
     std::unique_ptr<hec::KrylovWS, hec::KrylovWSDeleter> ws;
 };
 

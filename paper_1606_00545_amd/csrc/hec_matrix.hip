@@ -3,7 +3,8 @@
 // Layout in HBM: the ELL slab is column-major (entry s of row i at s*ld + i,
 // ld = n rounded up to 256), so a wavefront's load of slot s touches 64
 // consecutive values: one 512-byte (FP64) or 256-byte (FP32/int32) segment.
-// The remainder is plain CSR plus a list of the rows that have one.
+// The remainder is plain CSR plus a list of the rows that have one; in the HYB
+// layout (HEC_COO_REMAINDER) it is also kept as COO, the row of every entry.
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -191,6 +192,124 @@ __global__ __launch_bounds__(256) void k_spmv_rem(int32_t nrows, const int32_t *
     }
 }
 
+// COO remainder (HYB): entry-parallel, deterministic. A wavefront takes a tile of
+// kCooTile consecutive entries (row order), kCooE per lane. A lane sums its own
+// entries row by row and adds every row that begins and ends inside its entries
+// to y. The rows at the lanes' edges are summed by the lane where the row begins
+// in the tile, over the following lanes in order (through LDS). A row that
+// continues from the previous tile or into the next one is not added here: its
+// partial sum goes to the tile's carry slots (first / last row), and k_coo_carry
+// adds them in tile order.
+constexpr int kCooE = 8;
+constexpr int kCooTile = 64 * kCooE;
+
+template <class VT, class XT, class YT, class AT>
+__global__ __launch_bounds__(256) void k_spmv_coo(int64_t nnz, const int32_t *__restrict__ row,
+                                                  const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                  AT alpha, const XT *__restrict__ x, YT *y, int32_t *crow,
+                                                  AT *cval, const int32_t *skip) {
+    if (skip && *skip) return;
+    __shared__ int32_t s_hr[4][64], s_tr[4][64];  // first and last row of each lane's entries (-1: none)
+    __shared__ AT s_hs[4][64], s_ts[4][64];       // sums of its first and last row
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t base = tile * kCooTile;
+    const bool live = base < nnz;  // uniform over the wavefront
+    int32_t hr = -1, tr = -1;
+    AT hs = 0, ts = 0;
+    if (live) {
+        const int64_t e0 = base + (int64_t)lane * kCooE;
+        int32_t cur = -1;
+        AT run = 0;
+        bool head_done = false;
+#pragma unroll
+        for (int j = 0; j < kCooE; ++j) {
+            const int64_t e = e0 + j;
+            if (e < nnz) {
+                const int32_t r = __builtin_nontemporal_load(row + e);
+                const AT p = (AT)__builtin_nontemporal_load(val + e) * (AT)x[__builtin_nontemporal_load(col + e)];
+                if (cur < 0) {
+                    cur = hr = r;
+                    run = p;
+                } else if (r == cur) {
+                    run += p;
+                } else {
+                    if (!head_done) {
+                        hs = run;
+                        head_done = true;
+                    } else {
+                        y[cur] = (YT)((AT)y[cur] + alpha * run);  // begins and ends in this lane
+                    }
+                    cur = r;
+                    run = p;
+                }
+            }
+        }
+        tr = cur;
+        ts = run;
+        if (!head_done) hs = run;
+    }
+    s_hr[wv][lane] = hr;
+    s_tr[wv][lane] = tr;
+    s_hs[wv][lane] = hs;
+    s_ts[wv][lane] = ts;
+    __syncthreads();
+    if (!live || hr < 0) return;
+    const int32_t prev_row = base > 0 ? row[base - 1] : -1;
+    const int64_t nb = base + kCooTile;
+    const int32_t next_row = nb < nnz ? row[nb] : -1;
+    if (lane == 0) {  // which of the tile's edge rows continue across it
+        const int32_t first_r = s_hr[wv][0];
+        const int32_t last_r = row[(nb < nnz ? nb : nnz) - 1];
+        const bool cf = first_r == prev_row, ct = last_r == next_row;
+        crow[2 * tile] = cf ? first_r : -1;
+        crow[2 * tile + 1] = ct ? (cf && first_r == last_r ? -2 : last_r) : -1;
+    }
+    auto finish = [&](int32_t r, AT total) {
+        const bool cf = r == prev_row, ct = r == next_row;
+        if (!cf && !ct) y[r] = (YT)((AT)y[r] + alpha * total);
+        else if (cf) cval[2 * tile] = total;  // also a tile that is one row throughout
+        else cval[2 * tile + 1] = total;
+    };
+    if (hr != tr && (lane == 0 || s_tr[wv][lane - 1] != hr)) finish(hr, hs);  // first row, ends in this lane
+    if (hr == tr && lane > 0 && s_tr[wv][lane - 1] == tr) return;  // one row, begun in an earlier lane
+    AT total = ts;
+    for (int m = lane + 1; m < 64; ++m) {  // the last row, on through the following lanes
+        if (s_hr[wv][m] != tr) break;
+        total += s_hs[wv][m];
+        if (s_tr[wv][m] != tr) break;
+    }
+    finish(tr, total);
+}
+
+// Rows cut by COO tile boundaries: the tile where such a row begins adds the
+// partial sums of the following tiles in order.
+template <class YT, class AT>
+__global__ __launch_bounds__(256) void k_coo_carry(int64_t ntiles, const int32_t *__restrict__ crow,
+                                                   const AT *__restrict__ cval, AT alpha, YT *y,
+                                                   const int32_t *skip) {
+    if (skip && *skip) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int32_t r = crow[2 * t + 1];
+    if (r < 0) return;
+    AT total = cval[2 * t + 1];
+    for (int64_t u = t + 1; u < ntiles; ++u) {
+        total += cval[2 * u];
+        if (crow[2 * u + 1] != -2) break;  // the row ends in tile u
+    }
+    y[r] = (YT)((AT)y[r] + alpha * total);
+}
+
+// y = beta * z (0 when beta == 0): the start of a product without an ELL part.
+template <class YT, class AT>
+__global__ __launch_bounds__(256) void k_spmv_beta(int32_t n, AT beta, const YT *z, YT *y, const int32_t *skip) {
+    if (skip && *skip) return;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = beta != (AT)0 ? (YT)(beta * (AT)z[i]) : (YT)0;
+}
+
 template <class VT, class XT, class YT, class AT, int LANES>
 static void launch_rem(const hec_matrix_s &A, const VT *rval, AT alpha, const XT *x, AT beta,
                        const YT *z, YT *y, bool first, hipStream_t s, const int32_t *skip) {
@@ -215,6 +334,28 @@ void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta
         rv = (const VT *)A.rem_val32.get();
     }
     bool first = A.K == 0;
+    if (A.coo) {
+        // HYB: ELL part (or y = beta z without one), then the COO remainder and its carries
+        if (first) {
+            k_spmv_beta<YT, AT><<<ceil_div(A.n, 256), 256, 0, s>>>(A.n, beta, z, y, skip);
+            HEC_CHECK_LAUNCH();
+        } else {
+            const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;
+            k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev, alpha, x, beta,
+                                                            z, y, skip);
+            HEC_CHECK_LAUNCH();
+        }
+        if (A.nnz_rem > 0) {
+            AT *cval = (AT *)A.carry_val.get();
+            k_spmv_coo<VT, XT, YT, AT><<<ceil_div((size_t)A.coo_tiles * 64, 256), 256, 0, s>>>(
+                A.nnz_rem, A.rem_row.get(), A.rem_col.get(), rv, alpha, x, y, A.carry_row.get(), cval, skip);
+            HEC_CHECK_LAUNCH();
+            k_coo_carry<YT, AT><<<ceil_div((size_t)A.coo_tiles, 256), 256, 0, s>>>(A.coo_tiles, A.carry_row.get(),
+                                                                                 cval, alpha, y, skip);
+            HEC_CHECK_LAUNCH();
+        }
+        return;
+    }
     if (!first) {
         const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;  // a multiple of 8 (XCD mapping)
         k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev,
@@ -273,7 +414,7 @@ hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const d
         if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
         validate_csr(n, Ap, Aj, Ax);
-        if (flags & ~HEC_KEEP_F32) fail(HEC_ERR_INVALID_ARG, "unknown flags");
+        if (flags & ~(HEC_KEEP_F32 | HEC_COO_REMAINDER)) fail(HEC_ERR_INVALID_ARG, "unknown flags");
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
         auto A = std::make_unique<hec_matrix_s>();
@@ -282,6 +423,16 @@ hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const d
         int32_t maxrow = 0;
         for (int32_t i = 0; i < n; ++i) maxrow = std::max(maxrow, Ap[i + 1] - Ap[i]);
         int32_t K = ell_width >= 0 ? ell_width : 20;
+        if (ell_width == HEC_WIDTH_HYB) {
+            // HYB rule: the largest K such that at least max(4096, n/3) rows hold K or more entries
+            std::vector<int64_t> atleast((size_t)maxrow + 2, 0);
+            for (int32_t i = 0; i < n; ++i) atleast[Ap[i + 1] - Ap[i]]++;
+            for (int32_t k = maxrow - 1; k >= 0; --k) atleast[k] += atleast[k + 1];
+            const int64_t need = std::max<int64_t>(4096, n / 3);
+            K = 0;
+            for (int32_t k = 1; k <= maxrow; ++k)
+                if (atleast[k] >= need) K = k;
+        }
         A->K = std::min(K, maxrow);
         A->ld = (int32_t)(((int64_t)n + 255) / 256 * 256);
         A->has_f32 = (flags & HEC_KEEP_F32) != 0;
@@ -317,6 +468,18 @@ hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const d
         A->rem_rows.alloc(rrows.size());
         A->rem_ptr.upload(rptr.data(), n + 1, s);
         A->rem_rows.upload(rrows.data(), rrows.size(), s);
+        std::vector<int32_t> rrow;
+        if (flags & HEC_COO_REMAINDER) {
+            A->coo = true;
+            rrow.resize(r);
+            for (int32_t i = 0; i < n; ++i)
+                for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e) rrow[e] = i;
+            A->coo_tiles = (r + kCooTile - 1) / kCooTile;
+            A->rem_row.alloc(r);
+            A->rem_row.upload(rrow.data(), r, s);
+            A->carry_row.alloc(2 * A->coo_tiles);
+            A->carry_val.alloc(2 * A->coo_tiles);
+        }
         // stage the CSR on the device and scatter it into the two parts
         DevBuf<int32_t> dAp(n + 1), dAj(A->nnz);
         DevBuf<double> dAx(A->nnz);

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libhec.so")
 OK, INVALID_ARG, NOMEM, ZERO_PIVOT, BREAKDOWN, NOT_CONVERGED, HIP_ERROR = range(7)
 F64, F32 = 0, 1
 KEEP_F32 = 1
+COO_REMAINDER = 2   # hec_from_csr flag: remainder as COO (HYB = ELL + COO)
+WIDTH_HYB = -2      # hec_from_csr ell_width: the HYB width rule
 LOWER, UPPER, LU = 1, 2, 3
 
 EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
@@ -184,11 +186,14 @@ class Batch(_Handle):
 
 # ---------------------------------------------------------------- HEC matrix
 
-def hec_from_csr(A, ell_width: int = -1, keep_f32: bool = False, stream=None) -> Matrix:
+def hec_from_csr(A, ell_width: int = -1, keep_f32: bool = False, coo: bool = False, stream=None) -> Matrix:
+    """HEC (default), plain ELL (ell_width >= longest row), CSR (ell_width = 0) or HYB
+    (coo=True, usually with ell_width=WIDTH_HYB) form of A on the device."""
     n, Ap, Aj, Ax = _csr(A)
     out = _vp()
+    flags = (KEEP_F32 if keep_f32 else 0) | (COO_REMAINDER if coo else 0)
     _check(load().hec_from_csr(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, ell_width,
-                               KEEP_F32 if keep_f32 else 0, _stream_or_null(stream), C.byref(out)),
+                               flags, _stream_or_null(stream), C.byref(out)),
            "hec_from_csr")
     return Matrix(out.value)
 

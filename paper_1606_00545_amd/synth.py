@@ -260,6 +260,49 @@ def workload_diffusion3d(m: int, sigma: float = 2.0, seed: int = 2, zscale: floa
     return A, uniform_vector(A.n, rng)
 
 
+def circuit_like(n: int, rng: np.random.Generator, nlong: int = 200, long_min: int = 2000,
+                 long_max: int = 20000) -> CSR:
+    """Banded rows with a few very long ones, the shape of circuit matrices (a stand-in
+    for the paper's circuit and power-network test matrices, which are not available).
+
+    Row i holds its diagonal and 2-6 further distinct columns within +-64 of it;
+    `nlong` rows (spread evenly) instead hold long_min..long_max distinct random
+    columns and the diagonal. Values ~ N(0,1) off the diagonal, diagonal = 1 + sum |off|.
+    """
+    k = rng.integers(2, 7, size=n)  # further columns drawn per banded row (duplicates merge)
+    offs = rng.integers(1, 65, size=(n, 6)) * np.where(rng.random((n, 6)) < 0.5, -1, 1)
+    cand = np.clip(np.arange(n)[:, None] + offs, 0, n - 1)
+    cand = np.where(np.arange(6)[None, :] < k[:, None], cand, n)  # n marks an unused draw
+    cand = np.sort(np.concatenate([cand, np.arange(n)[:, None]], axis=1), axis=1)
+    keep = cand < n
+    keep[:, 1:] &= cand[:, 1:] != cand[:, :-1]
+    long_rows = np.unique(np.linspace(0, n - 1, nlong).astype(np.int64)) if nlong else np.zeros(0, np.int64)
+    keep[long_rows] = False
+    lens = keep.sum(axis=1).astype(np.int64)
+    long_cols = []
+    for i in long_rows:
+        L = int(rng.integers(long_min, long_max + 1))
+        c = np.unique(np.concatenate([rng.choice(n, size=min(L, n), replace=False), [i]]))
+        long_cols.append(c)
+        lens[i] = c.size
+    Ap = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=Ap[1:])
+    Aj = np.empty(int(Ap[-1]), np.int32)
+    rank = np.cumsum(keep, axis=1) - 1
+    r, j = np.nonzero(keep)
+    Aj[Ap[r] + rank[r, j]] = cand[r, j]
+    for i, c in zip(long_rows, long_cols):
+        Aj[Ap[i]:Ap[i + 1]] = c
+    Ax = rng.standard_normal(Aj.size)
+    rows = np.repeat(np.arange(n), lens)
+    diag = Aj == rows
+    Ax[diag] = 0.0
+    rowabs = np.zeros(n)
+    np.add.at(rowabs, rows, np.abs(Ax))
+    Ax[diag] = 1.0 + rowabs[rows[diag]]
+    return CSR(n, Ap.astype(np.int32), Aj, Ax)
+
+
 def workload_powerlaw(n: int = 4_000_000, seed: int = 3):
     """Power-law random nonsymmetric matrix (mean row length 12, max 512): (A, x)."""
     rng = np.random.default_rng(seed)
