@@ -272,6 +272,57 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
 hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
                     const hec_solve_opts *opts, hec_solve_info *info, void *stream);
 
+/* ---------------------------------------------------------------- AMG (Sec. 2.8) */
+
+typedef struct hec_amg_s *hec_amg;
+
+typedef struct {
+    double theta;        /* strength threshold: j strongly influences i when
+                            -a_ij >= theta * max_{k != i} (-a_ik) > 0; in (0, 1] (0.25) */
+    int32_t max_levels;  /* most levels, the finest included; 1..32 (8, as Sec. 3.3) */
+    int32_t coarse_size; /* a level of at most this many rows is the coarsest; 1..4096 (64) */
+    double omega;        /* damped Jacobi weight; in (0, 2) (2/3) */
+    int32_t nu1, nu2;    /* pre- and post-smoothing sweeps; 0..64 (3 and 3, as Sec. 3.3) */
+} hec_amg_opts;
+
+/* Sec. 2.8: AMG setup on the host for the n x n CSR matrix (Ap, Aj, Ax: host
+ * arrays, 0-based, columns ascending; read during the call only). Per level:
+ * Ruge-Stueben strength and coarsening (first pass: largest measure first,
+ * smallest index on ties; points with no strong connection are F), direct
+ * interpolation P (the paper's RSD), R = P^T, A_{l+1} = R A_l P (Galerkin), until
+ * a level has at most coarse_size rows, max_levels levels exist or no coarsening
+ * happens; the coarsest level keeps its dense inverse. Every operator is uploaded
+ * as a HEC matrix; the handle owns them and the per-level vectors. opts may be
+ * NULL (the defaults above). Errors: INVALID_ARG for a malformed CSR, n == 0 or
+ * bad options; ZERO_PIVOT for a zero or missing diagonal on any level or a
+ * singular coarsest level. */
+hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, const hec_amg_opts *opts,
+                     void *stream, hec_amg *out);
+
+/* Hierarchy sizes: nlevels, and per level (arrays of nlevels entries, any may be
+ * NULL) the rows, the nonzeros of A_l and of P_l (0 on the coarsest level). */
+hec_status amg_info(hec_amg H, int32_t *nlevels, int32_t *n, int64_t *nnz, int64_t *nnz_p);
+
+/* Host copies of level `level`: its C/F splitting (n_l entries, 1 = C; not
+ * written on the coarsest level), A_l (n_l + 1, nnz, nnz) and P_l (n_l + 1,
+ * nnz_p, nnz_p; columns are coarse indices, C points numbered in row order).
+ * Any pointer may be NULL. */
+hec_status amg_export_level(hec_amg H, int32_t level, int8_t *cf, int32_t *Ap, int32_t *Aj, double *Ax,
+                            int32_t *Pp, int32_t *Pj, double *Px);
+
+/* Alg. 5: x = 0, then V-cycles (nu1 damped Jacobi sweeps, residual restricted by
+ * R, coarse correction from zero, prolongated by P and added, nu2 sweeps; the
+ * coarsest level solved with its inverse) until ||b - A x|| <= rtol ||b|| in FP64
+ * or maxit cycles. b, x: device FP64 vectors of n elements, not overlapping. The
+ * calls of one handle must not overlap in time (its per-level vectors are
+ * shared). Returns NOT_CONVERGED after maxit cycles (x holds the last iterate),
+ * BREAKDOWN on a non-finite residual; info (may be NULL) gets the cycles and the
+ * final relative residual. */
+hec_status amg_solve(hec_amg H, const double *b, double *x, int32_t maxit, double rtol, void *stream,
+                     hec_solve_info *info);
+
+hec_status amg_destroy(hec_amg H);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *hec_last_error(void);
 

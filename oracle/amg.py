@@ -1,0 +1,251 @@
+"""AMG oracle (test infrastructure only): the setup and the V-cycle of Sec. 2.8,
+Alg. 5, written out plainly in FP64 with numpy/scipy. Only the tests and the
+benchmark's CPU leg use it; it shares no code with the GPU library.
+
+* strength(A, theta): classical Ruge-Stueben strength. j strongly influences i
+  (j in S_i) when -a_ij >= theta * max_{k != i} (-a_ik) and that maximum is
+  positive.
+* rs_split(n, S): Ruge-Stueben coarsening, first pass. Points with no strong
+  connection either way are F. Every other point starts undecided with measure
+  lambda_i = |S_i^T| (how many points it strongly influences). Repeatedly the
+  undecided point of largest measure (smallest index on ties) becomes C; the
+  undecided points it strongly influences become F, and each undecided point
+  that strongly influences a new F point gains 1; each undecided point that
+  strongly influences the new C point loses 1.
+* direct_interpolation(A, S, cf): "RSD" (Stueben's direct interpolation). A C
+  point injects its coarse value. An F point i interpolates from its strong C
+  neighbours C_i, separately for negative and positive couplings:
+  w_ij = -alpha_i a_ij / a_ii (a_ij < 0), w_ij = -beta_i a_ij / a_ii (a_ij > 0),
+  alpha_i = sum_{k != i, a_ik < 0} a_ik / sum_{j in C_i, a_ij < 0} a_ij and beta_i
+  likewise over positive entries; when C_i holds no positive coupling, the
+  positive entries are added to the diagonal instead.
+* galerkin(A, P): A_c = P^T A P (R = P^T), in a stated order: (AP)_iJ sums
+  a_ik p_kJ over row i of A in column order; (A_c)_IJ sums p_iI (AP)_iJ over the
+  fine rows i in ascending order. Every entry touched is kept, zero or not.
+* hierarchy(A, ...): levels A_0 = A, A_{l+1} = galerkin(A_l, P_l) until a level
+  has at most coarse_size rows, max_levels levels exist, or coarsening stops (no C
+  point, or no reduction); the coarsest level is solved exactly.
+* vcycle / solve: Alg. 5 with damped Jacobi pre- and post-smoothing,
+  x <- x + omega D^{-1} (b - A x), nu1 and nu2 sweeps.
+"""
+from __future__ import annotations
+
+import heapq
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _csr(A) -> sp.csr_matrix:
+    M = sp.csr_matrix((np.asarray(A.Ax, np.float64), np.asarray(A.Aj), np.asarray(A.Ap)), shape=(A.n, A.n))
+    M.sort_indices()
+    return M
+
+
+def strength(M: sp.csr_matrix, theta: float):
+    """S as a CSR pattern (row i: the points that strongly influence i), columns ascending."""
+    n = M.shape[0]
+    Sp, Sj = [0], []
+    for i in range(n):
+        cols = M.indices[M.indptr[i]:M.indptr[i + 1]]
+        vals = M.data[M.indptr[i]:M.indptr[i + 1]]
+        off = cols != i
+        m = (-vals[off]).max(initial=0.0)
+        if m > 0.0:
+            Sj.extend(int(c) for c, v in zip(cols[off], vals[off]) if -v >= theta * m)
+        Sp.append(len(Sj))
+    return np.array(Sp, np.int64), np.array(Sj, np.int64)
+
+
+def _transpose_pattern(n, Sp, Sj):
+    cnt = np.bincount(Sj, minlength=n) if Sj.size else np.zeros(n, np.int64)
+    Tp = np.concatenate([[0], np.cumsum(cnt)])
+    Tj = np.empty(Sj.size, np.int64)
+    fill = Tp[:-1].copy()
+    for i in range(n):
+        for j in Sj[Sp[i]:Sp[i + 1]]:
+            Tj[fill[j]] = i
+            fill[j] += 1
+    return Tp, Tj
+
+
+def rs_split(n, Sp, Sj):
+    """cf[i] = 1 for C, 0 for F (first pass of Ruge-Stueben coarsening)."""
+    Tp, Tj = _transpose_pattern(n, Sp, Sj)
+    U, C, F = 0, 1, 2
+    state = np.full(n, U, np.int8)
+    lam = (Tp[1:] - Tp[:-1]).astype(np.int64)
+    for i in range(n):
+        if Sp[i + 1] == Sp[i] and Tp[i + 1] == Tp[i]:
+            state[i] = F  # no strong connection either way
+    heap = [(-int(lam[i]), i) for i in range(n) if state[i] == U]
+    heapq.heapify(heap)
+    while heap:
+        negl, i = heapq.heappop(heap)
+        if state[i] != U or -negl != lam[i]:
+            continue  # stale entry
+        state[i] = C
+        for j in Tj[Tp[i]:Tp[i + 1]]:  # points i strongly influences
+            if state[j] == U:
+                state[j] = F
+                for k in Sj[Sp[j]:Sp[j + 1]]:  # points that strongly influence the new F point
+                    if state[k] == U:
+                        lam[k] += 1
+                        heapq.heappush(heap, (-int(lam[k]), int(k)))
+        for k in Sj[Sp[i]:Sp[i + 1]]:  # points that strongly influence the new C point
+            if state[k] == U:
+                lam[k] -= 1
+                heapq.heappush(heap, (-int(lam[k]), int(k)))
+    return (state == C).astype(np.int8)
+
+
+def direct_interpolation(M: sp.csr_matrix, Sp, Sj, cf):
+    """P (n x nc) as a scipy CSR matrix with columns ascending."""
+    n = M.shape[0]
+    cidx = np.cumsum(cf) - 1  # coarse index of each C point
+    nc = int(cf.sum())
+    Pp, Pj, Px = [0], [], []
+    for i in range(n):
+        if cf[i]:
+            Pj.append(int(cidx[i]))
+            Px.append(1.0)
+            Pp.append(len(Pj))
+            continue
+        cols = M.indices[M.indptr[i]:M.indptr[i + 1]]
+        vals = M.data[M.indptr[i]:M.indptr[i + 1]]
+        strong = set(int(j) for j in Sj[Sp[i]:Sp[i + 1]])
+        aii = 0.0
+        sneg = spos = cneg = cpos = 0.0
+        for j, v in zip(cols, vals):
+            if j == i:
+                aii = v
+            elif v < 0:
+                sneg += v
+            else:
+                spos += v
+        Ci = [(int(j), v) for j, v in zip(cols, vals) if j != i and j in strong and cf[j]]
+        for j, v in Ci:
+            if v < 0:
+                cneg += v
+            else:
+                cpos += v
+        if cpos == 0.0:
+            aii += spos  # no positive coupling to interpolate from: lump onto the diagonal
+        alpha = sneg / cneg if cneg != 0.0 else 0.0
+        beta = spos / cpos if cpos != 0.0 else 0.0
+        for j, v in Ci:
+            w = -(alpha if v < 0 else beta) * v / aii
+            Pj.append(int(cidx[j]))
+            Px.append(w)
+        Pp.append(len(Pj))
+    P = sp.csr_matrix((np.array(Px), np.array(Pj, np.int64), np.array(Pp, np.int64)), shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+def galerkin(M: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
+    n, nc = P.shape
+    AP = []
+    for i in range(n):
+        acc = {}
+        for e in range(M.indptr[i], M.indptr[i + 1]):
+            k, a = int(M.indices[e]), float(M.data[e])
+            for f in range(P.indptr[k], P.indptr[k + 1]):
+                J = int(P.indices[f])
+                acc[J] = acc.get(J, 0.0) + a * float(P.data[f])
+        AP.append(acc)
+    rows = [dict() for _ in range(nc)]
+    for i in range(n):
+        for f in range(P.indptr[i], P.indptr[i + 1]):
+            I, p = int(P.indices[f]), float(P.data[f])
+            acc = rows[I]
+            for J, v in AP[i].items():
+                acc[J] = acc.get(J, 0.0) + p * v
+    Cp, Cj, Cx = [0], [], []
+    for I in range(nc):
+        for J in sorted(rows[I]):
+            Cj.append(J)
+            Cx.append(rows[I][J])
+        Cp.append(len(Cj))
+    return sp.csr_matrix((np.array(Cx), np.array(Cj, np.int64), np.array(Cp, np.int64)), shape=(nc, nc))
+
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    cf: np.ndarray = None
+    P: sp.csr_matrix = None
+    dinv: np.ndarray = field(default=None)
+
+
+@dataclass
+class Hierarchy:
+    levels: list
+    omega: float
+    nu1: int
+    nu2: int
+
+
+def hierarchy(A, theta=0.25, max_levels=8, coarse_size=64, omega=2.0 / 3.0, nu1=3, nu2=3) -> Hierarchy:
+    M = _csr(A)
+    levels = []
+    while True:
+        lev = Level(M, dinv=1.0 / M.diagonal())
+        levels.append(lev)
+        n = M.shape[0]
+        if n <= coarse_size or len(levels) == max_levels:
+            break
+        Sp, Sj = strength(M, theta)
+        cf = rs_split(n, Sp, Sj)
+        nc = int(cf.sum())
+        if nc == 0 or nc == n:
+            break
+        P = direct_interpolation(M, Sp, Sj, cf)
+        lev.cf, lev.P = cf, P
+        M = galerkin(M, P)
+    return Hierarchy(levels, omega, nu1, nu2)
+
+
+def _jacobi(lev: Level, x, b, omega, sweeps):
+    for _ in range(sweeps):
+        x = x + omega * lev.dinv * (b - lev.A @ x)
+    return x
+
+
+def vcycle(H: Hierarchy, b, x=None, l=0):
+    """Alg. 5 from level l: pre-smooth, restrict the residual, recurse, prolongate, post-smooth;
+    the coarsest level is solved exactly."""
+    lev = H.levels[l]
+    if l == len(H.levels) - 1:
+        return np.linalg.solve(lev.A.toarray(), b)
+    x = np.zeros_like(b) if x is None else x
+    x = _jacobi(lev, x, b, H.omega, H.nu1)
+    r = b - lev.A @ x
+    xc = vcycle(H, lev.P.T @ r, None, l + 1)
+    x = x + lev.P @ xc
+    return _jacobi(lev, x, b, H.omega, H.nu2)
+
+
+@dataclass
+class AmgResult:
+    x: np.ndarray
+    iterations: int
+    rel_res: float
+    converged: bool
+
+
+def solve(H: Hierarchy, b, rtol=1e-8, maxit=100) -> AmgResult:
+    """V-cycles from x = 0 until ||b - A x|| <= rtol ||b|| (FP64 residual) or maxit."""
+    A = H.levels[0].A
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if nb == 0.0:
+        return AmgResult(x, 0, 0.0, True)
+    res = 1.0
+    for it in range(1, maxit + 1):
+        x = vcycle(H, b, x)
+        res = np.linalg.norm(b - A @ x) / nb
+        if res <= rtol:
+            return AmgResult(x, it, res, True)
+    return AmgResult(x, maxit, res, False)

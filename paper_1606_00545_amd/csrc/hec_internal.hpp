@@ -117,7 +117,8 @@ inline unsigned ceil_div(size_t a, size_t b) { return (unsigned)((a + b - 1) / b
 // ------------------------------------------------------------------ host CSR checks
 
 // Validates a host CSR (Ap monotone from 0, columns strictly ascending and in range).
-void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax);
+// ncols < 0: a square matrix (columns < n)
+void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t ncols = -1);
 
 }  // namespace hec
 
@@ -154,6 +155,13 @@ struct hec_matrix_s {
     hec::DevBuf<double> carry_val;   // 2 * coo_tiles slots of 8 bytes (holds FP32 sums for FP32 values)
     std::unique_ptr<hec::KrylovWS, hec::KrylovWSDeleter> ws;
 };
+
+namespace hec {
+// HEC (HYB, ELL, CSR) form of an n x ncols CSR matrix already validated; hec_from_csr's
+// ell_width and flags.
+std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *Ap, const int32_t *Aj,
+                                       const double *Ax, int32_t ell_width, uint32_t flags, hipStream_t s);
+}  // namespace hec
 
 struct hec_ilu_s {
     int32_t n = 0, k = 0;   // n: size of the factor (the stacked extended blocks for RAS)

@@ -38,7 +38,8 @@ void ensure_pool() {
     done_dev = dev;
 }
 
-void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax) {
+void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t ncols) {
+    if (ncols < 0) ncols = n;
     if (n < 0) fail(HEC_ERR_INVALID_ARG, "n < 0");
     if (!Ap) fail(HEC_ERR_INVALID_ARG, "Ap is NULL");
     if (Ap[0] != 0) fail(HEC_ERR_INVALID_ARG, "Ap[0] != 0");
@@ -48,7 +49,7 @@ void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double 
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
             int32_t j = Aj[e];
-            if (j < 0 || j >= n)
+            if (j < 0 || j >= ncols)
                 fail(HEC_ERR_INVALID_ARG, "column index out of range in row " + std::to_string(i));
             if (e > Ap[i] && j <= Aj[e - 1])
                 fail(HEC_ERR_INVALID_ARG, "columns not strictly ascending in row " + std::to_string(i));
@@ -59,7 +60,7 @@ void validate_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double 
 // ------------------------------------------------------------------ conversion kernels
 
 // One thread per slab row i < ld: writes the K slots of row i (coalesced across i).
-__global__ __launch_bounds__(256) void k_hec_fill_ell(int32_t n, int32_t K, int32_t ld,
+__global__ __launch_bounds__(256) void k_hec_fill_ell(int32_t n, int32_t ncols, int32_t K, int32_t ld,
                                                       const int32_t *__restrict__ Ap,
                                                       const int32_t *__restrict__ Aj,
                                                       const double *__restrict__ Ax,
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void k_hec_fill_ell(int32_t n, int32_t K, int3
             c = Aj[a + s];
             v = Ax[a + s];
         } else {
-            c = i < n ? i : 0;
+            c = i < n && i < ncols ? i : 0;  // padding: any valid column, value 0
             v = 0.0;
         }
         ell_col[slot] = c;
@@ -400,6 +401,95 @@ template void spmv_launch<float, double, float>(const hec_matrix_s &, double, co
                                                   const float *, float *, hipStream_t,
                                                   const int32_t *);
 
+// The HEC (or HYB, ELL, CSR) form of an n x ncols CSR matrix (validated by the
+// caller); also used for the rectangular transfer operators of AMG.
+std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *Ap, const int32_t *Aj,
+                                       const double *Ax, int32_t ell_width, uint32_t flags, hipStream_t s) {
+    auto A = std::make_unique<hec_matrix_s>();
+    A->n = n;
+    A->nnz = Ap[n];
+    int32_t maxrow = 0;
+    for (int32_t i = 0; i < n; ++i) maxrow = std::max(maxrow, Ap[i + 1] - Ap[i]);
+    int32_t K = ell_width >= 0 ? ell_width : 20;
+    if (ell_width == HEC_WIDTH_HYB) {
+        // HYB rule: the largest K such that at least max(4096, n/3) rows hold K or more entries
+        std::vector<int64_t> atleast((size_t)maxrow + 2, 0);
+        for (int32_t i = 0; i < n; ++i) atleast[Ap[i + 1] - Ap[i]]++;
+        for (int32_t k = maxrow - 1; k >= 0; --k) atleast[k] += atleast[k + 1];
+        const int64_t need = std::max<int64_t>(4096, n / 3);
+        K = 0;
+        for (int32_t k = 1; k <= maxrow; ++k)
+            if (atleast[k] >= need) K = k;
+    }
+    A->K = std::min(K, maxrow);
+    A->ld = (int32_t)(((int64_t)n + 255) / 256 * 256);
+    A->has_f32 = (flags & HEC_KEEP_F32) != 0;
+    // remainder row pointer and row list (host prefix sum)
+    std::vector<int32_t> rptr(n + 1);
+    std::vector<int32_t> rrows;
+    int64_t r = 0;
+    rptr[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t len = Ap[i + 1] - Ap[i];
+        int32_t extra = len > A->K ? len - A->K : 0;
+        if (A->K == 0 || extra > 0) rrows.push_back(i);
+        r += extra;
+        rptr[i + 1] = (int32_t)r;
+    }
+    A->nnz_rem = r;
+    A->n_rem_rows = (int32_t)rrows.size();
+    {
+        // lanes per remainder row: the power of two nearest the mean remainder length
+        double mean = rrows.empty() ? 0.0 : (double)r / rrows.size();
+        int lanes = 2;
+        while (lanes < 64 && lanes * 1.5 < mean) lanes *= 2;
+        A->rem_lanes = lanes;
+    }
+    size_t slab = (size_t)A->K * A->ld;
+    A->ell_col.alloc(slab);
+    A->ell_val.alloc(slab);
+    if (A->has_f32) A->ell_val32.alloc(slab);
+    A->rem_ptr.alloc(n + 1);
+    A->rem_col.alloc(r);
+    A->rem_val.alloc(r);
+    if (A->has_f32) A->rem_val32.alloc(r);
+    A->rem_rows.alloc(rrows.size());
+    A->rem_ptr.upload(rptr.data(), n + 1, s);
+    A->rem_rows.upload(rrows.data(), rrows.size(), s);
+    std::vector<int32_t> rrow;
+    if (flags & HEC_COO_REMAINDER) {
+        A->coo = true;
+        rrow.resize(r);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e) rrow[e] = i;
+        A->coo_tiles = (r + kCooTile - 1) / kCooTile;
+        A->rem_row.alloc(r);
+        A->rem_row.upload(rrow.data(), r, s);
+        A->carry_row.alloc(2 * A->coo_tiles);
+        A->carry_val.alloc(2 * A->coo_tiles);
+    }
+    // stage the CSR on the device and scatter it into the two parts
+    DevBuf<int32_t> dAp(n + 1), dAj(A->nnz);
+    DevBuf<double> dAx(A->nnz);
+    dAp.upload(Ap, n + 1, s);
+    dAj.upload(Aj, A->nnz, s);
+    dAx.upload(Ax, A->nnz, s);
+    if (slab) {
+        k_hec_fill_ell<<<ceil_div(A->ld, 256), 256, 0, s>>>(n, ncols, A->K, A->ld, dAp.get(), dAj.get(),
+                                                            dAx.get(), A->ell_col.get(), A->ell_val.get(),
+                                                            A->ell_val32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    if (r && n) {
+        k_hec_fill_rem<<<ceil_div(n, 256), 256, 0, s>>>(n, A->K, dAp.get(), dAj.get(), dAx.get(),
+                                                        A->rem_ptr.get(), A->rem_col.get(),
+                                                        A->rem_val.get(), A->rem_val32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    HEC_HIP(hipStreamSynchronize(s));
+    return A;
+}
+
 }  // namespace hec
 
 using namespace hec;
@@ -417,89 +507,7 @@ hec_status hec_from_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const d
         if (flags & ~(HEC_KEEP_F32 | HEC_COO_REMAINDER)) fail(HEC_ERR_INVALID_ARG, "unknown flags");
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
-        auto A = std::make_unique<hec_matrix_s>();
-        A->n = n;
-        A->nnz = Ap[n];
-        int32_t maxrow = 0;
-        for (int32_t i = 0; i < n; ++i) maxrow = std::max(maxrow, Ap[i + 1] - Ap[i]);
-        int32_t K = ell_width >= 0 ? ell_width : 20;
-        if (ell_width == HEC_WIDTH_HYB) {
-            // HYB rule: the largest K such that at least max(4096, n/3) rows hold K or more entries
-            std::vector<int64_t> atleast((size_t)maxrow + 2, 0);
-            for (int32_t i = 0; i < n; ++i) atleast[Ap[i + 1] - Ap[i]]++;
-            for (int32_t k = maxrow - 1; k >= 0; --k) atleast[k] += atleast[k + 1];
-            const int64_t need = std::max<int64_t>(4096, n / 3);
-            K = 0;
-            for (int32_t k = 1; k <= maxrow; ++k)
-                if (atleast[k] >= need) K = k;
-        }
-        A->K = std::min(K, maxrow);
-        A->ld = (int32_t)(((int64_t)n + 255) / 256 * 256);
-        A->has_f32 = (flags & HEC_KEEP_F32) != 0;
-        // remainder row pointer and row list (host prefix sum)
-        std::vector<int32_t> rptr(n + 1);
-        std::vector<int32_t> rrows;
-        int64_t r = 0;
-        rptr[0] = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t len = Ap[i + 1] - Ap[i];
-            int32_t extra = len > A->K ? len - A->K : 0;
-            if (A->K == 0 || extra > 0) rrows.push_back(i);
-            r += extra;
-            rptr[i + 1] = (int32_t)r;
-        }
-        A->nnz_rem = r;
-        A->n_rem_rows = (int32_t)rrows.size();
-        {
-            // lanes per remainder row: the power of two nearest the mean remainder length
-            double mean = rrows.empty() ? 0.0 : (double)r / rrows.size();
-            int lanes = 2;
-            while (lanes < 64 && lanes * 1.5 < mean) lanes *= 2;
-            A->rem_lanes = lanes;
-        }
-        size_t slab = (size_t)A->K * A->ld;
-        A->ell_col.alloc(slab);
-        A->ell_val.alloc(slab);
-        if (A->has_f32) A->ell_val32.alloc(slab);
-        A->rem_ptr.alloc(n + 1);
-        A->rem_col.alloc(r);
-        A->rem_val.alloc(r);
-        if (A->has_f32) A->rem_val32.alloc(r);
-        A->rem_rows.alloc(rrows.size());
-        A->rem_ptr.upload(rptr.data(), n + 1, s);
-        A->rem_rows.upload(rrows.data(), rrows.size(), s);
-        std::vector<int32_t> rrow;
-        if (flags & HEC_COO_REMAINDER) {
-            A->coo = true;
-            rrow.resize(r);
-            for (int32_t i = 0; i < n; ++i)
-                for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e) rrow[e] = i;
-            A->coo_tiles = (r + kCooTile - 1) / kCooTile;
-            A->rem_row.alloc(r);
-            A->rem_row.upload(rrow.data(), r, s);
-            A->carry_row.alloc(2 * A->coo_tiles);
-            A->carry_val.alloc(2 * A->coo_tiles);
-        }
-        // stage the CSR on the device and scatter it into the two parts
-        DevBuf<int32_t> dAp(n + 1), dAj(A->nnz);
-        DevBuf<double> dAx(A->nnz);
-        dAp.upload(Ap, n + 1, s);
-        dAj.upload(Aj, A->nnz, s);
-        dAx.upload(Ax, A->nnz, s);
-        if (slab) {
-            k_hec_fill_ell<<<ceil_div(A->ld, 256), 256, 0, s>>>(n, A->K, A->ld, dAp.get(), dAj.get(),
-                                                                dAx.get(), A->ell_col.get(), A->ell_val.get(),
-                                                                A->ell_val32.get());
-            HEC_CHECK_LAUNCH();
-        }
-        if (r && n) {
-            k_hec_fill_rem<<<ceil_div(n, 256), 256, 0, s>>>(n, A->K, dAp.get(), dAj.get(), dAx.get(),
-                                                            A->rem_ptr.get(), A->rem_col.get(),
-                                                            A->rem_val.get(), A->rem_val32.get());
-            HEC_CHECK_LAUNCH();
-        }
-        HEC_HIP(hipStreamSynchronize(s));
-        *out = A.release();
+        *out = make_hec(n, n, Ap, Aj, Ax, ell_width, flags, s).release();
     });
 }
 

@@ -28,7 +28,8 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "ilu_factor", "ilu_factor_ras", "ilu_info", "ilu_ras_export", "ilu_export", "ilu_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve", "cg_solve",
-            "batch_create", "batch_destroy", "gmres_solve_batched", "hec_last_error")
+            "batch_create", "batch_destroy", "gmres_solve_batched",
+            "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy", "hec_last_error")
 BATCH_MAX_N = 8192
 
 
@@ -42,6 +43,11 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("precision", C.c_int32),
                 ("x0_zero", C.c_int32), ("rtol", C.c_double), ("ir_rtol", C.c_double),
                 ("inner_rtol", C.c_double)]
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("max_levels", C.c_int32), ("coarse_size", C.c_int32),
+                ("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -96,6 +102,11 @@ def load(path: str = LIB_PATH):
     L.batch_destroy.argtypes = [_vp]
     L.gmres_solve_batched.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts),
                                       _vp, _vp]
+    L.amg_setup.argtypes = [C.c_int32, _vp, _vp, _vp, C.POINTER(AmgOpts), _vp, C.POINTER(_vp)]
+    L.amg_info.argtypes = [_vp, _i32p, _vp, _vp, _vp]
+    L.amg_export_level.argtypes = [_vp, C.c_int32] + [_vp] * 7
+    L.amg_solve.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_double, _vp, C.POINTER(SolveInfo)]
+    L.amg_destroy.argtypes = [_vp]
     for name in EXPORTED:
         if name != "hec_last_error":
             getattr(L, name).restype = C.c_int
@@ -171,6 +182,10 @@ class Factor(_Handle):
 
 class Levels(_Handle):
     _destroy = "levels_destroy"
+
+
+class Amg(_Handle):
+    _destroy = "amg_destroy"
 
 
 class Batch(_Handle):
@@ -374,3 +389,52 @@ def gmres_solve_batched(B: Batch, systems, maxit: int = 10000, rtol: float = 1e-
     if check and code != OK:
         _check(code, "gmres_solve_batched")
     return [infos[i].as_dict() for i in range(count)]
+
+
+# ------------------------------------------------------------------ AMG (Sec. 2.8)
+
+def amg_setup(A, theta: float = 0.25, max_levels: int = 8, coarse_size: int = 64, omega: float = 2.0 / 3.0,
+              nu1: int = 3, nu2: int = 3, stream=None) -> Amg:
+    n, Ap, Aj, Ax = _csr(A)
+    o = AmgOpts(theta, max_levels, coarse_size, omega, nu1, nu2)
+    out = _vp()
+    _check(load().amg_setup(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, C.byref(o),
+                            _stream_or_null(stream), C.byref(out)), "amg_setup")
+    return Amg(out.value)
+
+
+def amg_info(H: Amg) -> dict:
+    nl = C.c_int32()
+    _check(load().amg_info(H.ptr, C.byref(nl), None, None, None), "amg_info")
+    n = np.zeros(nl.value, np.int32)
+    nnz = np.zeros(nl.value, np.int64)
+    nnzp = np.zeros(nl.value, np.int64)
+    _check(load().amg_info(H.ptr, C.byref(nl), n.ctypes.data, nnz.ctypes.data, nnzp.ctypes.data), "amg_info")
+    return {"levels": nl.value, "n": n.tolist(), "nnz": nnz.tolist(), "nnz_p": nnzp.tolist()}
+
+
+def amg_export_level(H: Amg, level: int) -> dict:
+    d = amg_info(H)
+    n, nnz, nnzp = d["n"][level], d["nnz"][level], d["nnz_p"][level]
+    cf = np.zeros(n, np.int8)
+    Ap, Aj, Ax = np.zeros(n + 1, np.int32), np.zeros(max(nnz, 1), np.int32), np.zeros(max(nnz, 1))
+    coarsest = level == d["levels"] - 1
+    Pp = np.zeros(n + 1, np.int32)
+    Pj, Px = np.zeros(max(nnzp, 1), np.int32), np.zeros(max(nnzp, 1))
+    _check(load().amg_export_level(H.ptr, level, None if coarsest else cf.ctypes.data, Ap.ctypes.data,
+                                   Aj.ctypes.data, Ax.ctypes.data, None if coarsest else Pp.ctypes.data,
+                                   Pj.ctypes.data, Px.ctypes.data), "amg_export_level")
+    out = {"A": (Ap, Aj[:nnz], Ax[:nnz])}
+    if not coarsest:
+        out.update(cf=cf, P=(Pp, Pj[:nnzp], Px[:nnzp]))
+    return out
+
+
+def amg_solve(H: Amg, b, x, maxit: int = 100, rtol: float = 1e-8, stream=None, check: bool = True) -> dict:
+    import torch
+    info = SolveInfo()
+    code = load().amg_solve(H.ptr, _dev(b, torch.float64), _dev(x, torch.float64), maxit, rtol, _stream(stream),
+                            C.byref(info))
+    if check and code != OK:
+        _check(code, "amg_solve")
+    return info.as_dict()

@@ -1,0 +1,140 @@
+"""Pins of the AMG oracle (Sec. 2.8, Alg. 5).
+
+Closed forms of Ruge-Stueben coarsening and direct interpolation on the 1D
+Laplacian; preservation of constants by direct interpolation on zero-row-sum
+rows; the first pass of the coarsening against a brute-force rescan on small
+random strength graphs; the Galerkin coarse-grid correction being exact on the
+coarse space; the symmetry of the V-cycle operator with matching pre- and
+post-smoothing; exact Jacobi on a diagonal matrix; and the single-level case."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import amg
+from paper_1606_00545_amd import synth
+from tests._mats import from_dense
+
+
+def test_1d_laplacian_closed_forms():
+    n = 17
+    H = amg.hierarchy(synth.poisson1d(n), coarse_size=2)
+    lev = H.levels[0]
+    assert np.array_equal(lev.cf, (np.arange(n) % 2 == 1).astype(np.int8))  # every other point is C
+    P = lev.P.toarray()
+    for i in range(n):
+        if i % 2:
+            assert P[i].tolist() == [1.0 if c == i // 2 else 0.0 for c in range(P.shape[1])]
+        else:  # linear interpolation from the two C neighbours (one at the ends)
+            want = np.zeros(P.shape[1])
+            for j in (i - 1, i + 1):
+                if 0 <= j < n:
+                    want[j // 2] = 0.5
+            assert np.array_equal(P[i], want)
+    Ac = H.levels[1].A.toarray()
+    nc = Ac.shape[0]
+    assert np.array_equal(Ac, np.diag(np.ones(nc)) - 0.5 * (np.eye(nc, k=1) + np.eye(nc, k=-1)))
+
+
+def test_direct_interpolation_preserves_constants_on_zero_row_sums():
+    A = synth.poisson3d(10)
+    H = amg.hierarchy(A, coarse_size=10)
+    M, P = H.levels[0].A, H.levels[0].P
+    rowsum = np.asarray(M.sum(axis=1)).ravel()
+    psum = np.asarray(P.sum(axis=1)).ravel()
+    z = rowsum == 0
+    assert z.any()
+    assert np.allclose(psum[z], 1.0, rtol=0, atol=1e-14)
+    assert (psum[~z] <= 1.0 + 1e-14).all()
+
+
+def _brute_split(n, Sp, Sj):
+    """Ruge-Stueben first pass by rescanning every undecided point at each step."""
+    T = [[] for _ in range(n)]
+    for i in range(n):
+        for j in Sj[Sp[i]:Sp[i + 1]]:
+            T[j].append(i)
+    state = ["U"] * n
+    lam = [len(T[i]) for i in range(n)]
+    for i in range(n):
+        if Sp[i + 1] == Sp[i] and not T[i]:
+            state[i] = "F"
+    while "U" in state:
+        best = max((lam[i], -i) for i in range(n) if state[i] == "U")
+        i = -best[1]
+        state[i] = "C"
+        for j in T[i]:
+            if state[j] == "U":
+                state[j] = "F"
+                for k in Sj[Sp[j]:Sp[j + 1]]:
+                    if state[k] == "U":
+                        lam[k] += 1
+        for k in Sj[Sp[i]:Sp[i + 1]]:
+            if state[k] == "U":
+                lam[k] -= 1
+    return np.array([s == "C" for s in state], np.int8)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_first_pass_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 60
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in rng.choice(n, size=int(rng.integers(0, 6)), replace=False):
+            if j != i:
+                D[i, j] = -rng.uniform(0.05, 1.0)
+        D[i, i] = 1.0 - D[i].sum()
+    M = sp.csr_matrix(D)
+    M.sort_indices()
+    Sp, Sj = amg.strength(M, 0.25)
+    assert np.array_equal(amg.rs_split(n, Sp, Sj), _brute_split(n, Sp, Sj))
+
+
+def test_coarse_grid_correction_is_exact_on_the_coarse_space():
+    # with no smoothing and an exact coarse solve, one cycle returns P y for b = A P y
+    A = synth.lognormal_tpfa((9, 8, 7), 1.5, np.random.default_rng(3))
+    H = amg.hierarchy(A, max_levels=2, coarse_size=1, nu1=0, nu2=0)
+    assert len(H.levels) == 2
+    P = H.levels[0].P
+    y = np.random.default_rng(4).uniform(-1, 1, P.shape[1])
+    b = H.levels[0].A @ (P @ y)
+    x = amg.vcycle(H, b)
+    assert np.linalg.norm(x - P @ y) <= 1e-12 * np.linalg.norm(P @ y)
+
+
+def test_vcycle_operator_is_symmetric():
+    A = synth.lognormal_tpfa((12, 10, 8), 2.0, np.random.default_rng(5))
+    H = amg.hierarchy(A, coarse_size=20)
+    assert len(H.levels) >= 3
+    rng = np.random.default_rng(6)
+    u, v = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    a, b = u @ amg.vcycle(H, v), v @ amg.vcycle(H, u)
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def test_diagonal_matrix_is_one_level_and_exact():
+    d = np.arange(1.0, 101.0)
+    A = from_dense(np.diag(d))
+    H = amg.hierarchy(A, coarse_size=10)
+    assert len(H.levels) == 1  # no strong connections: nothing to coarsen
+    b = np.ones(100)
+    r = amg.solve(H, b)
+    assert r.iterations == 1 and np.allclose(r.x, 1.0 / d, rtol=1e-15, atol=0)
+
+
+def test_jacobi_with_unit_weight_is_exact_on_a_diagonal_level():
+    d = np.arange(2.0, 202.0)
+    A = from_dense(np.diag(d))
+    H = amg.hierarchy(A, coarse_size=1000, omega=1.0)
+    lev = H.levels[0]
+    x = amg._jacobi(lev, np.zeros(200), np.ones(200), 1.0, 1)
+    assert np.array_equal(x, 1.0 / d)
+
+
+def test_3d_poisson_converges_in_few_cycles():
+    A = synth.poisson3d(20)
+    H = amg.hierarchy(A)
+    b = np.random.default_rng(7).uniform(-1, 1, A.n)
+    r = amg.solve(H, b, rtol=1e-8)
+    assert r.converged and r.iterations <= 12
+    assert np.linalg.norm(b - H.levels[0].A @ r.x) <= 1e-8 * np.linalg.norm(b)
