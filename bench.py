@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
                    choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "iluk", "formats",
-                            "copy"],
+                            "amg", "copy"],
                    help="diffusion128 is the benchmark line; the others print extra records "
                         "(copy: a plain 1 GiB device copy, the reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=200, help="serving: number of requests")
@@ -128,6 +128,59 @@ def formats_table():
         res.append(row)
         del A
     return {"formats": res, "note": "FP64 values and vectors; speedup = one-core oracle CSR SpMV time / GPU time"}
+
+
+def amg_table():
+    """Tables 6-7 of the paper (AMG with RS coarsening, direct interpolation and damped
+    Jacobi, V-cycle, at most 8 levels, 3 + 3 sweeps) on the paper's 3D Poisson 50^3 and
+    a 1000 x 1000 2D lognormal diffusion stand-in for ecology2: setup time, hierarchy,
+    V-cycles to 1e-8 and solve time on the GPU; the oracle's V-cycle solve on one host
+    core beside it for the 50^3 case (its pure-Python setup is too slow for 10^6 rows)."""
+    import torch
+    import oracle.amg as OA
+    from paper_1606_00545_amd import hec, synth
+    dev = "cuda"
+    res = []
+    try:
+        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+    except (AttributeError, OSError):
+        pass
+    for name, mk, cpu in (("3D Poisson 50^3 (the paper's)", lambda: synth.poisson3d(50), True),
+                          ("2D lognormal diffusion 1000^2, sigma 2 (stand-in for ecology2)",
+                           lambda: synth.lognormal_tpfa((1000, 1000), 2.0, np.random.default_rng(8)), False)):
+        A = mk()
+        xt = np.random.default_rng(9).uniform(-1, 1, A.n)
+        ts = time.time()
+        G = hec.amg_setup(A)
+        t_setup = time.time() - ts
+        info = hec.amg_info(G)
+        opc = sum(info["nnz"]) / info["nnz"][0]
+        Mh = hec.hec_from_csr(A)
+        xd = torch.from_numpy(xt).to(dev)
+        b = torch.empty_like(xd)
+        hec.hec_spmv(Mh, xd, b)
+        runs = []
+        for _ in range(3):
+            x = torch.empty_like(b)
+            inf = hec.amg_solve(G, b, x, maxit=200, rtol=1e-8)
+            runs.append(inf)
+        best = min(runs, key=lambda r: r["seconds"])
+        row = {"matrix": name, "n": A.n, "nnz": A.nnz, "setup_s": round(t_setup, 3), "levels": info["levels"],
+               "level_rows": info["n"], "operator_complexity": round(opc, 3), "cycles": best["iterations"],
+               "rel_res": best["rel_res_true"], "gpu_solve_s": round(best["seconds"], 4),
+               "ms_per_cycle": round(best["seconds"] * 1e3 / max(1, best["iterations"]), 3)}
+        if cpu:
+            H = OA.hierarchy(A)
+            bh = b.cpu().numpy()
+            tc = time.perf_counter()
+            ro = OA.solve(H, bh, rtol=1e-8, maxit=200)
+            t_cpu = time.perf_counter() - tc
+            row.update(cpu_oracle_solve_s=round(t_cpu, 3), cpu_oracle_cycles=ro.iterations,
+                       speedup_vs_cpu=round(t_cpu / best["seconds"], 2))
+        log(f"[bench] amg: {row}")
+        res.append(row)
+    return {"amg": res, "note": "FP64; RS first pass, direct interpolation, damped Jacobi (omega 2/3), 3 + 3 sweeps, "
+                                "at most 8 levels, coarsest <= 64 rows solved with its inverse"}
 
 
 def main():
@@ -497,6 +550,8 @@ def extra(args):
         out.update({"n": A.n, "nnz": A.nnz, "iluk": rows})
     elif args.workload == "formats":
         out.update(formats_table())
+    elif args.workload == "amg":
+        out.update(amg_table())
     elif args.workload == "copy":
         nbytes = 1 << 30
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)

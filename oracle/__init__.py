@@ -18,6 +18,8 @@ Functions, each following the passage cited in ``oracle.c``:
 * :func:`ras_blocks`, :func:`ras_factor`, :func:`ras_apply` -- Sec. 2.5 restricted
   additive Schwarz (sequence partition, overlap layers, per-block ILU(k), restricted
   solve), written out block by block from the definition
+* :func:`hyb_width`, :func:`hyb_from_csr` -- Sec. 2.1 HYB layout (ELL + COO)
+* ``oracle.amg`` -- Sec. 2.8, Alg. 5: Ruge-Stueben setup and the V-cycle (plain numpy)
 """
 from __future__ import annotations
 
