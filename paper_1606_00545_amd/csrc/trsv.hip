@@ -409,7 +409,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     for (int u = 0; u < B; ++u) pend |= xs[u] == SENT;
                 }
             };
-            auto put = [&](char *sl, uint32_t so, int s0, const int (&es)[B], const T (&vs)[B], const U (&xs)[B]) {
+            // entries and dependency addresses (known before any poll completes)
+            auto put = [&](char *sl, uint32_t so, int s0, const int (&es)[B], const T (&vs)[B]) {
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
                     const int s = s0 + u;
@@ -419,8 +420,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     else if (es[u] != kPad) at = sx_off + (uint32_t)(((-1 - es[u]) & (W - 1)) * sizeof(T));
                     ((uint32_t *)(sl + L.a()))[s * kSub + lane] = at;
                     ((T *)(sl + L.v()))[s * kSub + lane] = vs[u];
-                    ((T *)(sl + L.xe()))[s * kSub + lane] = from_bits<T>(xs[u]);
                 }
+            };
+            // the polled values of dependencies outside the part (other entries never read theirs)
+            auto put_xe = [&](char *sl, int s0, const int (&es)[B], const U (&xs)[B]) {
+#pragma unroll
+                for (int u = 0; u < B; ++u)
+                    if (es[u] >= 0) ((T *)(sl + L.xe()))[(s0 + u) * kSub + lane] = from_bits<T>(xs[u]);
             };
             auto process = [&](int rel, Pre &cur, Pre &nxt) {
                 const int slot = rel % D;
@@ -433,13 +439,18 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
 #pragma unroll
                 for (int u = 0; u < B; ++u) xs[u] = first_poll(xq, cur.es[u]);
                 if (kPfPipe && rel + NP < nss) issue(rel + NP, nxt);
-                poll(cur.es, xs);
-                // the slot's previous sub-segment, rel - D, must be solved
+                // the slot's previous sub-segment, rel - D, must be solved; everything but the
+                // outside values goes in before the polls, so that only those and the flag
+                // follow the last poll
                 const int prev = rel - D;
                 if (prev >= 0)
                     while (__hip_atomic_load(&done[prev & (NS - 1)], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= prev)
                         __builtin_amdgcn_s_sleep(4);
-                put(sl, so, 0, cur.es, cur.vs, xs);
+                put(sl, so, 0, cur.es, cur.vs);
+                ((T *)(sl + L.b()))[lane] = bb;
+                if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = cur.dd;
+                poll(cur.es, xs);
+                put_xe(sl, 0, cur.es, xs);
                 for (int s0 = B; s0 < KC; s0 += B) {  // rows longer than one batch
                     int es[B];
                     T vs[B];
@@ -455,11 +466,10 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                     U xs2[B];
 #pragma unroll
                     for (int u = 0; u < B; ++u) xs2[u] = first_poll(xq, es[u]);
+                    put(sl, so, s0, es, vs);
                     poll(es, xs2);
-                    put(sl, so, s0, es, vs, xs2);
+                    put_xe(sl, s0, es, xs2);
                 }
-                ((T *)(sl + L.b()))[lane] = bb;
-                if constexpr (UPPER) ((T *)(sl + L.d()))[lane] = cur.dd;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (lane == 0) __hip_atomic_store(&filled[slot], rel, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             };
