@@ -283,6 +283,8 @@ typedef struct {
     int32_t coarse_size; /* a level of at most this many rows is the coarsest; 1..4096 (64) */
     double omega;        /* damped Jacobi weight; in (0, 2) (2/3) */
     int32_t nu1, nu2;    /* pre- and post-smoothing sweeps; 0..64 (3 and 3, as Sec. 3.3) */
+    int32_t use_graph;   /* 1: record one cycle into a HIP graph at the first solve and replay it;
+                            0: launch the kernels of every cycle (1) */
 } hec_amg_opts;
 
 /* Sec. 2.8: AMG setup on the host for the n x n CSR matrix (Ap, Aj, Ax: host
@@ -315,7 +317,8 @@ hec_status amg_export_level(hec_amg H, int32_t level, int8_t *cf, int32_t *Ap, i
  * coarsest level solved with its inverse) until ||b - A x|| <= rtol ||b|| in FP64
  * or maxit cycles. b, x: device FP64 vectors of n elements, not overlapping. The
  * calls of one handle must not overlap in time (its per-level vectors are
- * shared). Returns NOT_CONVERGED after maxit cycles (x holds the last iterate),
+ * shared). The handle runs the cycles on a stream of its own, ordered after the
+ * caller's stream on entry and before it on return. Returns NOT_CONVERGED after maxit cycles (x holds the last iterate),
  * BREAKDOWN on a non-finite residual; info (may be NULL) gets the cycles and the
  * final relative residual. */
 hec_status amg_solve(hec_amg H, const double *b, double *x, int32_t maxit, double rtol, void *stream,

@@ -24,6 +24,12 @@
 // Solve: x = 0, then V-cycles (Alg. 5) until ||b - A x|| <= rtol ||b||: nu1
 // damped Jacobi sweeps x += omega D^{-1} (b - A x), the residual restricted with
 // R, the coarse correction (from zero) prolongated with P and added, nu2 sweeps.
+// A level whose rows are of about the same length (plain ELL wastes at most 30%
+// of its slab) is stored as plain ELL, so that one launch does a whole sweep
+// (the residual and the update, into a second vector); other levels keep the
+// HEC layout and sweep with an SpMV for the residual and an update. One cycle
+// with its residual norm is captured once into a HIP graph on the handle's own
+// stream and replayed.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -277,6 +283,24 @@ __global__ __launch_bounds__(256) void k_jacobi_update(int32_t n, double omega, 
     if (i < n) x[i] += omega * dinv[i] * r[i];
 }
 
+// One damped Jacobi sweep on an ELL matrix (slab entry s of row i at s*ld + i):
+// xo = xi + omega * dinv * (b - A xi).
+__global__ __launch_bounds__(256) void k_jacobi_ell(int32_t n, int32_t K, int32_t ld, const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, const double *__restrict__ dinv,
+                                                    double omega, const double *__restrict__ xi,
+                                                    const double *__restrict__ b, double *__restrict__ xo) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int32_t s = 0; s < K; ++s) acc += val[(size_t)s * ld + i] * xi[col[(size_t)s * ld + i]];
+    xo[i] = xi[i] + omega * dinv[i] * (b[i] - acc);
+}
+
+__global__ __launch_bounds__(256) void k_copy(int32_t n, const double *__restrict__ a, double *__restrict__ b) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 __global__ __launch_bounds__(256) void k_zero(int32_t n, double *__restrict__ x) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0.0;
@@ -317,8 +341,10 @@ using namespace hec;
 struct hec_amg_level {
     amgs::Csr A, P;                      // host copies (A_l, and P_l for l < L)
     std::vector<int8_t> cf;              // C/F splitting of this level (l < L)
-    std::unique_ptr<hec_matrix_s> dA, dP, dR;
-    DevBuf<double> dinv, x, b, r;
+    std::unique_ptr<hec_matrix_s> dA;    // plain ELL when `fused`, else HEC
+    bool fused = false;
+    std::unique_ptr<hec_matrix_s> dP, dR;
+    DevBuf<double> dinv, x, y, b, r;     // x, y: the iterate and the other buffer of a sweep
 };
 
 struct hec_amg_s {
@@ -326,12 +352,27 @@ struct hec_amg_s {
     std::vector<std::unique_ptr<hec_amg_level>> lev;
     std::unique_ptr<hec_matrix_s> coarse_inv;  // dense inverse of the coarsest level
     DevBuf<double> part, nrm;
+    hipStream_t hs = nullptr;                  // the handle's stream (the cycle graph replays on it)
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~hec_amg_s() {
+        if (hs) (void)hipStreamSynchronize(hs);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        lev.clear();
+        coarse_inv.reset();
+        part.release();
+        nrm.release();
+        if (ev) (void)hipEventDestroy(ev);
+        if (hs) (void)hipStreamDestroy(hs);
+    }
 };
 
 namespace {
 
-std::unique_ptr<hec_matrix_s> upload(const amgs::Csr &M, hipStream_t s) {
-    return make_hec(M.n, M.m, M.p.data(), M.j.data(), M.x.data(), -1, 0, s);
+std::unique_ptr<hec_matrix_s> upload(const amgs::Csr &M, int32_t width, hipStream_t s) {
+    return make_hec(M.n, M.m, M.p.data(), M.j.data(), M.x.data(), width, 0, s);
 }
 
 // y = alpha * M x + beta * z
@@ -340,45 +381,74 @@ void spmv(const hec_matrix_s &M, double alpha, const double *x, double beta, con
     spmv_launch<double, double, double>(M, alpha, x, beta, z, y, s);
 }
 
-double norm2(hec_amg_s &H, int32_t n, const double *v, hipStream_t s) {
+void sumsq(hec_amg_s &H, int32_t n, const double *v, hipStream_t s) {
     k_sumsq<<<kNormBlocks, 256, 0, s>>>(n, v, H.part.get());
     HEC_CHECK_LAUNCH();
     k_sumsq_finish<<<1, 64, 0, s>>>(H.part.get(), H.nrm.get());
     HEC_CHECK_LAUNCH();
+}
+
+double read_norm(hec_amg_s &H, hipStream_t s) {
     double h = 0.0;
     H.nrm.download(&h, 1, s);
     HEC_HIP(hipStreamSynchronize(s));
     return std::sqrt(h);
 }
 
-void smooth(hec_amg_level &L, double omega, int sweeps, double *x, const double *b, hipStream_t s) {
-    const int32_t n = L.A.n;
+// `sweeps` damped Jacobi sweeps from *cur, alternating between the level's x and y;
+// *cur ends on the buffer that holds the result.
+void smooth(hec_amg_level &L, double omega, int sweeps, double *&cur, const double *b, hipStream_t s) {
+    const hec_matrix_s &M = *L.dA;
     for (int k = 0; k < sweeps; ++k) {
-        spmv(*L.dA, -1.0, x, 1.0, b, L.r.get(), s);  // r = b - A x
-        k_jacobi_update<<<ceil_div(n, 256), 256, 0, s>>>(n, omega, L.dinv.get(), L.r.get(), x);
+        if (!L.fused) {  // r = b - A x, then x += omega D^{-1} r in place
+            spmv(M, -1.0, cur, 1.0, b, L.r.get(), s);
+            k_jacobi_update<<<ceil_div(M.n, 256), 256, 0, s>>>(M.n, omega, L.dinv.get(), L.r.get(), cur);
+            HEC_CHECK_LAUNCH();
+            continue;
+        }
+        double *nxt = cur == L.x.get() ? L.y.get() : L.x.get();
+        k_jacobi_ell<<<ceil_div(M.n, 256), 256, 0, s>>>(M.n, M.K, M.ld, M.ell_col.get(), M.ell_val.get(),
+                                                       L.dinv.get(), omega, cur, b, nxt);
         HEC_CHECK_LAUNCH();
+        cur = nxt;
     }
 }
 
-// Alg. 5 from level l with the iterate in x and the right-hand side in b.
-void vcycle(hec_amg_s &H, size_t l, double *x, const double *b, hipStream_t s) {
+// Alg. 5 from level l (iterate in L.x, right-hand side in L.b); returns the buffer
+// holding the result.
+double *vcycle(hec_amg_s &H, size_t l, hipStream_t s) {
     hec_amg_level &L = *H.lev[l];
     if (l + 1 == H.lev.size()) {
-        spmv(*H.coarse_inv, 1.0, b, 0.0, b, x, s);  // x_L = A_L^{-1} b_L
-        return;
+        spmv(*H.coarse_inv, 1.0, L.b.get(), 0.0, L.b.get(), L.x.get(), s);  // x_L = A_L^{-1} b_L
+        return L.x.get();
     }
     const hec_amg_opts &o = H.opts;
-    smooth(L, o.omega, o.nu1, x, b, s);
-    spmv(*L.dA, -1.0, x, 1.0, b, L.r.get(), s);  // r = b - A x
+    double *cur = L.x.get();
+    smooth(L, o.omega, o.nu1, cur, L.b.get(), s);
+    spmv(*L.dA, -1.0, cur, 1.0, L.b.get(), L.r.get(), s);  // r = b - A x
     hec_amg_level &C = *H.lev[l + 1];
     spmv(*L.dR, 1.0, L.r.get(), 0.0, L.r.get(), C.b.get(), s);  // b_{l+1} = R r
     if (l + 2 < H.lev.size()) {
         k_zero<<<ceil_div(C.A.n, 256), 256, 0, s>>>(C.A.n, C.x.get());
         HEC_CHECK_LAUNCH();
     }
-    vcycle(H, l + 1, C.x.get(), C.b.get(), s);
-    spmv(*L.dP, 1.0, C.x.get(), 1.0, x, x, s);  // x += P x_{l+1}
-    smooth(L, o.omega, o.nu2, x, b, s);
+    const double *xc = vcycle(H, l + 1, s);
+    spmv(*L.dP, 1.0, xc, 1.0, cur, cur, s);  // x += P x_{l+1}
+    smooth(L, o.omega, o.nu2, cur, L.b.get(), s);
+    return cur;
+}
+
+// One cycle on level 0 ending with the iterate back in x, then ||b - A x||^2 into nrm.
+void enqueue_cycle(hec_amg_s &H, hipStream_t s) {
+    hec_amg_level &L0 = *H.lev[0];
+    const int32_t n = L0.A.n;
+    double *res = vcycle(H, 0, s);
+    if (res != L0.x.get()) {
+        k_copy<<<ceil_div(n, 256), 256, 0, s>>>(n, res, L0.x.get());
+        HEC_CHECK_LAUNCH();
+    }
+    spmv(*L0.dA, -1.0, L0.x.get(), 1.0, L0.b.get(), L0.r.get(), s);
+    sumsq(H, n, L0.r.get(), s);
 }
 
 }  // namespace
@@ -392,11 +462,11 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
         *out = nullptr;
         validate_csr(n, Ap, Aj, Ax);
         if (n == 0) fail(HEC_ERR_INVALID_ARG, "empty matrix");
-        hec_amg_opts o{0.25, 8, 64, 2.0 / 3.0, 3, 3};
+        hec_amg_opts o{0.25, 8, 64, 2.0 / 3.0, 3, 3, 1};
         if (opts) o = *opts;
         if (!(o.theta > 0.0 && o.theta <= 1.0) || o.max_levels < 1 || o.max_levels > 32 || o.coarse_size < 1 ||
             o.coarse_size > 4096 || !(o.omega > 0.0 && o.omega < 2.0) || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 64 ||
-            o.nu2 > 64)
+            o.nu2 > 64 || (o.use_graph != 0 && o.use_graph != 1))
             fail(HEC_ERR_INVALID_ARG, "bad AMG options");
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
@@ -418,10 +488,14 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
                 if (dinv[i] == 0.0 || !std::isfinite(dinv[i]))
                     fail(HEC_ERR_ZERO_PIVOT, "AMG level " + std::to_string(H->lev.size()) + ": zero or missing diagonal in row " + std::to_string(i));
             }
-            L->dA = upload(L->A, s);
+            int32_t width = 0;
+            for (int32_t i = 0; i < nl; ++i) width = std::max(width, L->A.p[i + 1] - L->A.p[i]);
+            L->fused = (double)width * nl <= 1.3 * (double)L->A.p[nl];
+            L->dA = upload(L->A, L->fused ? width : -1, s);
             L->dinv.alloc(nl);
             L->dinv.upload(dinv.data(), nl, s);
             L->x.alloc(nl);
+            L->y.alloc(nl);
             L->b.alloc(nl);
             L->r.alloc(nl);
             const bool last = nl <= o.coarse_size || (int32_t)H->lev.size() + 1 == o.max_levels;
@@ -436,8 +510,8 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
                     L->P = amgs::direct_interpolation(L->A, Sp, Sj, L->cf);
                     amgs::Csr R = amgs::transpose(L->P);
                     Ac = amgs::galerkin(L->A, L->P, R);
-                    L->dP = upload(L->P, s);
-                    L->dR = upload(R, s);
+                    L->dP = upload(L->P, -1, s);
+                    L->dR = upload(R, -1, s);
                 } else {
                     L->cf.clear();
                 }
@@ -459,6 +533,8 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
         H->part.alloc(kNormBlocks);
         H->nrm.alloc(1);
         HEC_HIP(hipStreamSynchronize(s));
+        HEC_HIP(hipStreamCreateWithFlags(&H->hs, hipStreamNonBlocking));
+        HEC_HIP(hipEventCreateWithFlags(&H->ev, hipEventDisableTiming));
         *out = H.release();
     });
 }
@@ -500,23 +576,42 @@ hec_status amg_solve(hec_amg H, const double *b, double *x, int32_t maxit, doubl
         if (b == x) fail(HEC_ERR_INVALID_ARG, "b and x must not overlap");
         if (maxit < 0 || !(rtol >= 0.0)) fail(HEC_ERR_INVALID_ARG, "bad maxit or rtol");
         const auto t0 = std::chrono::steady_clock::now();
-        hipStream_t s = as_stream(stream);
+        hipStream_t us = as_stream(stream), s = H->hs;
         StreamScope scope(s);
+        HEC_HIP(hipEventRecord(H->ev, us));  // after the caller's work on b and x
+        HEC_HIP(hipStreamWaitEvent(s, H->ev, 0));
         hec_amg_level &L0 = *H->lev[0];
         const int32_t n = L0.A.n;
-        k_zero<<<ceil_div(n, 256), 256, 0, s>>>(n, x);
+        HEC_HIP(hipMemcpyAsync(L0.b.get(), b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        k_zero<<<ceil_div(n, 256), 256, 0, s>>>(n, L0.x.get());
         HEC_CHECK_LAUNCH();
-        const double nb = norm2(*H, n, b, s);
+        sumsq(*H, n, L0.b.get(), s);
+        const double nb = read_norm(*H, s);
         int32_t it = 0;
         double res = nb > 0.0 ? 1.0 : 0.0;
         hec_status st = HEC_OK;
         if (nb > 0.0) {
             st = HEC_ERR_NOT_CONVERGED;
+            if (H->opts.use_graph && !H->exec && maxit > 0) {
+                HEC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    enqueue_cycle(*H, s);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(s, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HEC_HIP(hipStreamEndCapture(s, &H->graph));
+                HEC_HIP(hipGraphInstantiate(&H->exec, H->graph, nullptr, nullptr, 0));
+            }
             while (it < maxit) {
-                vcycle(*H, 0, x, b, s);
+                if (H->opts.use_graph)
+                    HEC_HIP(hipGraphLaunch(H->exec, s));
+                else
+                    enqueue_cycle(*H, s);
                 ++it;
-                spmv(*L0.dA, -1.0, x, 1.0, b, L0.r.get(), s);
-                res = norm2(*H, n, L0.r.get(), s) / nb;
+                res = read_norm(*H, s) / nb;
                 if (!std::isfinite(res)) {
                     st = HEC_ERR_BREAKDOWN;
                     break;
@@ -527,6 +622,10 @@ hec_status amg_solve(hec_amg H, const double *b, double *x, int32_t maxit, doubl
                 }
             }
         }
+        HEC_HIP(hipMemcpyAsync(x, L0.x.get(), (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HEC_HIP(hipEventRecord(H->ev, s));
+        HEC_HIP(hipStreamWaitEvent(us, H->ev, 0));  // the caller's later work sees x
+        HEC_HIP(hipStreamSynchronize(s));
         if (info) {
             *info = hec_solve_info{};
             info->status = st;

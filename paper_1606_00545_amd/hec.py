@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
 
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_levels", C.c_int32), ("coarse_size", C.c_int32),
-                ("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32)]
+                ("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -394,9 +394,9 @@ def gmres_solve_batched(B: Batch, systems, maxit: int = 10000, rtol: float = 1e-
 # ------------------------------------------------------------------ AMG (Sec. 2.8)
 
 def amg_setup(A, theta: float = 0.25, max_levels: int = 8, coarse_size: int = 64, omega: float = 2.0 / 3.0,
-              nu1: int = 3, nu2: int = 3, stream=None) -> Amg:
+              nu1: int = 3, nu2: int = 3, use_graph: bool = True, stream=None) -> Amg:
     n, Ap, Aj, Ax = _csr(A)
-    o = AmgOpts(theta, max_levels, coarse_size, omega, nu1, nu2)
+    o = AmgOpts(theta, max_levels, coarse_size, omega, nu1, nu2, 1 if use_graph else 0)
     out = _vp()
     _check(load().amg_setup(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, C.byref(o),
                             _stream_or_null(stream), C.byref(out)), "amg_setup")

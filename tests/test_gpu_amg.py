@@ -93,6 +93,27 @@ def test_one_cycle_matches_oracle_closely():
     assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("nu", [(3, 3), (2, 1)])
+def test_graph_replays_equal_eager_cycles(nu):
+    """The recorded cycle, replayed many times with other device work and
+    synchronisations in between, gives bit for bit what launching every cycle gives."""
+    import torch
+    A = synth.lognormal_tpfa((23, 19, 17), 2.0, np.random.default_rng(8))
+    Gg = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=True)
+    Ge = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=False)
+    for rep in range(4):
+        b = np.random.default_rng(20 + rep).uniform(-1, 1, A.n)
+        xe, xg = empty(A.n), empty(A.n)
+        ie = hec.amg_solve(Ge, dev(b), xe, maxit=3 + rep, rtol=0.0, check=False)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        junk.mul_(3.0).sum().item()
+        ig = hec.amg_solve(Gg, dev(b), xg, maxit=3 + rep, rtol=0.0, check=False)
+        torch.cuda.synchronize()
+        assert ie["iterations"] == ig["iterations"] == 3 + rep
+        assert np.array_equal(host(xe).view(np.uint64), host(xg).view(np.uint64)), rep
+        assert ie["rel_res_true"] == ig["rel_res_true"]
+
+
 def test_edge_cases():
     # a diagonal matrix: no strong connection, one level, solved exactly by its inverse
     d = np.arange(1.0, 301.0)
@@ -117,6 +138,7 @@ def test_edge_cases():
     assert inf["iterations"] == 0 and not host(x).any()
     # bad options and a zero diagonal
     for kw in ({"theta": 0.0}, {"max_levels": 0}, {"omega": 2.0}, {"nu1": -1}, {"coarse_size": 0}):
+        kw = dict(kw)
         with pytest.raises(hec.HecError) as e:
             hec.amg_setup(A, **kw)
         assert e.value.code == hec.INVALID_ARG
