@@ -134,7 +134,8 @@ struct KrylovWSDeleter {
 struct hec_matrix_s {
     int32_t n = 0, K = 0, ld = 0;
     int64_t nnz = 0, nnz_rem = 0;
-    int32_t n_rem_rows = 0;   // rows with a nonempty remainder
+    int32_t n_rem_rows = 0;   // rows with a nonempty remainder of fewer than 1024 entries
+    int32_t n_rem_long = 0;   // rows with a remainder of 1024 entries or more
     int32_t rem_lanes = 64;   // lanes per remainder row in the CSR kernel
     bool has_f32 = false;
     hec::DevBuf<int32_t> ell_col;
@@ -144,7 +145,8 @@ struct hec_matrix_s {
     hec::DevBuf<int32_t> rem_col;
     hec::DevBuf<double> rem_val;
     hec::DevBuf<float> rem_val32;
-    hec::DevBuf<int32_t> rem_rows;  // ascending rows with remainder entries (all rows when K == 0)
+    hec::DevBuf<int32_t> rem_rows;  // ascending short-remainder rows (all short rows when K == 0)
+    hec::DevBuf<int32_t> rem_long;  // ascending long-remainder rows, one workgroup each
     // COO remainder (HEC_COO_REMAINDER: the HYB layout): the row of every remainder
     // entry, multiplied entry-parallel in tiles; partial sums of the rows cut by tile
     // boundaries (2 per tile: row, then value) are finished by a second launch

@@ -160,9 +160,50 @@ __global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t K, int32_t 
     y[i] = (YT)r;
 }
 
-// CSR remainder (Alg. 1, second loop): LANES lanes per row (a sub-wavefront),
-// lanes stride the row, then a butterfly reduction inside the group.
-// first == true (no ELL part): y = alpha*t + beta*z; otherwise y += alpha*t.
+// Sum of rval[e] * x[rcol[e]] over e = e0 + t, e0 + t + step, ... < e1, in that
+// order. The loads of four consecutive terms are issued before their products
+// are added, so that a lane keeps four gathers in flight instead of one.
+template <class VT, class XT, class AT>
+__device__ __forceinline__ AT rem_strided_sum(int32_t e0, int32_t e1, int32_t t, int32_t step,
+                                              const int32_t *__restrict__ rcol,
+                                              const VT *__restrict__ rval, const XT *__restrict__ x) {
+    AT acc = 0;
+    int32_t e = e0 + t;
+    for (; e + 3 * step < e1; e += 4 * step) {
+        int32_t j0 = __builtin_nontemporal_load(rcol + e);
+        int32_t j1 = __builtin_nontemporal_load(rcol + e + step);
+        int32_t j2 = __builtin_nontemporal_load(rcol + e + 2 * step);
+        int32_t j3 = __builtin_nontemporal_load(rcol + e + 3 * step);
+        VT a0 = __builtin_nontemporal_load(rval + e);
+        VT a1 = __builtin_nontemporal_load(rval + e + step);
+        VT a2 = __builtin_nontemporal_load(rval + e + 2 * step);
+        VT a3 = __builtin_nontemporal_load(rval + e + 3 * step);
+        XT x0 = x[j0], x1 = x[j1], x2 = x[j2], x3 = x[j3];
+        acc += (AT)a0 * (AT)x0;
+        acc += (AT)a1 * (AT)x1;
+        acc += (AT)a2 * (AT)x2;
+        acc += (AT)a3 * (AT)x3;
+    }
+    for (; e < e1; e += step) acc += (AT)__builtin_nontemporal_load(rval + e) * (AT)x[__builtin_nontemporal_load(rcol + e)];
+    return acc;
+}
+
+// Finish remainder row r with its sum t. first == true (no ELL part):
+// y = alpha*t + beta*z; otherwise y += alpha*t.
+template <class YT, class AT>
+__device__ __forceinline__ void rem_finish(int32_t r, AT t, AT alpha, AT beta, const YT *z, YT *y, bool first) {
+    if (first) {
+        AT v = alpha * t;
+        if (beta != (AT)0) v += beta * (AT)z[r];
+        y[r] = (YT)v;
+    } else {
+        y[r] = (YT)((AT)y[r] + alpha * t);
+    }
+}
+
+// CSR remainder (Alg. 1, second loop), rows shorter than kLongRem: LANES lanes
+// per row (a sub-wavefront), lanes stride the row, then a butterfly reduction
+// inside the group.
 template <class VT, class XT, class YT, class AT, int LANES>
 __global__ __launch_bounds__(256) void k_spmv_rem(int32_t nrows, const int32_t *__restrict__ rows,
                                                   const int32_t *__restrict__ rptr,
@@ -176,20 +217,40 @@ __global__ __launch_bounds__(256) void k_spmv_rem(int32_t nrows, const int32_t *
     int32_t lane = threadIdx.x % LANES;
     if (grp >= nrows) return;
     int32_t r = rows[grp];
-    int32_t e0 = rptr[r], e1 = rptr[r + 1];
-    AT acc = 0;
-    for (int32_t e = e0 + lane; e < e1; e += LANES)
-        acc += (AT)__builtin_nontemporal_load(rval + e) * (AT)x[__builtin_nontemporal_load(rcol + e)];
+    AT acc = rem_strided_sum<VT, XT, AT>(rptr[r], rptr[r + 1], lane, LANES, rcol, rval, x);
 #pragma unroll
     for (int off = LANES / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LANES);
-    if (lane == 0) {
-        if (first) {
-            AT t = alpha * acc;
-            if (beta != (AT)0) t += beta * (AT)z[r];
-            y[r] = (YT)t;
-        } else {
-            y[r] = (YT)((AT)y[r] + alpha * acc);
-        }
+    if (lane == 0) rem_finish<YT, AT>(r, acc, alpha, beta, z, y, first);
+}
+
+// CSR remainder rows of kLongRem entries or more (a few very long rows, as in
+// circuit matrices): one workgroup of kLongThreads per row, so that such a row
+// does not leave a single wavefront working through it while the rest of the
+// chip idles. Threads stride the row; each wavefront reduces by butterfly, and
+// thread 0 adds the wavefronts' sums in wavefront order (deterministic).
+constexpr int32_t kLongRem = 1024;
+constexpr int kLongThreads = 1024;
+
+template <class VT, class XT, class YT, class AT>
+__global__ __launch_bounds__(kLongThreads) void k_spmv_rem_long(const int32_t *__restrict__ rows,
+                                                                const int32_t *__restrict__ rptr,
+                                                                const int32_t *__restrict__ rcol,
+                                                                const VT *__restrict__ rval, AT alpha,
+                                                                const XT *__restrict__ x, AT beta,
+                                                                const YT *z, YT *y, bool first,
+                                                                const int32_t *skip) {
+    if (skip && *skip) return;
+    __shared__ AT part[kLongThreads / 64];
+    const int32_t r = rows[blockIdx.x];
+    AT acc = rem_strided_sum<VT, XT, AT>(rptr[r], rptr[r + 1], (int32_t)threadIdx.x, kLongThreads, rcol, rval, x);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        AT t = part[0];
+        for (int w = 1; w < kLongThreads / 64; ++w) t += part[w];
+        rem_finish<YT, AT>(r, t, alpha, beta, z, y, first);
     }
 }
 
@@ -374,6 +435,11 @@ void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta
         }
         HEC_CHECK_LAUNCH();
     }
+    if (A.n_rem_long > 0) {
+        k_spmv_rem_long<VT, XT, YT, AT><<<A.n_rem_long, kLongThreads, 0, s>>>(
+            A.rem_long.get(), A.rem_ptr.get(), A.rem_col.get(), rv, alpha, x, beta, z, y, first, skip);
+        HEC_CHECK_LAUNCH();
+    }
 }
 
 template void spmv_launch<double, double, double>(const hec_matrix_s &, double, const double *, double,
@@ -426,21 +492,27 @@ std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *
     A->has_f32 = (flags & HEC_KEEP_F32) != 0;
     // remainder row pointer and row list (host prefix sum)
     std::vector<int32_t> rptr(n + 1);
-    std::vector<int32_t> rrows;
-    int64_t r = 0;
+    std::vector<int32_t> rrows, rlong;
+    int64_t r = 0, rshort = 0;
     rptr[0] = 0;
     for (int32_t i = 0; i < n; ++i) {
         int32_t len = Ap[i + 1] - Ap[i];
         int32_t extra = len > A->K ? len - A->K : 0;
-        if (A->K == 0 || extra > 0) rrows.push_back(i);
+        if (extra >= kLongRem) {
+            rlong.push_back(i);
+        } else if (A->K == 0 || extra > 0) {
+            rrows.push_back(i);
+            rshort += extra;
+        }
         r += extra;
         rptr[i + 1] = (int32_t)r;
     }
     A->nnz_rem = r;
     A->n_rem_rows = (int32_t)rrows.size();
+    A->n_rem_long = (int32_t)rlong.size();
     {
-        // lanes per remainder row: the power of two nearest the mean remainder length
-        double mean = rrows.empty() ? 0.0 : (double)r / rrows.size();
+        // lanes per short remainder row: the power of two nearest their mean length
+        double mean = rrows.empty() ? 0.0 : (double)rshort / rrows.size();
         int lanes = 2;
         while (lanes < 64 && lanes * 1.5 < mean) lanes *= 2;
         A->rem_lanes = lanes;
@@ -456,6 +528,8 @@ std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *
     A->rem_rows.alloc(rrows.size());
     A->rem_ptr.upload(rptr.data(), n + 1, s);
     A->rem_rows.upload(rrows.data(), rrows.size(), s);
+    A->rem_long.alloc(rlong.size());
+    A->rem_long.upload(rlong.data(), rlong.size(), s);
     std::vector<int32_t> rrow;
     if (flags & HEC_COO_REMAINDER) {
         A->coo = true;

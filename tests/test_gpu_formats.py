@@ -129,3 +129,31 @@ def test_hyb_beta_zero_does_not_read_y_and_rejects_bad_flags():
     out = C.c_void_p()
     rc = hec.load().hec_from_csr(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, -1, 8, None, C.byref(out))
     assert rc == hec.INVALID_ARG
+
+
+@pytest.mark.parametrize("name", ["long_rows_9000", "powerlaw_20000"])
+@pytest.mark.parametrize("width", [-1, 0, 2])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.5, -2.0)])
+def test_hec_csr_remainder_long_rows(name, width, alpha, beta):
+    """HEC's CSR remainder with rows of 1024 remainder entries or more (5000 and
+    1300 in long_rows_9000), which take one workgroup each, beside short rows,
+    empty rows and the pure-CSR case (width 0); FP64 within the bound, repeated
+    calls bit-identical, FP32 values within their bound."""
+    import torch
+    A = MATS[name]
+    rng = np.random.default_rng(17)
+    x = rng.uniform(-1, 1, A.n)
+    y0 = rng.uniform(-1, 1, A.n)
+    M = hec.hec_from_csr(A, ell_width=width, keep_f32=True)
+    outs = []
+    for _ in range(2):
+        yd = dev(y0)
+        hec.hec_spmv(M, dev(x), yd, alpha, beta)
+        outs.append(host(yd))
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    _check(A, outs[0], x, alpha, beta, y0, U64)
+    y32 = empty(A.n, "f32")
+    hec.hec_spmv(M, dev(x, torch.float32), y32, vals=hec.F32)
+    ref = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, x)
+    K = int(np.diff(A.Ap).max())
+    assert (np.abs(host(y32).astype(np.float64) - ref) <= abs_product(A, x) * ((K + 4) * U32) * 1.01).all()
