@@ -27,6 +27,13 @@ namespace {
 
 constexpr int RB = 256;          // threads per reduction workgroup
 constexpr int kMaxRedBlocks = 1024;
+// Basis vectors are 64-element aligned plus this offset (8.5 KiB in FP64), so that
+// the vectors a Gram-Schmidt pass reads together do not start at addresses that
+// are equal modulo a large power of two (n = 2^21 rows otherwise puts every vector
+// 16 MiB apart); measured 2-4% faster passes at 128^3.
+#ifndef HEC_BASIS_PAD
+#define HEC_BASIS_PAD 1088
+#endif
 constexpr int kMaxRestart = 32;  // the orthogonalisation keeps up to 32 basis coefficients in registers
 
 inline int red_blocks(int64_t n) {
@@ -180,209 +187,272 @@ struct OpCycleStart : NoInit {
     }
 };
 
-// Givens step of column j (one thread): H(:, j) = h1 + h2, h_{j+1,j} = hn, the
-// earlier rotations applied to the column, a new rotation zeroing h_{j+1,j},
-// g updated, and the convergence test |g_{j+1}| <= tol (or hn == 0).
-__device__ void givens_finish(int j, double hn, double *sd, int32_t *si, int32_t *hf, const GLayout &L) {
-    for (int k = 0; k <= j; ++k) sd[L.Hij(k, j)] = sd[L.h1 + k] + sd[L.h2 + k];
-    sd[SD_HNEXT] = hn;
-    for (int k = 0; k < j; ++k) {
-        double a = sd[L.Hij(k, j)], c = sd[L.Hij(k + 1, j)];
-        double cs = sd[L.cs + k], sn = sd[L.sn + k];
-        sd[L.Hij(k, j)] = cs * a + sn * c;
-        sd[L.Hij(k + 1, j)] = -sn * a + cs * c;
+// Givens step of column j by a workgroup: H(:, j) = h1 + h2, h_{j+1,j} = hn, the
+// earlier rotations applied to the column, a new rotation zeroing h_{j+1,j}, g
+// updated, and the convergence test |g_{j+1}| <= tol (or hn == 0). The column and
+// the rotations are read in parallel into LDS; one thread applies the rotations.
+__device__ void givens_block(int j, double hn, double *sd, int32_t *si, int32_t *hf, const GLayout &L) {
+    __shared__ double col[kMaxRestart + 1];
+    __shared__ double rcs[kMaxRestart], rsn[kMaxRestart];
+    const int t = threadIdx.x;
+    if (t <= j) col[t] = sd[L.h1 + t] + sd[L.h2 + t];
+    if (t < j) {
+        rcs[t] = sd[L.cs + t];
+        rsn[t] = sd[L.sn + t];
     }
-    double a = sd[L.Hij(j, j)], c = hn;
-    double rr = hypot(a, c);
-    double cs = 1.0, sn = 0.0;
-    if (c != 0.0) {
-        cs = a / rr;
-        sn = c / rr;
+    __syncthreads();
+    if (t == 0) {
+        sd[SD_HNEXT] = hn;
+        double a = col[0];  // entry k of the column, rotated by rotations 0..k-1
+        for (int k = 0; k < j; ++k) {
+            const double c = col[k + 1], cs = rcs[k], sn = rsn[k];
+            col[k] = cs * a + sn * c;
+            a = -sn * a + cs * c;
+        }
+        const double c = hn;
+        const double rr = hypot(a, c);
+        double cs = 1.0, sn = 0.0;
+        if (c != 0.0) {
+            cs = a / rr;
+            sn = c / rr;
+        }
+        sd[L.cs + j] = cs;
+        sd[L.sn + j] = sn;
+        col[j] = cs * a + sn * c;
+        const double gj = sd[L.g + j];
+        sd[L.g + j + 1] = -sn * gj;
+        sd[L.g + j] = cs * gj;
+        const double res = fabs(sd[L.g + j + 1]);
+        sd[SD_RES] = res;
+        si[SI_JDONE] = j + 1;
+        mirror(hf, SI_JDONE, j + 1);
+        if (!(res > sd[SD_TOL]) || hn == 0.0 || !isfinite(res)) {
+            si[SI_DONE] = 1;
+            mirror(hf, SI_DONE, 1);
+        }
     }
-    sd[L.cs + j] = cs;
-    sd[L.sn + j] = sn;
-    sd[L.Hij(j, j)] = cs * a + sn * c;
-    double gj = sd[L.g + j];
-    sd[L.g + j + 1] = -sn * gj;
-    sd[L.g + j] = cs * gj;
-    double res = fabs(sd[L.g + j + 1]);
-    sd[SD_RES] = res;
-    si[SI_JDONE] = j + 1;
-    mirror(hf, SI_JDONE, j + 1);
-    if (!(res > sd[SD_TOL]) || hn == 0.0 || !isfinite(res)) {
-        si[SI_DONE] = 1;
-        mirror(hf, SI_DONE, 1);
+    __syncthreads();
+    if (t <= j) sd[L.Hij(t, j)] = col[t];
+}
+
+// R consecutive rows of a vector at row i0 (R * sizeof(VT) = 8 bytes: one load per
+// lane), zero past n; NT: non-temporal (streaming) loads.
+template <class VT, int R, bool NT>
+__device__ __forceinline__ void load_rows(const VT *p, int64_t i0, int64_t n, VT (&o)[R]) {
+    if constexpr (R == 1) {
+        o[0] = i0 < n ? (NT ? __builtin_nontemporal_load(p + i0) : p[i0]) : (VT)0;
+    } else {
+        using VV = VT __attribute__((ext_vector_type(R)));
+        if (i0 + R <= n) {
+            const VV x = NT ? __builtin_nontemporal_load((const VV *)(p + i0)) : *(const VV *)(p + i0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) o[r] = x[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) o[r] = i0 + r < n ? p[i0 + r] : (VT)0;
+        }
     }
+}
+
+template <class VT, int R>
+__device__ __forceinline__ void store_rows(VT *p, int64_t i0, int64_t n, const VT (&o)[R]) {
+    if constexpr (R == 1) {
+        if (i0 < n) p[i0] = o[0];
+    } else {
+        using VV = VT __attribute__((ext_vector_type(R)));
+        if (i0 + R <= n) {
+            VV x;
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = o[r];
+            *(VV *)(p + i0) = x;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (i0 + r < n) p[i0 + r] = o[r];
+        }
+    }
+}
+
+// Sums of NS values over the 64 lanes of a wavefront at once: each butterfly
+// step halves the number of values a lane holds (the lanes with the step's bit
+// set keep the upper half, added to their partner's), then the lanes that share
+// an index finish with a plain butterfly. Returns the sum with index cgs_sum_index(lane); every sum is
+// added in a fixed order.
+template <int NS>
+constexpr int log2_of() {
+    return NS <= 1 ? 0 : 1 + log2_of<NS / 2>();
+}
+
+template <int NS>
+__device__ __forceinline__ double multi_wave_sum(double (&v)[NS], int lane) {
+    constexpr int LG = log2_of<NS>();
+#pragma unroll
+    for (int st = 0; st < LG; ++st) {
+        const int h = NS >> (st + 1), o = 32 >> st;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < NS / 2; ++i) {
+            if (i < h) {
+                // both halves cross, then each lane keeps the sum of its half (a
+                // select between two values, not between two array elements, so
+                // that the array stays in registers)
+                const double lo = v[i], hi = v[i + h];
+                const double rlo = __shfl_xor(lo, o), rhi = __shfl_xor(hi, o);
+                v[i] = up ? hi + rhi : lo + rlo;
+            }
+        }
+    }
+    double x = v[0];
+#pragma unroll
+    for (int st = LG; st < 6; ++st) x += __shfl_xor(x, 32 >> st);
+    return x;
+}
+
+template <int NS>
+__device__ __forceinline__ int cgs_sum_index(int lane) {
+    int idx = 0;
+#pragma unroll
+    for (int st = 0; st < log2_of<NS>(); ++st)
+        if (lane & (32 >> st)) idx += NS >> (st + 1);
+    return idx;
 }
 
 // Classical Gram-Schmidt passes over the basis V (vectors of type VT, FP64 sums):
 //   MODE 1: hout[k] = <V_k, w>                                  k < nv
 //   MODE 2: w -= V hin;  hout[k] = <V_k, w>
-//   MODE 3: w -= V hin;  ||w||^2, then the Givens step of column nv-1
-// A workgroup's 4 wavefronts take the same 64 R rows at a time, R consecutive rows
-// per lane (R = 16 bytes / element size: one 16-byte load per vector and lane);
-// wavefront q owns the vectors k = q, q+4, q+8, ... (8 sums per thread for up to
-// 32 vectors).
-// The update w -= V hin adds the 4 wavefronts' partial sums in a fixed order
-// through LDS; every sum is reduced in a fixed order (deterministic).
-template <class VT, int MODE>
+//   MODE 3: w -= V hin;  ||w||^2
+// for nv <= NB basis vectors. Every wavefront works alone (no barrier in its
+// loop) on steps of U = 32 / NB chunks of 64 R rows (R = 8 bytes / element size:
+// one 8-byte load per vector, chunk and lane), so that a pass over few vectors
+// keeps as many loads in flight per wavefront as one over many. Steps are dealt
+// to the grid's wavefronts round-robin; each keeps its sums in registers, and the
+// workgroup adds its 4 wavefronts' sums in a fixed order (deterministic). The
+// grid's per-workgroup sums go to part[k * gridDim.x + block].
+template <class VT, int MODE, int NB>
 __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V, int64_t ldv, VT *w, int nv,
                                             const double *__restrict__ hin, double *part, const int32_t *skip) {
-    constexpr int KW = kMaxRestart / 4;  // vectors per wavefront
-    constexpr int NS = kMaxRestart + 1;  // sums per workgroup: nv dots (+ the norm)
-    constexpr int R = 16 / (int)sizeof(VT);  // consecutive rows per lane: one 16-byte load per vector
-    constexpr int64_t TR = 64 * R;            // rows per tile
-    using VV = VT __attribute__((ext_vector_type(R)));
+    constexpr int R = 8 / (int)sizeof(VT);
+    constexpr int U = kMaxRestart / NB;
+    constexpr int64_t CR = 64 * R;          // rows per chunk
+    constexpr int64_t TR = CR * U;          // rows per wavefront step
+    constexpr int NS = MODE == 3 ? 1 : NB;  // sums per wavefront
     if (skip && *skip) return;
-    __shared__ double sh[kMaxRestart];
-    __shared__ double px[4][R][64];
-    __shared__ double red[NS];
+    __shared__ double sh[NB];
+    __shared__ double red[4][NS];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     if (MODE != 1 && (int)threadIdx.x < nv) sh[threadIdx.x] = hin[threadIdx.x];
     __syncthreads();
-    double acc[KW];
+    double acc[NS];
 #pragma unroll
-    for (int u = 0; u < KW; ++u) acc[u] = 0.0;
-    double nrm = 0.0;
-    const int64_t ntiles = (n + TR - 1) / TR;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t i0 = t * TR + (int64_t)lane * R;
-        const bool full = i0 + R <= n;  // V's columns and w are 16-byte aligned (ldv is a multiple of 64)
-        VT vk[KW][R];
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    // Streaming (non-temporal) loads when the basis may hold more than 16 vectors
+    // (more than the memory-side cache holds at 128^3); passes over a smaller basis
+    // read part of it from that cache in passes 2 and 3 instead (measured).
+    constexpr bool NT = NB == kMaxRestart;
+    const int64_t nsteps = (n + TR - 1) / TR;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + q; t < nsteps; t += (int64_t)gridDim.x * 4) {
+        VT vk[U][NB][R];
+        VT wv[U][R];
+        double wi[U][R];
 #pragma unroll
-        for (int u = 0; u < KW; ++u) {
-            const int k = q + 4 * u;
-            if (k < nv && full) {
-                const VV x = *(const VV *)(V + k * ldv + i0);
+        for (int u = 0; u < U; ++u) {
+            const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
+            load_rows<VT, R, NT>(w, i0, n, wv[u]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) vk[u][r] = x[r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) vk[u][r] = (k < nv && i0 + r < n) ? V[k * ldv + i0 + r] : (VT)0;
-            }
-        }
-        double wi[R];
-        if (full) {
-            const VV x = *(const VV *)(w + i0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) wi[r] = (double)x[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) wi[r] = i0 + r < n ? (double)w[i0 + r] : 0.0;
-        }
-        if constexpr (MODE != 1) {
-            double ps[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) ps[r] = 0.0;
-#pragma unroll
-            for (int u = 0; u < KW; ++u) {
-                const int k = q + 4 * u;
+            for (int k = 0; k < NB; ++k) {
                 if (k < nv) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) ps[r] += sh[k] * (double)vk[u][r];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) px[q][r][lane] = ps[r];
-            __syncthreads();
-            VV wv;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                wi[r] -= ((px[0][r][lane] + px[1][r][lane]) + px[2][r][lane]) + px[3][r][lane];
-                wv[r] = (VT)wi[r];
-                wi[r] = (double)wv[r];
-            }
-            if (q == 0) {
-                if (full) {
-                    *(VV *)(w + i0) = wv;
+                    load_rows<VT, R, NT>(V + k * ldv, i0, n, vk[u][k]);
                 } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (i0 + r < n) w[i0 + r] = wv[r];
+                    for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
                 }
             }
-            __syncthreads();
-        }
-        if constexpr (MODE == 3) {
-            if (q == 0) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) nrm += wi[r] * wi[r];
+            for (int r = 0; r < R; ++r) wi[u][r] = (double)wv[u][r];
+        }
+        if constexpr (MODE != 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double ps = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+                        if (k < nv) ps += sh[k] * (double)vk[u][k][r];
+                    wv[u][r] = (VT)(wi[u][r] - ps);  // w is stored (and used) in its own precision
+                    wi[u][r] = (double)wv[u][r];
+                }
+                store_rows<VT, R>(w, t * TR + u * CR + (int64_t)lane * R, n, wv[u]);
             }
-        } else {
-#pragma unroll
-            for (int u = 0; u < KW; ++u)
-#pragma unroll
-                for (int r = 0; r < R; ++r) acc[u] += (double)vk[u][r] * wi[r];
         }
-    }
-    // per-workgroup sums: wavefront q reduces its own vectors; the norm lives in slot kMaxRestart
 #pragma unroll
-    for (int u = 0; u < KW; ++u) {
-        const int k = q + 4 * u;
-        if (MODE != 3 && k < nv) {
-            double v = wave_sum(acc[u]);
-            if (lane == 0) red[k] = v;
-        }
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (MODE == 3) {
+                    acc[0] += wi[u][r] * wi[u][r];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) acc[k] += (double)vk[u][k][r] * wi[u][r];
+                }
+            }
     }
-    if (MODE == 3 && q == 0) {
-        double v = wave_sum(nrm);
-        if (lane == 0) red[kMaxRestart] = v;
-    }
+    const double v = multi_wave_sum<NS>(acc, lane);
+    if ((lane & (64 / NS - 1)) == 0) red[q][cgs_sum_index<NS>(lane)] = v;
     __syncthreads();
-    const int lo = MODE == 3 ? kMaxRestart : 0, hi = MODE == 3 ? kMaxRestart + 1 : nv;
-    // partial sums stored sum-major (part[k * grid + block]) so the finishing launch reads them coalesced
-    if ((int)threadIdx.x >= lo && (int)threadIdx.x < hi)
-        part[(size_t)(threadIdx.x - lo) * gridDim.x + blockIdx.x] = red[threadIdx.x];
+    const int cnt = MODE == 3 ? 1 : nv;
+    if ((int)threadIdx.x < cnt) {
+        const int k = threadIdx.x;
+        part[(size_t)k * gridDim.x + blockIdx.x] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
 }
 
-// The grid's sums of a k_cgs pass in a fixed order (one workgroup, launched right
-// after it): MODE 1/2 write the nv dot products, MODE 3 takes the Givens step.
+// The grid's sums of a k_cgs pass, added in a fixed order: workgroup k of the
+// finishing launch adds the nblocks partial sums of sum k (contiguous). MODE 1/2
+// write the nv dot products (one workgroup each); MODE 3 (one workgroup) takes the
+// Givens step of column nv-1 with the norm.
 template <int MODE>
 __global__ __launch_bounds__(RB) void k_cgs_finish(int nv, const double *part, int nblocks, double *hout,
                                                    const int32_t *skip, double *sd, int32_t *si, int32_t *hf,
                                                    GLayout L) {
-    constexpr int KW = kMaxRestart / 4;           // sums per wavefront
-    constexpr int NR = kMaxRedBlocks / 64;        // partials per lane and sum
+    constexpr int NR = kMaxRedBlocks / RB;  // partials per thread
     if (skip && *skip) return;
-    __shared__ double tot[kMaxRestart];
+    __shared__ double tot[RB / 64];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int cnt = MODE == 3 ? 1 : nv;
-    // wavefront q adds sums k = q, q+4, ...; its lanes stride over the workgroups'
-    // partials (contiguous per sum), all loads issued before the additions
-    double acc[KW];
+    const double *p = part + (size_t)blockIdx.x * nblocks;
+    double v[NR];
 #pragma unroll
-    for (int u = 0; u < KW; ++u) {
-        const int k = q + 4 * u;
-        double a = 0.0;
-        // unconditional loads from clamped (in-bounds) addresses, so that all of them
-        // are in flight together; out-of-range terms add zero
-        const int kc = k < cnt ? k : 0;
-        double v[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int b = lane + 64 * r;
-            v[r] = part[(size_t)kc * nblocks + (b < nblocks ? b : 0)];
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) a += (k < cnt && lane + 64 * r < nblocks) ? v[r] : 0.0;
-        acc[u] = a;
+    for (int r = 0; r < NR; ++r) {
+        const int b = (int)threadIdx.x + RB * r;
+        v[r] = b < nblocks ? p[b] : 0.0;
     }
+    double a = 0.0;
 #pragma unroll
-    for (int u = 0; u < KW; ++u) {
-        const int k = q + 4 * u;
-        if (k < cnt) {
-            const double v = wave_sum(acc[u]);
-            if (lane == 0) tot[k] = v;
-        }
-    }
+    for (int r = 0; r < NR; ++r) a += v[r];
+    a = wave_sum(a);
+    if (lane == 0) tot[q] = a;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if constexpr (MODE == 3) {
-            givens_finish(nv - 1, sqrt(tot[0]), sd, si, hf, L);
-        } else {
-            for (int k = 0; k < nv; ++k) hout[k] = tot[k];
-        }
+    const double sum = ((tot[0] + tot[1]) + tot[2]) + tot[3];
+    if constexpr (MODE == 3) {
+        givens_block(nv - 1, sqrt(sum), sd, si, hf, L);
+    } else {
+        if (threadIdx.x == 0) hout[blockIdx.x] = sum;
     }
+}
+
+// A Gram-Schmidt pass with the smallest vector bound NB >= nv.
+template <class VT, int MODE>
+void launch_cgs(unsigned g, int64_t n, const VT *V, int64_t ldv, VT *w, int nv, const double *hin, double *part,
+                const int32_t *skip, hipStream_t s) {
+    if (nv <= 4)
+        k_cgs<VT, MODE, 4><<<g, RB, 0, s>>>(n, V, ldv, w, nv, hin, part, skip);
+    else if (nv <= 8)
+        k_cgs<VT, MODE, 8><<<g, RB, 0, s>>>(n, V, ldv, w, nv, hin, part, skip);
+    else if (nv <= 16)
+        k_cgs<VT, MODE, 16><<<g, RB, 0, s>>>(n, V, ldv, w, nv, hin, part, skip);
+    else
+        k_cgs<VT, MODE, 32><<<g, RB, 0, s>>>(n, V, ldv, w, nv, hin, part, skip);
+    HEC_CHECK_LAUNCH();
 }
 
 // v = r / beta (start of a cycle)
@@ -746,7 +816,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     A.ws.reset();
     auto nw = std::unique_ptr<KrylovWS, KrylovWSDeleter>(new KrylovWS());
     nw->n = A.n;
-    nw->ldv = ((int64_t)A.n + 63) / 64 * 64;
+    nw->ldv = ((int64_t)A.n + 63) / 64 * 64 + HEC_BASIS_PAD;
     nw->m = mm;
     nw->mixed = mx;
     nw->bicg = bc;
@@ -830,16 +900,13 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
         const int nv = j + 1;
         const unsigned g = ws.nred;
         double *part = ws.part.get();
-        k_cgs<VT, 1><<<g, RB, 0, s>>>(n, V, ldv, w, nv, nullptr, part, done);
+        launch_cgs<VT, 1>(g, n, V, ldv, w, nv, nullptr, part, done, s);
+        k_cgs_finish<1><<<nv, RB, 0, s>>>(nv, part, g, sd + L.h1, done, sd, si, ws.dflags, L);
         HEC_CHECK_LAUNCH();
-        k_cgs_finish<1><<<1, RB, 0, s>>>(nv, part, g, sd + L.h1, done, sd, si, ws.dflags, L);
+        launch_cgs<VT, 2>(g, n, V, ldv, w, nv, sd + L.h1, part, done, s);
+        k_cgs_finish<2><<<nv, RB, 0, s>>>(nv, part, g, sd + L.h2, done, sd, si, ws.dflags, L);
         HEC_CHECK_LAUNCH();
-        k_cgs<VT, 2><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h1, part, done);
-        HEC_CHECK_LAUNCH();
-        k_cgs_finish<2><<<1, RB, 0, s>>>(nv, part, g, sd + L.h2, done, sd, si, ws.dflags, L);
-        HEC_CHECK_LAUNCH();
-        k_cgs<VT, 3><<<g, RB, 0, s>>>(n, V, ldv, w, nv, sd + L.h2, part, done);
-        HEC_CHECK_LAUNCH();
+        launch_cgs<VT, 3>(g, n, V, ldv, w, nv, sd + L.h2, part, done, s);
         k_cgs_finish<3><<<1, RB, 0, s>>>(nv, part, g, nullptr, done, sd, si, ws.dflags, L);
         HEC_CHECK_LAUNCH();
         if (j + 1 < mcyc) {
