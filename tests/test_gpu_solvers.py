@@ -170,3 +170,23 @@ def test_cg_breakdown_on_indefinite_system():
     b = np.ones(100)
     with pytest.raises(hec.HecError):
         hec.cg_solve(Mh, F, lv, dev(b), empty(100), rtol=1e-10)
+
+
+@pytest.mark.parametrize("restart", [1, 4, 5, 8, 9, 16, 17, 32])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_restart_lengths_match_oracle(restart, precision):
+    """Restart lengths at the edges of the Gram-Schmidt pass's vector bounds (4, 8,
+    16, 32 basis vectors) and the largest restart, FP64 and mixed: the FP64 residual
+    is reached, and FP64 iteration counts stay within the usual margin of the
+    oracle's (MGS) for the same restart."""
+    A, xt, b = _system("tpfa3d_24")
+    Fo = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    ro = O.gmres(A, Fo, b, restart=restart, rtol=1e-8, maxit=4000)
+    Mh, F, lv = _setup(A, 0, f32=precision == 1)
+    x = empty(A.n)
+    info = hec.gmres_solve(Mh, F, lv, dev(b), x, restart=restart, rtol=1e-8, maxit=4000, precision=precision)
+    rr = _rel_res(A, host(x), b)
+    assert info["status"] == hec.OK and rr <= 1e-8
+    if precision == 0:
+        assert abs(info["iterations"] - ro.iterations) <= max(2, ro.iterations // 10)
+    print(f"restart {restart} precision {precision}: gpu it={info['iterations']} oracle it={ro.iterations} res={rr:.2e}")
