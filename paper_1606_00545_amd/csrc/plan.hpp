@@ -37,7 +37,7 @@ constexpr int kPad = INT_MIN;     // padding entry of a row shorter than K
 #define HEC_TRSV_MAX_RING 32
 #endif
 #ifndef HEC_TRSV_SOLVERS
-#define HEC_TRSV_SOLVERS 1
+#define HEC_TRSV_SOLVERS 2
 #endif
 #ifndef HEC_TRSV_TILE
 #define HEC_TRSV_TILE 0
@@ -48,7 +48,7 @@ constexpr int kTileParts = HEC_TRSV_TILE_PARTS;      // grid tiles: at most abou
 constexpr int kMaxRing = HEC_TRSV_MAX_RING;          // most LDS slots in the ring
 constexpr int kMaxSolvers = 8;                       // solver wavefronts per workgroup: 1, 2, 4 or 8 ...
 constexpr int kSolvers = HEC_TRSV_SOLVERS;           // ... the kernels are built for (the planner's default)
-constexpr int kTile = HEC_TRSV_TILE;                 // grid tile side (0: from the solver count)
+constexpr int kTile = HEC_TRSV_TILE;                 // grid tile side (0: from the part count)
 static_assert(kSolvers == 1 || kSolvers == 2 || kSolvers == 4 || kSolvers == 8, "solver count");
 
 HEC_HD constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
@@ -237,9 +237,11 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
             const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
             const int64_t plane = (int64_t)gnx * gny;
             int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
-            // a tile's levels (x + y + z = const inside it) hold up to T*T rows: about one
-            // sub-segment per solver wavefront
-            T = kTile > 0 ? kTile : std::max<int64_t>(T, std::lround(std::sqrt((double)kSub * solvers)));
+            // the tile side comes from the part count alone: widening tiles so that a level
+            // fills every solver wavefront lengthens each tile's lead on its neighbours
+            // (measured slower at 128^3 ILU(0)); where levels are wide anyway (ILU(k > 0))
+            // the planner's solver count below takes them
+            if (kTile > 0) T = kTile;
             const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
             const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
             ntiles = PX * PY;

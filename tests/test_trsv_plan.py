@@ -402,9 +402,10 @@ def test_plan_structure_and_replay(factors, name):
                                           ("tpfa3d_41x37x23_k0", 4), ("tpfa3d_41x37x23_k1", 4),
                                           ("random_20000_k1", 4), ("poisson2d_64_k0", 4)])
 def test_multi_solver_plans(factors, name, solvers):
-    """Plans with several solver wavefronts per workgroup: tiles sized for them on a
-    3D grid, the dependency bounds and ring size checked, and the solve replayed
-    under adversarial interleavings of the solvers, bit for bit against the oracle."""
+    """Plans with several solver wavefronts per workgroup: taken on 3D grids whose tile
+    levels span several sub-segments, the dependency bounds and ring size checked, and
+    the solve replayed under adversarial interleavings of the solvers, bit for bit
+    against the oracle."""
     A, F, opt = factors(name)
     grid = _plan.detect_grid(A)
     b = np.random.default_rng(11).uniform(-1, 1, A.n)
