@@ -331,7 +331,7 @@ __device__ __forceinline__ int cgs_sum_index(int lane) {
 template <class VT, int MODE, int NB>
 __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V, int64_t ldv, VT *w, int nv,
                                             const double *__restrict__ hin, double *part, const int32_t *skip) {
-    constexpr int R = 8 / (int)sizeof(VT);
+    constexpr int R = 1;  // one element per lane and chunk (FP32 pairs held more registers than they saved)
     constexpr int U = kMaxRestart / NB;
     constexpr int64_t CR = 64 * R;          // rows per chunk
     constexpr int64_t TR = CR * U;          // rows per wavefront step
@@ -346,30 +346,54 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
     // Streaming (non-temporal) loads when the basis may hold more than 16 vectors
-    // (more than the memory-side cache holds at 128^3); passes over a smaller basis
-    // read part of it from that cache in passes 2 and 3 instead (measured).
-    constexpr bool NT = NB == kMaxRestart;
+    // (more than the memory-side cache holds at 128^3), and always for an FP32 basis;
+    // FP64 passes over a smaller basis read part of it from that cache in passes 2
+    // and 3 instead (measured).
+    constexpr bool NT = NB == kMaxRestart || sizeof(VT) == 4;
     const int64_t nsteps = (n + TR - 1) / TR;
     for (int64_t t = (int64_t)blockIdx.x * 4 + q; t < nsteps; t += (int64_t)gridDim.x * 4) {
         VT vk[U][NB][R];
         VT wv[U][R];
         double wi[U][R];
+        // a step inside the vectors (uniform over the wavefront) loads without per-lane
+        // bounds checks: one straight run of loads, so that they are all in flight
+        // before the first is used (per-lane checks become branches, and the compiler
+        // then waits for each load inside its branch)
+        if ((t + 1) * TR <= n) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
-            load_rows<VT, R, NT>(w, i0, n, wv[u]);
+            for (int u = 0; u < U; ++u) {
+                const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
+                load_rows<VT, R, NT>(w, i0, i0 + R, wv[u]);
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (k < nv) {
-                    load_rows<VT, R, NT>(V + k * ldv, i0, n, vk[u][k]);
-                } else {
+                for (int k = 0; k < NB; ++k) {
+                    if (k < nv) {
+                        load_rows<VT, R, NT>(V + k * ldv, i0, i0 + R, vk[u][k]);
+                    } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
+                        for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
+                    }
                 }
             }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
+                load_rows<VT, R, NT>(w, i0, n, wv[u]);
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (k < nv) {
+                        load_rows<VT, R, NT>(V + k * ldv, i0, n, vk[u][k]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int r = 0; r < R; ++r) wi[u][r] = (double)wv[u][r];
-        }
         if constexpr (MODE != 1) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
