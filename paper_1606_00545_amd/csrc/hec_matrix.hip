@@ -116,8 +116,11 @@ __global__ __launch_bounds__(256) void k_hec_fill_rem(int32_t n, int32_t K,
 // ELL part (Alg. 1, first loop): one thread per row, slab loads are
 // non-temporal (streamed once), x is gathered through the caches.
 // y[i] = alpha * sum_s val[s*ld+i] * x[col[s*ld+i]] + beta * z[i].
-template <class VT, class XT, class YT, class AT>
-__global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t K, int32_t ld,
+// KT > 0: the width is KT, known at compile time, so that all 2 KT slab loads and
+// then all KT gathers of a row are issued before the first is used (a run-time
+// width leaves the entries past the last group of four to load one after another).
+template <class VT, class XT, class YT, class AT, int KT = 0>
+__global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t Kd, int32_t ld,
                                                   const int32_t *__restrict__ col,
                                                   const VT *__restrict__ val, AT alpha,
                                                   const XT *__restrict__ x, AT beta,
@@ -134,6 +137,24 @@ __global__ __launch_bounds__(256) void k_spmv_ell(int32_t n, int32_t K, int32_t 
     const int32_t *c = col + i;
     const VT *v = val + i;
     AT acc = 0;
+    if constexpr (KT > 0) {
+        int32_t j[KT];
+        VT a[KT];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) j[s] = __builtin_nontemporal_load(c + (size_t)s * ld);
+#pragma unroll
+        for (int s = 0; s < KT; ++s) a[s] = __builtin_nontemporal_load(v + (size_t)s * ld);
+        XT xs[KT];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) xs[s] = x[j[s]];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) acc += (AT)a[s] * (AT)xs[s];
+        AT r = alpha * acc;
+        if (beta != (AT)0) r += beta * (AT)z[i];
+        y[i] = (YT)r;
+        return;
+    }
+    const int32_t K = Kd;
     int32_t s = 0;
     for (; s + 4 <= K; s += 4) {
         int32_t j0 = __builtin_nontemporal_load(c + (size_t)(s + 0) * ld);
@@ -372,6 +393,34 @@ __global__ __launch_bounds__(256) void k_spmv_beta(int32_t n, AT beta, const YT 
     y[i] = beta != (AT)0 ? (YT)(beta * (AT)z[i]) : (YT)0;
 }
 
+// The ELL kernel with the width fixed at compile time for widths 1..8 (stencil
+// and most HEC slabs), else the run-time width.
+template <class VT, class XT, class YT, class AT>
+static void launch_ell(const hec_matrix_s &A, const VT *ev, AT alpha, const XT *x, AT beta, const YT *z, YT *y,
+                       hipStream_t s, const int32_t *skip) {
+    const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;  // a multiple of 8 (XCD mapping)
+#define HEC_ELL_K(KK)                                                                                  \
+    case KK:                                                                                           \
+        k_spmv_ell<VT, XT, YT, AT, KK><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev, alpha, x, \
+                                                            beta, z, y, skip);                         \
+        break;
+    switch (A.K) {
+        HEC_ELL_K(1)
+        HEC_ELL_K(2)
+        HEC_ELL_K(3)
+        HEC_ELL_K(4)
+        HEC_ELL_K(5)
+        HEC_ELL_K(6)
+        HEC_ELL_K(7)
+        HEC_ELL_K(8)
+        default:
+            k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev, alpha, x, beta, z,
+                                                            y, skip);
+    }
+#undef HEC_ELL_K
+    HEC_CHECK_LAUNCH();
+}
+
 template <class VT, class XT, class YT, class AT, int LANES>
 static void launch_rem(const hec_matrix_s &A, const VT *rval, AT alpha, const XT *x, AT beta,
                        const YT *z, YT *y, bool first, hipStream_t s, const int32_t *skip) {
@@ -402,10 +451,7 @@ void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta
             k_spmv_beta<YT, AT><<<ceil_div(A.n, 256), 256, 0, s>>>(A.n, beta, z, y, skip);
             HEC_CHECK_LAUNCH();
         } else {
-            const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;
-            k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev, alpha, x, beta,
-                                                            z, y, skip);
-            HEC_CHECK_LAUNCH();
+            launch_ell<VT, XT, YT, AT>(A, ev, alpha, x, beta, z, y, s, skip);
         }
         if (A.nnz_rem > 0) {
             AT *cval = (AT *)A.carry_val.get();
@@ -418,12 +464,7 @@ void spmv_launch(const hec_matrix_s &A, double alpha_d, const XT *x, double beta
         }
         return;
     }
-    if (!first) {
-        const unsigned grid = (ceil_div(A.n, 256) + 7u) / 8u * 8u;  // a multiple of 8 (XCD mapping)
-        k_spmv_ell<VT, XT, YT, AT><<<grid, 256, 0, s>>>(A.n, A.K, A.ld, A.ell_col.get(), ev,
-                                                                     alpha, x, beta, z, y, skip);
-        HEC_CHECK_LAUNCH();
-    }
+    if (!first) launch_ell<VT, XT, YT, AT>(A, ev, alpha, x, beta, z, y, s, skip);
     if (A.n_rem_rows > 0) {
         switch (A.rem_lanes) {
             case 2: launch_rem<VT, XT, YT, AT, 2>(A, rv, alpha, x, beta, z, y, first, s, skip); break;
