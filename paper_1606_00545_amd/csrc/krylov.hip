@@ -235,42 +235,13 @@ __device__ void givens_block(int j, double hn, double *sd, int32_t *si, int32_t 
     if (t <= j) sd[L.Hij(t, j)] = col[t];
 }
 
-// R consecutive rows of a vector at row i0 (R * sizeof(VT) = 8 bytes: one load per
-// lane), zero past n; NT: non-temporal (streaming) loads.
-template <class VT, int R, bool NT>
-__device__ __forceinline__ void load_rows(const VT *p, int64_t i0, int64_t n, VT (&o)[R]) {
-    if constexpr (R == 1) {
-        o[0] = i0 < n ? (NT ? __builtin_nontemporal_load(p + i0) : p[i0]) : (VT)0;
-    } else {
-        using VV = VT __attribute__((ext_vector_type(R)));
-        if (i0 + R <= n) {
-            const VV x = NT ? __builtin_nontemporal_load((const VV *)(p + i0)) : *(const VV *)(p + i0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) o[r] = x[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) o[r] = i0 + r < n ? p[i0 + r] : (VT)0;
-        }
-    }
-}
-
-template <class VT, int R>
-__device__ __forceinline__ void store_rows(VT *p, int64_t i0, int64_t n, const VT (&o)[R]) {
-    if constexpr (R == 1) {
-        if (i0 < n) p[i0] = o[0];
-    } else {
-        using VV = VT __attribute__((ext_vector_type(R)));
-        if (i0 + R <= n) {
-            VV x;
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = o[r];
-            *(VV *)(p + i0) = x;
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (i0 + r < n) p[i0 + r] = o[r];
-        }
-    }
+// Element i of a vector; NT: a non-temporal (streaming) load.
+template <class VT, bool NT>
+__device__ __forceinline__ VT load_elem(const VT *p, int64_t i) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p + i);
+    else
+        return p[i];
 }
 
 // Sums of NS values over the 64 lanes of a wavefront at once: each butterfly
@@ -322,19 +293,17 @@ __device__ __forceinline__ int cgs_sum_index(int lane) {
 //   MODE 2: w -= V hin;  hout[k] = <V_k, w>
 //   MODE 3: w -= V hin;  ||w||^2
 // for nv <= NB basis vectors. Every wavefront works alone (no barrier in its
-// loop) on steps of U = 32 / NB chunks of 64 R rows (R = 8 bytes / element size:
-// one 8-byte load per vector, chunk and lane), so that a pass over few vectors
-// keeps as many loads in flight per wavefront as one over many. Steps are dealt
-// to the grid's wavefronts round-robin; each keeps its sums in registers, and the
-// workgroup adds its 4 wavefronts' sums in a fixed order (deterministic). The
-// grid's per-workgroup sums go to part[k * gridDim.x + block].
+// loop) on steps of U = 32 / NB chunks of 64 rows (one element per vector, chunk
+// and lane), so that a pass over few vectors keeps as many loads in flight per
+// wavefront as one over many. Steps are dealt to the grid's wavefronts
+// round-robin; each keeps its sums in registers, and the workgroup adds its 4
+// wavefronts' sums in a fixed order (deterministic). The grid's per-workgroup sums
+// go to part[k * gridDim.x + block].
 template <class VT, int MODE, int NB>
 __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V, int64_t ldv, VT *w, int nv,
                                             const double *__restrict__ hin, double *part, const int32_t *skip) {
-    constexpr int R = 1;  // one element per lane and chunk (FP32 pairs held more registers than they saved)
     constexpr int U = kMaxRestart / NB;
-    constexpr int64_t CR = 64 * R;          // rows per chunk
-    constexpr int64_t TR = CR * U;          // rows per wavefront step
+    constexpr int64_t TR = 64 * U;          // rows per wavefront step
     constexpr int NS = MODE == 3 ? 1 : NB;  // sums per wavefront
     if (skip && *skip) return;
     __shared__ double sh[NB];
@@ -352,74 +321,51 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
     constexpr bool NT = NB == kMaxRestart || sizeof(VT) == 4;
     const int64_t nsteps = (n + TR - 1) / TR;
     for (int64_t t = (int64_t)blockIdx.x * 4 + q; t < nsteps; t += (int64_t)gridDim.x * 4) {
-        VT vk[U][NB][R];
-        VT wv[U][R];
-        double wi[U][R];
-        // a step inside the vectors (uniform over the wavefront) loads without per-lane
-        // bounds checks: one straight run of loads, so that they are all in flight
-        // before the first is used (per-lane checks become branches, and the compiler
-        // then waits for each load inside its branch)
-        if ((t + 1) * TR <= n) {
+        VT vk[U][NB];
+        VT wv[U];
+        double wi[U];
+        // A step inside the vectors (uniform over the wavefront) loads without per-lane
+        // bounds checks: one straight run of loads, all in flight before the first is
+        // used (per-lane checks become branches, and the compiler then waits for each
+        // load inside its branch). Rows past n read zero.
+        const bool inside = (t + 1) * TR <= n;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
-                load_rows<VT, R, NT>(w, i0, i0 + R, wv[u]);
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = t * TR + 64 * u + lane;
+            if (inside) {
+                wv[u] = load_elem<VT, NT>(w, i);
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    if (k < nv) {
-                        load_rows<VT, R, NT>(V + k * ldv, i0, i0 + R, vk[u][k]);
-                    } else {
+                for (int k = 0; k < NB; ++k) vk[u][k] = k < nv ? load_elem<VT, NT>(V + k * ldv, i) : (VT)0;
+            } else {
+                wv[u] = i < n ? load_elem<VT, NT>(w, i) : (VT)0;
 #pragma unroll
-                        for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
-                    }
-                }
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t i0 = t * TR + u * CR + (int64_t)lane * R;
-                load_rows<VT, R, NT>(w, i0, n, wv[u]);
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    if (k < nv) {
-                        load_rows<VT, R, NT>(V + k * ldv, i0, n, vk[u][k]);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) vk[u][k][r] = (VT)0;
-                    }
-                }
+                for (int k = 0; k < NB; ++k) vk[u][k] = k < nv && i < n ? load_elem<VT, NT>(V + k * ldv, i) : (VT)0;
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < R; ++r) wi[u][r] = (double)wv[u][r];
+        for (int u = 0; u < U; ++u) wi[u] = (double)wv[u];
         if constexpr (MODE != 1) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                double ps = 0.0;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double ps = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NB; ++k)
-                        if (k < nv) ps += sh[k] * (double)vk[u][k][r];
-                    wv[u][r] = (VT)(wi[u][r] - ps);  // w is stored (and used) in its own precision
-                    wi[u][r] = (double)wv[u][r];
-                }
-                store_rows<VT, R>(w, t * TR + u * CR + (int64_t)lane * R, n, wv[u]);
+                for (int k = 0; k < NB; ++k)
+                    if (k < nv) ps += sh[k] * (double)vk[u][k];
+                wv[u] = (VT)(wi[u] - ps);  // w is stored (and used) in its own precision
+                wi[u] = (double)wv[u];
+                const int64_t i = t * TR + 64 * u + lane;
+                if (i < n) w[i] = wv[u];
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            if constexpr (MODE == 3) {
+                acc[0] += wi[u] * wi[u];
+            } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if constexpr (MODE == 3) {
-                    acc[0] += wi[u][r] * wi[u][r];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NB; ++k) acc[k] += (double)vk[u][k][r] * wi[u][r];
-                }
+                for (int k = 0; k < NB; ++k) acc[k] += (double)vk[u][k] * wi[u];
             }
+        }
     }
     const double v = multi_wave_sum<NS>(acc, lane);
     if ((lane & (64 / NS - 1)) == 0) red[q][cgs_sum_index<NS>(lane)] = v;

@@ -134,3 +134,24 @@ def test_spmv_deterministic():
         hec.hec_spmv(M, x, y)
         ys.append(host(y))
     assert all(np.array_equal(ys[0].view(np.uint64), y.view(np.uint64)) for y in ys)
+
+
+@pytest.mark.parametrize("width", list(range(1, 10)))
+def test_spmv_every_slab_width(width):
+    """Every ELL width the product fixes at compile time (1-8) and the run-time width
+    (9), each with a CSR remainder behind it, in FP64 and with FP32 values and vectors."""
+    import torch
+    A = MATS["powerlaw_3000"]
+    rng = np.random.default_rng(40 + width)
+    x = rng.uniform(-1, 1, A.n)
+    y0 = rng.uniform(-1, 1, A.n)
+    M = hec.hec_from_csr(A, ell_width=width, keep_f32=True)
+    assert hec.hec_info(M)["K"] == width
+    yd = dev(y0)
+    hec.hec_spmv(M, dev(x), yd, 0.5, -2.0)
+    _check_spmv(A, host(yd), x, 0.5, -2.0, y0, 1e-12, U64)
+    y32 = empty(A.n, "f32")
+    hec.hec_spmv(M, dev(x, torch.float32), y32, vals=hec.F32)
+    ref = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, x)
+    K = int(np.diff(A.Ap).max())
+    assert (np.abs(host(y32).astype(np.float64) - ref) <= abs_product(A, x) * ((K + 4) * U32) * 1.01).all()
