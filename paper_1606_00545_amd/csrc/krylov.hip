@@ -443,14 +443,24 @@ __global__ __launch_bounds__(256) void k_scale_next(int64_t n, const VT *w, VT *
     v[i] = (VT)((double)w[i] / sd[SD_HNEXT]);
 }
 
-// H y = g back substitution on the jdone x jdone upper triangle (one thread).
-__global__ void k_backsolve(double *sd, const int32_t *si, GLayout L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int jd = si[SI_JDONE];
-    for (int i = jd - 1; i >= 0; --i) {
-        double t = sd[L.g + i];
-        for (int q = i + 1; q < jd; ++q) t -= sd[L.Hij(i, q)] * sd[L.y + q];
-        sd[L.y + i] = t / sd[L.Hij(i, i)];
+// H y = g back substitution on the jdone x jdone upper triangle.
+// One wavefront, column by column: lane t holds row t of the triangle (loaded
+// once, in parallel) and g_t; y_i = g_i / H_ii is broadcast and every lane t < i
+// subtracts H_ti y_i (g_i ends as g_i - sum over q > i of H_iq y_q, q descending).
+__global__ __launch_bounds__(64) void k_backsolve(double *sd, const int32_t *si, GLayout L) {
+    const int t = threadIdx.x;
+    const int jd = si[SI_JDONE];
+    double h[kMaxRestart];
+#pragma unroll
+    for (int q = 0; q < kMaxRestart; ++q) h[q] = (t < jd && q < jd && q >= t) ? sd[L.Hij(t, q)] : 0.0;
+    double g = t < jd ? sd[L.g + t] : 0.0;
+#pragma unroll
+    for (int i = kMaxRestart - 1; i >= 0; --i) {
+        if (i < jd) {
+            const double yi = __shfl(g, i) / __shfl(h[i], i);
+            if (t == i) sd[L.y + i] = yi;
+            g -= h[i] * yi;  // rows t < i; h[i] is zero below the diagonal
+        }
     }
 }
 
