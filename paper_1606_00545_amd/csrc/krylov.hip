@@ -306,11 +306,8 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
     constexpr int64_t TR = 64 * U;          // rows per wavefront step
     constexpr int NS = MODE == 3 ? 1 : NB;  // sums per wavefront
     if (skip && *skip) return;
-    __shared__ double sh[NB];
     __shared__ double red[4][NS];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    if (MODE != 1 && (int)threadIdx.x < nv) sh[threadIdx.x] = hin[threadIdx.x];
-    __syncthreads();
     double acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
@@ -350,7 +347,7 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
                 double ps = 0.0;
 #pragma unroll
                 for (int k = 0; k < NB; ++k)
-                    if (k < nv) ps += sh[k] * (double)vk[u][k];
+                    if (k < nv) ps += hin[k] * (double)vk[u][k];  // uniform: scalar loads
                 wv[u] = (VT)(wi[u] - ps);  // w is stored (and used) in its own precision
                 wi[u] = (double)wv[u];
                 const int64_t i = t * TR + 64 * u + lane;
