@@ -296,6 +296,13 @@ __global__ __launch_bounds__(256) void k_jacobi_ell(int32_t n, int32_t K, int32_
     xo[i] = xi[i] + omega * dinv[i] * (b[i] - acc);
 }
 
+// The first damped Jacobi sweep from x = 0: x = omega * dinv * b (the residual is b).
+__global__ __launch_bounds__(256) void k_jacobi_first(int32_t n, double omega, const double *__restrict__ dinv,
+                                                      const double *__restrict__ b, double *__restrict__ x) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = omega * dinv[i] * b[i];
+}
+
 __global__ __launch_bounds__(256) void k_copy(int32_t n, const double *__restrict__ a, double *__restrict__ b) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -396,10 +403,18 @@ double read_norm(hec_amg_s &H, hipStream_t s) {
 }
 
 // `sweeps` damped Jacobi sweeps from *cur, alternating between the level's x and y;
-// *cur ends on the buffer that holds the result.
-void smooth(hec_amg_level &L, double omega, int sweeps, double *&cur, const double *b, hipStream_t s) {
+// *cur ends on the buffer that holds the result. zero_start: the iterate is zero,
+// so the first sweep is x = omega D^{-1} b (one elementwise launch, nothing to zero).
+void smooth(hec_amg_level &L, double omega, int sweeps, double *&cur, const double *b, hipStream_t s,
+            bool zero_start = false) {
     const hec_matrix_s &M = *L.dA;
-    for (int k = 0; k < sweeps; ++k) {
+    int k = 0;
+    if (zero_start && sweeps > 0) {
+        k_jacobi_first<<<ceil_div(M.n, 256), 256, 0, s>>>(M.n, omega, L.dinv.get(), b, cur);
+        HEC_CHECK_LAUNCH();
+        k = 1;
+    }
+    for (; k < sweeps; ++k) {
         if (!L.fused) {  // r = b - A x, then x += omega D^{-1} r in place
             spmv(M, -1.0, cur, 1.0, b, L.r.get(), s);
             k_jacobi_update<<<ceil_div(M.n, 256), 256, 0, s>>>(M.n, omega, L.dinv.get(), L.r.get(), cur);
@@ -424,11 +439,11 @@ double *vcycle(hec_amg_s &H, size_t l, hipStream_t s) {
     }
     const hec_amg_opts &o = H.opts;
     double *cur = L.x.get();
-    smooth(L, o.omega, o.nu1, cur, L.b.get(), s);
+    smooth(L, o.omega, o.nu1, cur, L.b.get(), s, l > 0);  // below level 0 the iterate starts at zero
     spmv(*L.dA, -1.0, cur, 1.0, L.b.get(), L.r.get(), s);  // r = b - A x
     hec_amg_level &C = *H.lev[l + 1];
     spmv(*L.dR, 1.0, L.r.get(), 0.0, L.r.get(), C.b.get(), s);  // b_{l+1} = R r
-    if (l + 2 < H.lev.size()) {
+    if (l + 2 < H.lev.size() && o.nu1 == 0) {  // no pre-smoothing to start from zero with
         k_zero<<<ceil_div(C.A.n, 256), 256, 0, s>>>(C.A.n, C.x.get());
         HEC_CHECK_LAUNCH();
     }
