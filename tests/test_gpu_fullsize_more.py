@@ -4,7 +4,8 @@
   conversion bit-exact against the oracle at ELL widths 8/12/16/24 and plain CSR,
   SpMV in FP64 (1e-12) and FP32 (error bound) against the oracle's CSR product;
 * anisotropic 3D diffusion 192^3 (n = 7,077,888) with ILU(1): factor pattern
-  bit-exact, preconditioner solve within 1e-12 of the oracle, and the FP64 and
+  bit-exact, preconditioner solve within 1e-12 of the oracle (1e-4 from the FP32
+  factor copy; these plans take two solver wavefronts per part), and the FP64 and
   mixed-precision GMRES solutions checked by their FP64 true residual (1e-10)
   computed with the oracle's SpMV.
 """
@@ -82,6 +83,12 @@ def test_aniso_ilu1_factor_and_trsv(aniso):
     hec.trsv_levels(F, lv, dev(r), x, hec.LU)
     x = host(x)
     assert np.linalg.norm(x - x_o) <= 1e-12 * np.linalg.norm(x_o)
+    # the same pair from the FP32 factor copy (its plans run two solver wavefronts per part)
+    import torch
+    x32 = empty(A.n, "f32")
+    hec.trsv_levels(F, lv, dev(r, torch.float32), x32, hec.LU)
+    rel = np.linalg.norm(host(x32).astype(np.float64) - x_o) / np.linalg.norm(x_o)
+    assert rel < 1e-4, rel
 
 
 @pytest.mark.parametrize("precision", [0, 1])
