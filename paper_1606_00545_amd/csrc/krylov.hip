@@ -374,19 +374,12 @@ __global__ __launch_bounds__(RB) void k_cgs(int64_t n, const VT *__restrict__ V,
     }
 }
 
-// The grid's sums of a k_cgs pass, added in a fixed order: workgroup k of the
-// finishing launch adds the nblocks partial sums of sum k (contiguous). MODE 1/2
-// write the nv dot products (one workgroup each); MODE 3 (one workgroup) takes the
-// Givens step of column nv-1 with the norm.
-template <int MODE>
-__global__ __launch_bounds__(RB) void k_cgs_finish(int nv, const double *part, int nblocks, double *hout,
-                                                   const int32_t *skip, double *sd, int32_t *si, int32_t *hf,
-                                                   GLayout L) {
+// The nblocks partial sums p[0..nblocks), added in a fixed order by one workgroup;
+// every thread gets the total.
+__device__ __forceinline__ double block_sum_fixed(const double *p, int nblocks) {
     constexpr int NR = kMaxRedBlocks / RB;  // partials per thread
-    if (skip && *skip) return;
     __shared__ double tot[RB / 64];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const double *p = part + (size_t)blockIdx.x * nblocks;
     double v[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -399,12 +392,32 @@ __global__ __launch_bounds__(RB) void k_cgs_finish(int nv, const double *part, i
     a = wave_sum(a);
     if (lane == 0) tot[q] = a;
     __syncthreads();
-    const double sum = ((tot[0] + tot[1]) + tot[2]) + tot[3];
-    if constexpr (MODE == 3) {
-        givens_block(nv - 1, sqrt(sum), sd, si, hf, L);
-    } else {
-        if (threadIdx.x == 0) hout[blockIdx.x] = sum;
-    }
+    return ((tot[0] + tot[1]) + tot[2]) + tot[3];
+}
+
+// The grid's sums of a k_cgs pass 1 or 2: workgroup k of the finishing launch adds
+// the nblocks partial sums of dot product k (contiguous) in a fixed order.
+__global__ __launch_bounds__(RB) void k_cgs_finish(const double *part, int nblocks, double *hout,
+                                                   const int32_t *skip) {
+    if (skip && *skip) return;
+    const double sum = block_sum_fixed(part + (size_t)blockIdx.x * nblocks, nblocks);
+    if (threadIdx.x == 0) hout[blockIdx.x] = sum;
+}
+
+// After pass 3: every workgroup adds the norm's partial sums in the same fixed order
+// (so all hold the same h_{j+1,j}); workgroup 0 takes the Givens step of column nv-1;
+// then, when vnext is given, v_{j+1} = w / h_{j+1,j} (a grid-stride loop). One launch
+// instead of a one-workgroup finish followed by the scaling launch.
+template <class VT>
+__global__ __launch_bounds__(RB) void k_finish_scale(int64_t n, const VT *__restrict__ w, VT *__restrict__ vnext,
+                                                     const double *part, int nblocks, int nv, const int32_t *skip,
+                                                     double *sd, int32_t *si, int32_t *hf, GLayout L) {
+    if (skip && *skip) return;
+    const double hn = sqrt(block_sum_fixed(part, nblocks));
+    if (blockIdx.x == 0) givens_block(nv - 1, hn, sd, si, hf, L);
+    if (!vnext) return;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
+        vnext[i] = (VT)((double)w[i] / hn);
 }
 
 // A Gram-Schmidt pass with the smallest vector bound NB >= nv.
@@ -430,15 +443,6 @@ __global__ __launch_bounds__(256) void k_scale_start(int64_t n, const RT *r, VT 
     v[i] = (VT)((double)r[i] / sd[SD_BETA]);
 }
 
-// v_{j+1} = w / h_{j+1,j}
-template <class VT>
-__global__ __launch_bounds__(256) void k_scale_next(int64_t n, const VT *w, VT *v, const double *sd,
-                                                    const int32_t *skip) {
-    if (*skip) return;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    v[i] = (VT)((double)w[i] / sd[SD_HNEXT]);
-}
 
 // H y = g back substitution on the jdone x jdone upper triangle.
 // One wavefront, column by column: lane t holds row t of the triangle (loaded
@@ -878,16 +882,16 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
         const unsigned g = ws.nred;
         double *part = ws.part.get();
         launch_cgs<VT, 1>(g, n, V, ldv, w, nv, nullptr, part, done, s);
-        k_cgs_finish<1><<<nv, RB, 0, s>>>(nv, part, g, sd + L.h1, done, sd, si, ws.dflags, L);
+        k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h1, done);
         HEC_CHECK_LAUNCH();
         launch_cgs<VT, 2>(g, n, V, ldv, w, nv, sd + L.h1, part, done, s);
-        k_cgs_finish<2><<<nv, RB, 0, s>>>(nv, part, g, sd + L.h2, done, sd, si, ws.dflags, L);
+        k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h2, done);
         HEC_CHECK_LAUNCH();
         launch_cgs<VT, 3>(g, n, V, ldv, w, nv, sd + L.h2, part, done, s);
-        k_cgs_finish<3><<<1, RB, 0, s>>>(nv, part, g, nullptr, done, sd, si, ws.dflags, L);
-        HEC_CHECK_LAUNCH();
-        if (j + 1 < mcyc) {
-            k_scale_next<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, w, V + (j + 1) * ldv, sd, done);
+        {
+            VT *vnext = j + 1 < mcyc ? V + (j + 1) * ldv : nullptr;  // the cycle's last step scales nothing
+            const unsigned gs = vnext ? (unsigned)std::min<int64_t>(ceil_div(n, (int64_t)RB * 8), kMaxRedBlocks) : 1u;
+            k_finish_scale<VT><<<gs, RB, 0, s>>>(n, w, vnext, part, g, nv, done, sd, si, ws.dflags, L);
             HEC_CHECK_LAUNCH();
         }
         HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
