@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes moved by one preconditioner solve (lower + upper k_trsv_blk) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
-TRSV_PAIR_TRAFFIC = int((157.8 + 48.5 + 166.4 + 59.3) * 1e6)
+TRSV_PAIR_TRAFFIC = int((157.8 + 48.5 + 165.4 + 59.3) * 1e6)
 
 
 def parse():
