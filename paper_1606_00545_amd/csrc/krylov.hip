@@ -50,6 +50,7 @@ enum : int {
     SD_BNORM = 0, SD_TOL = 1, SD_BETA = 2, SD_HNEXT = 3, SD_RES = 4,  // GMRES
     SD_RHO = 5, SD_RHO_PREV = 6, SD_ALPHA = 7, SD_OMEGA = 8,       // BiCGSTAB
     SD_SNORM2 = 9, SD_RNORM2 = 10, SD_CGBETA = 11,                 // CG: beta
+    SD_TRUE = 12,                                                  // GMRES: true residual norm after a cycle
     SD_SCALARS = 16
 };
 
@@ -778,10 +779,12 @@ struct KrylovWS {
     DevBuf<double> part;         // partial sums, nred x kMaxRestart
     int32_t *hflags = nullptr;   // mapped pinned mirror of si
     int32_t *dflags = nullptr;   // its device address
+    double *hsd = nullptr;       // pinned host copy of the scalars (one read per GMRES cycle)
     std::vector<hipEvent_t> ev;
     ~KrylovWS() {
         for (auto e : ev) (void)hipEventDestroy(e);
         if (hflags) give_flags(hflags);
+        if (hsd) (void)hipHostFree(hsd);
     }
 };
 
@@ -821,6 +824,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     nw->part.alloc((size_t)nw->nred * (kMaxRestart + 1));
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
     nw->hflags = take_flags();
+    HEC_HIP(hipHostMalloc((void **)&nw->hsd, SD_SCALARS * sizeof(double), hipHostMallocDefault));
     std::memset(nw->hflags, 0, SI_COUNT * sizeof(int32_t));
     HEC_HIP(hipHostGetDevicePointer((void **)&nw->dflags, nw->hflags, 0));
     nw->ev.resize(kMaxRestart + 2);
@@ -845,7 +849,7 @@ static inline volatile int32_t *hf(KrylovWS &ws) { return (volatile int32_t *)ws
 // sd[SD_TOL] the absolute target. Returns the Arnoldi steps taken; x += Z y.
 template <class VT>
 static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc, int m, double *x,
-                       hipStream_t s) {
+                       hipStream_t s, bool sync_end = true) {
     const int64_t n = A.n, ldv = ws.ldv;
     VT *V, *Z, *w;
     if constexpr (sizeof(VT) == 8) {
@@ -902,6 +906,7 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
     HEC_CHECK_LAUNCH();
     k_update_x<VT><<<ceil_div(n, 256), 256, 0, s>>>(n, Z, ldv, x, sd, si, L);
     HEC_CHECK_LAUNCH();
+    if (!sync_end) return -1;  // the caller reads the step count after its own synchronisation
     HEC_HIP(hipStreamSynchronize(s));
     return hf(ws)[SI_JDONE];
 }
@@ -916,6 +921,16 @@ static double read_scalar(KrylovWS &ws, int idx, hipStream_t s) {
 static void set_scalar(KrylovWS &ws, int idx, double v, hipStream_t s) {
     HEC_HIP(hipMemcpyAsync(ws.sd.get() + idx, &v, sizeof(double), hipMemcpyHostToDevice, s));
     HEC_HIP(hipStreamSynchronize(s));
+}
+
+__global__ void k_set_scalar(double *p, double v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+// The same without a host round trip: the value travels as a kernel argument.
+static void set_scalar_async(KrylovWS &ws, int idx, double v, hipStream_t s) {
+    k_set_scalar<<<1, 64, 0, s>>>(ws.sd.get() + idx, v);
+    HEC_CHECK_LAUNCH();
 }
 
 // ||b - A x|| for the FP64 matrix into ws.r; returns the norm
@@ -982,21 +997,27 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
         int it = 0, cycles = 0;
         while (res / bnorm > target && it < o->maxit) {
             int mcyc = std::min(o->restart, o->maxit - it);
-            int jd;
             if (!mixed) {
-                set_scalar(ws, SD_TOL, target * bnorm, s);
-                jd = gmres_cycle<double>(*A, *lv, ws, mcyc, o->restart, x, s);
+                set_scalar_async(ws, SD_TOL, target * bnorm, s);
+                gmres_cycle<double>(*A, *lv, ws, mcyc, o->restart, x, s, false);
             } else {
                 // inner solve of A d = r in FP32 storage, one cycle, to inner_rtol
                 double inner = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-4;
-                set_scalar(ws, SD_TOL, std::max(inner * res, 0.5 * target * bnorm), s);
-                jd = gmres_cycle<float>(*A, *lv, ws, mcyc, o->restart, x, s);
+                set_scalar_async(ws, SD_TOL, std::max(inner * res, 0.5 * target * bnorm), s);
+                gmres_cycle<float>(*A, *lv, ws, mcyc, o->restart, x, s, false);
                 inf.ir_steps++;
             }
-            inf.rel_res_est = read_scalar(ws, SD_RES, s) / bnorm;
+            // the true residual after the cycle, then one copy of the scalars and one
+            // synchronisation for the cycle's estimate, the true residual and the step count
+            spmv_launch<double, double, double>(*A, -1.0, x, 1.0, b, ws.r.get(), s);
+            launch_pass<1>(ws, n, OpNorm<double>{{}, ws.r.get(), ws.sd.get() + SD_TRUE}, 1, s, nullptr);
+            HEC_HIP(hipMemcpyAsync(ws.hsd, ws.sd.get(), SD_SCALARS * sizeof(double), hipMemcpyDeviceToHost, s));
+            HEC_HIP(hipStreamSynchronize(s));
+            const int jd = hf(ws)[SI_JDONE];
+            inf.rel_res_est = ws.hsd[SD_RES] / bnorm;
+            res = ws.hsd[SD_TRUE];
             it += jd;
             cycles++;
-            res = true_residual(*A, ws, b, x, s);
             if (jd == 0) break;  // no progress possible (breakdown at the start of a cycle)
         }
         inf.iterations = it;
