@@ -1072,8 +1072,8 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
             if (!hf(ws)[SI_DONE]) {
                 int k = 0;
                 for (; it + k < o->maxit; ++k) {
-                    if (k >= 2) {  // wait for pass k-2, keep pass k-1 queued
-                        HEC_HIP(hipEventSynchronize(ws.ev[k % 2]));
+                    if (k >= 3 && (k & 1)) {  // every other pass: wait for pass k-2, keep k-1 queued
+                        HEC_HIP(hipEventSynchronize(ws.ev[1]));
                         if (hf(ws)[SI_DONE]) break;
                     }
                     const int32_t *done = si + SI_DONE;
@@ -1091,7 +1091,7 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
                     spmv_launch<double, double, double>(*A, 1.0, ss, 0.0, t, t, s, done);
                     launch_pass<2>(ws, n, OpBiOmega{{}, t, sv, sd}, 2, s, done);
                     launch_pass<2>(ws, n, OpBiXR{{}, x, r, ps, ss, sv, t, r0, sd, si, ws.dflags}, 2, s, done);
-                    HEC_HIP(hipEventRecord(ws.ev[k % 2], s));
+                    if (k & 1) HEC_HIP(hipEventRecord(ws.ev[1], s));  // an event record costs ~6 us of stream time
                 }
                 HEC_HIP(hipStreamSynchronize(s));
                 it += hf(ws)[SI_JDONE];
@@ -1155,8 +1155,8 @@ hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, dou
             if (!hf(ws)[SI_DONE]) {
                 const int32_t *done = si + SI_DONE;
                 for (int k = 0; it + k < o->maxit; ++k) {
-                    if (k >= 2) {  // wait for iteration k-2, keep k-1 queued
-                        HEC_HIP(hipEventSynchronize(ws.ev[k % 2]));
+                    if (k >= 3 && (k & 1)) {  // every other iteration: wait for k-2, keep k-1 queued
+                        HEC_HIP(hipEventSynchronize(ws.ev[1]));
                         if (hf(ws)[SI_DONE]) break;
                     }
                     spmv_launch<double, double, double>(*A, 1.0, p, 0.0, q, q, s, done);
@@ -1166,7 +1166,7 @@ hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, dou
                     launch_pass<1>(ws, n, OpCgRho{{}, r, z, sd, si, ws.dflags}, 1, s, done);
                     k_cg_p<<<g, 256, 0, s>>>(n, z, p, sd, si);
                     HEC_CHECK_LAUNCH();
-                    HEC_HIP(hipEventRecord(ws.ev[k % 2], s));
+                    if (k & 1) HEC_HIP(hipEventRecord(ws.ev[1], s));  // an event record costs ~6 us of stream time
                 }
                 HEC_HIP(hipStreamSynchronize(s));
                 it += hf(ws)[SI_JDONE];
