@@ -868,11 +868,10 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
     // beta = ||r||, g = beta e1
     OpCycleStart st{{}, ws.r.get(), sd, si, ws.dflags, L};
     launch_pass<1>(ws, n, st, 1, s, nullptr);
-    HEC_HIP(hipEventRecord(ws.ev[0], s));
     k_scale_start<VT, double><<<ceil_div(n, 256), 256, 0, s>>>(n, ws.r.get(), V, sd);
     HEC_CHECK_LAUNCH();
-    HEC_HIP(hipEventSynchronize(ws.ev[0]));
-    if (hf(ws)[SI_DONE]) return 0;
+    // no wait here: if the start is already converged, the queued steps return at entry
+    // (the device's done flag) and the cycle adds no columns to x
     for (int j = 0; j < mcyc; ++j) {
         // look two iterations behind, every other iteration: stop issuing work once the
         // device is done. An event record costs the stream about 6 us (it waits for the
