@@ -558,7 +558,7 @@ struct OpBiAlpha : NoInit {
     }
 };
 
-// s = r - alpha v, ||s||; if ||s|| is small: x += alpha p*, stop.
+// s = r - alpha v, ||s||; if ||s|| is small: x += alpha p* (k_bi_xs of the same pass) and stop.
 struct OpBiS : NoInit {
     const double *r, *v, *ps;
     double *s, *x;
@@ -571,24 +571,23 @@ struct OpBiS : NoInit {
     }
     __device__ void finish(const double *t) const {
         sd[SD_SNORM2] = t[0];
-        si[SI_JDONE] += 1;
-        mirror(hf, SI_JDONE, si[SI_JDONE]);
-        if (!(sqrt(t[0]) > sd[SD_TOL])) si[SI_STOP_S] = 1;
+        const int32_t pass = si[SI_JDONE] + 1;
+        si[SI_JDONE] = pass;
+        mirror(hf, SI_JDONE, pass);
+        if (!(sqrt(t[0]) > sd[SD_TOL])) {  // the pass that stops is recorded for k_bi_xs
+            si[SI_STOP_S] = pass;
+            si[SI_DONE] = 1;
+            mirror(hf, SI_DONE, 1);
+        }
     }
 };
 
-// once ||s|| was small enough the rest of the pass is skipped
-__global__ void k_fold_stop(int32_t *si, int32_t *hf) {
-    if (si[SI_STOP_S] && !si[SI_DONE]) {
-        si[SI_DONE] = 1;
-        mirror(hf, SI_DONE, 1);
-    }
-}
-
-// early exit of Alg. 4: x += alpha p* when ||s|| was small enough
-__global__ __launch_bounds__(256) void k_bi_xs(int64_t n, double *x, const double *ps, double *sd, int32_t *si,
-                                               int32_t *hf) {
-    if (si[SI_DONE] || !si[SI_STOP_S]) return;
+// early exit of Alg. 4: x += alpha p* when ||s|| was small enough in this pass (the
+// pass number, counted from the run's start, is what OpBiS recorded; the rest of the
+// pass is skipped by the done flag OpBiS set)
+__global__ __launch_bounds__(256) void k_bi_xs(int64_t n, double *x, const double *ps, const double *sd,
+                                               const int32_t *si, int32_t pass) {
+    if (si[SI_STOP_S] != pass) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] += sd[SD_ALPHA] * ps[i];
 }
@@ -1082,9 +1081,7 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
                     spmv_launch<double, double, double>(*A, 1.0, ps, 0.0, v, v, s, done);
                     launch_pass<1>(ws, n, OpBiAlpha{{}, r0, v, sd, si, ws.dflags}, 1, s, done);
                     launch_pass<1>(ws, n, OpBiS{{}, r, v, ps, sv, x, sd, si, ws.dflags}, 1, s, done);
-                    k_bi_xs<<<g, 256, 0, s>>>(n, x, ps, sd, si, ws.dflags);
-                    HEC_CHECK_LAUNCH();
-                    k_fold_stop<<<1, 1, 0, s>>>(si, ws.dflags);
+                    k_bi_xs<<<g, 256, 0, s>>>(n, x, ps, sd, si, k + 1);
                     HEC_CHECK_LAUNCH();
                     trsv_launch<double>(*lv, HEC_LU, sv, ss, s, done);
                     spmv_launch<double, double, double>(*A, 1.0, ss, 0.0, t, t, s, done);
