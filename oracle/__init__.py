@@ -75,12 +75,12 @@ def lib():
         L.orc_trsv_lower.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_trsv_upper.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_gmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
-                                C.c_int, C.c_int, C.c_double, _ip, _dp]
+                                C.c_int, C.c_int, C.c_double, _ip, _dp, C.c_void_p, C.c_void_p, _ip]
         L.orc_gmres.restype = C.c_int
         L.orc_bicgstab.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
-                                   C.c_int, C.c_double, _ip, _dp]
+                                   C.c_int, C.c_double, _ip, _dp, _ip]
         L.orc_bicgstab.restype = C.c_int
-        L.orc_cg.argtypes = L.orc_bicgstab.argtypes
+        L.orc_cg.argtypes = L.orc_bicgstab.argtypes[:-1]
         L.orc_cg.restype = C.c_int
         _lib = L
     return _lib
@@ -237,16 +237,28 @@ class SolveResult:
     x: np.ndarray
     iterations: int
     rel_res: float
+    restarts: int = 0
+    # GMRES with arnoldi=True: the last cycle's basis V ((steps+1) x n, or steps x n when
+    # the cycle stopped on convergence) and its Hessenberg matrix before the rotations
+    # ((restart+1) x restart)
+    V: np.ndarray = None
+    Hbar: np.ndarray = None
+    steps: int = 0
 
 
-def gmres(A, F: Factor, b, x0=None, restart=30, maxit=10000, rtol=1e-8) -> SolveResult:
+def gmres(A, F: Factor, b, x0=None, restart=30, maxit=10000, rtol=1e-8, arnoldi=False) -> SolveResult:
     """Restarted right-preconditioned GMRES(m) with MGS (Sec. 2.7). A has .n/.Ap/.Aj/.Ax."""
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
     it = C.c_int()
     rr = C.c_double()
+    steps = C.c_int(0)
+    V = np.zeros((restart + 1, A.n)) if arnoldi else None
+    H = np.zeros((restart + 1, restart)) if arnoldi else None
     st = lib().orc_gmres(A.n, _i32(A.Ap), _i32(A.Aj), _f64(A.Ax), F.LUp, F.LUj, F.LUx, _f64(b), x,
-                         restart, maxit, rtol, C.byref(it), C.byref(rr))
-    return SolveResult(st, x, it.value, rr.value)
+                         restart, maxit, rtol, C.byref(it), C.byref(rr),
+                         V.ctypes.data if arnoldi else None, H.ctypes.data if arnoldi else None,
+                         C.byref(steps))
+    return SolveResult(st, x, it.value, rr.value, 0, V, H, steps.value)
 
 
 def bicgstab(A, F: Factor, b, x0=None, maxit=10000, rtol=1e-8) -> SolveResult:
@@ -254,9 +266,10 @@ def bicgstab(A, F: Factor, b, x0=None, maxit=10000, rtol=1e-8) -> SolveResult:
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
     it = C.c_int()
     rr = C.c_double()
+    rs = C.c_int()
     st = lib().orc_bicgstab(A.n, _i32(A.Ap), _i32(A.Aj), _f64(A.Ax), F.LUp, F.LUj, F.LUx, _f64(b), x,
-                            maxit, rtol, C.byref(it), C.byref(rr))
-    return SolveResult(st, x, it.value, rr.value)
+                            maxit, rtol, C.byref(it), C.byref(rr), C.byref(rs))
+    return SolveResult(st, x, it.value, rr.value, rs.value)
 
 
 def cg(A, F: Factor, b, x0=None, maxit=10000, rtol=1e-8) -> SolveResult:

@@ -12,13 +12,16 @@ benchmark's CPU leg use it; it shares no code with the GPU library.
   undecided points it strongly influences become F, and each undecided point
   that strongly influences a new F point gains 1; each undecided point that
   strongly influences the new C point loses 1.
-* direct_interpolation(A, S, cf): "RSD" (Stueben's direct interpolation). A C
-  point injects its coarse value. An F point i interpolates from its strong C
-  neighbours C_i, separately for negative and positive couplings:
-  w_ij = -alpha_i a_ij / a_ii (a_ij < 0), w_ij = -beta_i a_ij / a_ii (a_ij > 0),
-  alpha_i = sum_{k != i, a_ik < 0} a_ik / sum_{j in C_i, a_ij < 0} a_ij and beta_i
-  likewise over positive entries; when C_i holds no positive coupling, the
-  positive entries are added to the diagonal instead.
+* direct_interpolation(A, S, cf, theta): "RSD" (Stueben's direct interpolation).
+  A C point injects its coarse value. An F point i interpolates from its strong
+  C neighbours, separately for negative and positive couplings:
+  w_ij = -alpha_i a_ij / a_ii for j in C_i^- = C & S_i (the strong negative
+  couplings above), w_ij = -beta_i a_ij / a_ii for j in C_i^+, the C points j
+  with a_ij > 0 and a_ij >= theta * max_{k != i} a_ik (strong positive couplings,
+  used for interpolation only, not for the coarsening);
+  alpha_i = sum_{k != i, a_ik < 0} a_ik / sum_{j in C_i^-} a_ij and beta_i likewise
+  over the positive entries; when C_i^+ is empty, the positive entries are added
+  to the diagonal instead.
 * galerkin(A, P): A_c = P^T A P (R = P^T), in a stated order: (AP)_iJ sums
   a_ik p_kJ over row i of A in column order; (A_c)_IJ sums p_iI (AP)_iJ over the
   fine rows i in ascending order. Every entry touched is kept, zero or not.
@@ -100,7 +103,7 @@ def rs_split(n, Sp, Sj):
     return (state == C).astype(np.int8)
 
 
-def direct_interpolation(M: sp.csr_matrix, Sp, Sj, cf):
+def direct_interpolation(M: sp.csr_matrix, Sp, Sj, cf, theta=0.25):
     """P (n x nc) as a scipy CSR matrix with columns ascending."""
     n = M.shape[0]
     cidx = np.cumsum(cf) - 1  # coarse index of each C point
@@ -114,7 +117,9 @@ def direct_interpolation(M: sp.csr_matrix, Sp, Sj, cf):
             continue
         cols = M.indices[M.indptr[i]:M.indptr[i + 1]]
         vals = M.data[M.indptr[i]:M.indptr[i + 1]]
-        strong = set(int(j) for j in Sj[Sp[i]:Sp[i + 1]])
+        strong = set(int(j) for j in Sj[Sp[i]:Sp[i + 1]])  # strong negative couplings
+        mpos = max((v for j, v in zip(cols, vals) if j != i and v > 0), default=0.0)
+        strong |= set(int(j) for j, v in zip(cols, vals) if j != i and v > 0 and v >= theta * mpos)
         aii = 0.0
         sneg = spos = cneg = cpos = 0.0
         for j, v in zip(cols, vals):
@@ -201,7 +206,7 @@ def hierarchy(A, theta=0.25, max_levels=8, coarse_size=64, omega=2.0 / 3.0, nu1=
         nc = int(cf.sum())
         if nc == 0 or nc == n:
             break
-        P = direct_interpolation(M, Sp, Sj, cf)
+        P = direct_interpolation(M, Sp, Sj, cf, theta)
         lev.cf, lev.P = cf, P
         M = galerkin(M, P)
     return Hierarchy(levels, omega, nu1, nu2)

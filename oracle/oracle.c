@@ -328,11 +328,18 @@ static double residual(int n, const int *Ap, const int *Aj, const double *Ax,
  * |g_{j+1}| / ||b|| <= rtol or h_{j+1,j} == 0; then H y = g is back-solved and
  * x += M^{-1} (V y). The true residual decides convergence, otherwise the
  * method restarts from x. iters counts Arnoldi steps; maxit bounds them.
- * LU is the in-place factor (L strict lower, U upper with diagonal). */
+ * LU is the in-place factor (L strict lower, U upper with diagonal).
+ *
+ * Optional outputs of the last cycle (NULL to skip), for checking the Arnoldi
+ * relation A M^{-1} V_j = V_{j+1} Hbar_j: V_out gets the basis vectors computed
+ * in it, (m+1) x n, vector i at V_out + i*n; Hbar_out the (m+1) x m Hessenberg
+ * matrix as Gram-Schmidt produced it, before the rotations (row i, column j at
+ * Hbar_out[i*m + j]); steps_out the number of its Arnoldi steps. */
 int orc_gmres(int n, const int *Ap, const int *Aj, const double *Ax,
               const int *LUp, const int *LUj, const double *LUx,
               const double *b, double *x, int m, int maxit, double rtol,
-              int *iters_out, double *relres_out)
+              int *iters_out, double *relres_out,
+              double *V_out, double *Hbar_out, int *steps_out)
 {
     *iters_out = 0;
     double bnorm = nrm2(n, b);
@@ -365,7 +372,9 @@ int orc_gmres(int n, const int *Ap, const int *Aj, const double *Ax,
         for (int i = 0; i < n; ++i) V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i) g[i] = 0.0;
         g[0] = beta;
-        int jdone = 0;
+        if (Hbar_out)
+            for (int i = 0; i < (m + 1) * m; ++i) Hbar_out[i] = 0.0;
+        int jdone = 0, vdone = 1;
         for (int j = 0; j < m && it < maxit; ++j) {
             double *vj = V + (size_t)j * N;
             apply_prec(n, LUp, LUj, LUx, vj, z, tmp);
@@ -378,6 +387,8 @@ int orc_gmres(int n, const int *Ap, const int *Aj, const double *Ax,
             }
             double hn = nrm2(n, w);
             H[(j + 1) * m + j] = hn;
+            if (Hbar_out)
+                for (int i = 0; i <= j + 1; ++i) Hbar_out[i * m + j] = H[i * m + j];
             for (int i = 0; i < j; ++i) {
                 double a = H[i * m + j], c = H[(i + 1) * m + j];
                 H[i * m + j] = cs[i] * a + sn[i] * c;
@@ -396,7 +407,10 @@ int orc_gmres(int n, const int *Ap, const int *Aj, const double *Ax,
             if (fabs(g[j + 1]) / bnorm <= rtol || hn == 0.0) break;
             double *vn = V + (size_t)(j + 1) * N;
             for (int q = 0; q < n; ++q) vn[q] = w[q] / hn;
+            vdone = j + 2;
         }
+        if (V_out) memcpy(V_out, V, sizeof(double) * (size_t)n * (size_t)vdone);
+        if (steps_out) *steps_out = jdone;
         /* back-solve the triangular H y = g */
         for (int i = jdone - 1; i >= 0; --i) {
             double t = g[i];
@@ -426,13 +440,15 @@ int orc_gmres(int n, const int *Ap, const int *Aj, const double *Ax,
  * ||r||. rho == 0 or (r0, v) == 0 is a breakdown; omega == 0 stops. After the
  * recurrence stops, the true residual b - A x decides; if it is not below rtol
  * the method restarts from x (new r0), at most 3 times, within maxit passes of
- * the loop. iters counts loop passes (2 products each). */
+ * the loop. iters counts loop passes (2 products each); restarts_out (may be
+ * NULL) the cycles started after the first. */
 int orc_bicgstab(int n, const int *Ap, const int *Aj, const double *Ax,
                  const int *LUp, const int *LUj, const double *LUx,
                  const double *b, double *x, int maxit, double rtol,
-                 int *iters_out, double *relres_out)
+                 int *iters_out, double *relres_out, int *restarts_out)
 {
     *iters_out = 0;
+    if (restarts_out) *restarts_out = 0;
     double bnorm = nrm2(n, b);
     if (bnorm == 0.0) {
         for (int i = 0; i < n; ++i) x[i] = 0.0;
@@ -455,9 +471,10 @@ int orc_bicgstab(int n, const int *Ap, const int *Aj, const double *Ax,
     }
     int it = 0, status = ORC_NOT_CONVERGED;
     double relres = residual(n, Ap, Aj, Ax, b, x, r) / bnorm;
-    int restarts = 0;
+    int cycles = 0;
     int broke = 0;
-    while (relres > rtol && it < maxit && restarts <= 3) {
+    while (relres > rtol && it < maxit && cycles < 4) {
+        ++cycles;
         /* r0 = b - A x0 */
         for (int i = 0; i < n; ++i) r0[i] = r[i];
         double rho_prev = 0.0, alpha = 0.0, omega = 0.0;
@@ -492,12 +509,12 @@ int orc_bicgstab(int n, const int *Ap, const int *Aj, const double *Ax,
             rho_prev = rho;
         }
         relres = residual(n, Ap, Aj, Ax, b, x, r) / bnorm;
-        if (relres > rtol) ++restarts;
     }
     if (relres <= rtol) status = ORC_OK;
     else if (broke) status = ORC_BREAKDOWN;
     *iters_out = it;
     *relres_out = relres;
+    if (restarts_out) *restarts_out = cycles > 0 ? cycles - 1 : 0;
     free(r0); free(r); free(p); free(ps); free(v); free(s); free(ss); free(t); free(tmp);
     return status;
 }

@@ -67,3 +67,31 @@ def identity_factor(n):
     import oracle as O
     return O.Factor(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
                     np.ones(n), np.zeros(n, np.int32))
+
+
+def poisson2d_positive(m, pairs, rng):
+    """2D 5-point Poisson (m x m) plus `pairs` symmetric positive couplings between random
+    points at most two cells apart, each added to both diagonals as well: a symmetric,
+    diagonally dominant (so SPD) matrix that is not an M-matrix."""
+    n = m * m
+    D = np.zeros((n, n))
+    for y in range(m):
+        for x in range(m):
+            i = x + m * y
+            D[i, i] = 4.0
+            for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                if 0 <= x + dx < m and 0 <= y + dy < m:
+                    D[i, x + dx + m * (y + dy)] = -1.0
+    for _ in range(pairs):
+        x, y = rng.integers(0, m, 2)
+        dx, dy = rng.integers(-2, 3, 2)
+        if (dx, dy) == (0, 0) or not (0 <= x + dx < m and 0 <= y + dy < m):
+            continue
+        i, j = x + m * y, x + dx + m * (y + dy)
+        if D[i, j] != 0.0:
+            continue
+        v = float(rng.uniform(0.1, 0.6))
+        D[i, j] = D[j, i] = v
+        D[i, i] += v
+        D[j, j] += v
+    return from_dense(D)

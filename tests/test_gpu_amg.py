@@ -10,7 +10,7 @@ import pytest
 from oracle import amg as OA
 from paper_1606_00545_amd import hec, synth
 from tests._gpu import dev, empty, host
-from tests._mats import from_dense
+from tests._mats import from_dense, poisson2d_positive
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +25,17 @@ def _cases():
     yield "poisson3d_16_two_levels", lambda: synth.poisson3d(16), {"max_levels": 2, "nu1": 1, "nu2": 2}
     yield "aniso3d_14", lambda: synth.lognormal_tpfa((14, 14, 14), 1.0, np.random.default_rng(3), zscale=0.01), \
         {"omega": 0.8}
+    # not M-matrices: positive off-diagonal couplings reach the beta weights and the lumping
+    # of direct interpolation
+    yield "nonm_worked_5", _worked_non_m, {"coarse_size": 1}
+    yield "poisson2d_40_positive", lambda: poisson2d_positive(40, 300, np.random.default_rng(7)), {}
+
+
+def _worked_non_m():
+    D = 4.0 * np.eye(5) - np.eye(5, k=1) - np.eye(5, k=-1)
+    for (i, j), v in {(0, 3): 0.5, (2, 4): 0.3, (0, 4): 0.05}.items():
+        D[i, j] = D[j, i] = v
+    return from_dense(D)
 
 
 CASES = {c[0]: c[1:] for c in _cases()}

@@ -63,5 +63,18 @@ def test_fullsize_solve_true_residual(system, solver):
     print(f"{solver}: iterations {info['iterations']} rel_res {rr:.3e} "
           f"|x - x_true|/|x_true| {np.linalg.norm(xh - xt) / np.linalg.norm(xt):.3e}")
     assert info["status"] == hec.OK and rr <= 1e-8
-    # the oracle needs 150 (GMRES) and 88 (BiCGSTAB) iterations on this system
-    assert abs(info["iterations"] - (150 if solver == "gmres" else 88)) <= 15
+    # the oracle's iteration counts on this system (tests/golden/make_fullsize_iterations.py)
+    want = _oracle_iterations()["gmres30" if solver == "gmres" else "bicgstab"]
+    assert abs(info["iterations"] - want) <= max(3, want // 10)
+
+
+def _oracle_iterations():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_iterations.txt")
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, it = line.split()[:2]
+                out[name] = int(it)
+    return out

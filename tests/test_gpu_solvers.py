@@ -190,3 +190,67 @@ def test_gmres_restart_lengths_match_oracle(restart, precision):
     if precision == 0:
         assert abs(info["iterations"] - ro.iterations) <= max(2, ro.iterations // 10)
     print(f"restart {restart} precision {precision}: gpu it={info['iterations']} oracle it={ro.iterations} res={rr:.2e}")
+
+
+# Alg. 4's breakdowns on 3 x 3 integer systems with the identity preconditioner (the ILU(0)
+# of the identity matrix): every quantity of the first pass is a small dyadic rational, so
+# the device reaches the same exact-zero tests as the oracle, whatever its summation order.
+_BREAK_CASES = {
+    "rho": ([[-1, 2, 1], [-1, -2, 1], [2, 2, 1]], [-2, 0, 0]),  # (r0, r) = 0 after pass 1
+    "r0v": ([[-2, 2, 1], [-2, 1, 2], [2, 0, 1]], [0, 0, 1]),    # (r0, v) = 0 inside pass 2
+}
+
+
+def _identity_preconditioned(D):
+    from tests._mats import from_dense
+    A = from_dense(np.array(D, float))
+    n = A.n
+    Mh = hec.hec_from_csr(A)
+    I = from_dense(np.eye(n))
+    F = hec.ilu_factor(I, k=0)
+    lv = hec.level_schedule(F)
+    return A, Mh, F, lv
+
+
+@pytest.mark.parametrize("case", sorted(_BREAK_CASES))
+def test_bicgstab_breakdown_restart_matches_oracle(case):
+    """A breakdown in pass 2, a restart from the current x, then convergence at the
+    half step (s small: x += alpha p*) of the third pass of the second cycle."""
+    from tests._mats import identity_factor
+    D, bl = _BREAK_CASES[case]
+    A, Mh, F, lv = _identity_preconditioned(D)
+    b = np.array(bl, float)
+    ro = O.bicgstab(A, identity_factor(3), b, rtol=1e-10)
+    assert ro.status == O.OK and ro.restarts == 1 and ro.iterations == 4
+    x = empty(3)
+    info = hec.bicgstab_solve(Mh, F, lv, dev(b), x, rtol=1e-10)
+    xh = host(x)
+    assert info["status"] == hec.OK
+    assert (info["iterations"], info["restarts"]) == (ro.iterations, ro.restarts)
+    assert np.abs(xh - ro.x).max() <= 1e-13 * np.abs(ro.x).max()
+    # one pass only: the iterate after pass 1 is exact on both sides
+    x1 = empty(3)
+    i1 = hec.bicgstab_solve(Mh, F, lv, dev(b), x1, maxit=1, rtol=1e-10, check=False)
+    r1 = O.bicgstab(A, identity_factor(3), b, maxit=1, rtol=1e-10)
+    assert i1["status"] == hec.NOT_CONVERGED and i1["iterations"] == 1
+    assert host(x1).tolist() == r1.x.tolist()
+
+
+def test_bicgstab_breakdown_status_after_three_restarts():
+    """Skew-symmetric A: (r, A r) = 0 for every r, so every cycle breaks down in its first
+    pass; the solver returns BREAKDOWN with x left at x0, as the oracle does."""
+    from tests._mats import identity_factor
+    n = 4
+    D = np.eye(n, k=1) - np.eye(n, k=-1)
+    A, Mh, F, lv = _identity_preconditioned(D)
+    b = np.arange(1.0, n + 1)
+    ro = O.bicgstab(A, identity_factor(n), b, rtol=1e-10)
+    assert ro.status == O.BREAKDOWN and ro.restarts == 3 and ro.iterations == 0
+    x = dev(np.array([1.0, -2.0, 0.5, 3.0]))
+    info = hec.bicgstab_solve(Mh, F, lv, dev(b), x, rtol=1e-10, x0_zero=False, check=False)
+    assert info["status"] == hec.BREAKDOWN
+    assert (info["iterations"], info["restarts"]) == (0, 3)
+    assert host(x).tolist() == [1.0, -2.0, 0.5, 3.0]
+    with pytest.raises(hec.HecError) as e:
+        hec.bicgstab_solve(Mh, F, lv, dev(b), empty(n), rtol=1e-10)
+    assert e.value.code == hec.BREAKDOWN

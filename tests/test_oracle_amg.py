@@ -138,3 +138,74 @@ def test_3d_poisson_converges_in_few_cycles():
     r = amg.solve(H, b, rtol=1e-8)
     assert r.converged and r.iterations <= 12
     assert np.linalg.norm(b - H.levels[0].A @ r.x) <= 1e-8 * np.linalg.norm(b)
+
+
+def _non_m_matrix():
+    """5 x 5, diagonal 4, the 1D chain -1 couplings, and positive couplings
+    a_03 = a_30 = 0.5, a_24 = a_42 = 0.3, a_04 = a_40 = 0.05."""
+    D = 4.0 * np.eye(5) - np.eye(5, k=1) - np.eye(5, k=-1)
+    for (i, j), v in {(0, 3): 0.5, (2, 4): 0.3, (0, 4): 0.05}.items():
+        D[i, j] = D[j, i] = v
+    return from_dense(D)
+
+
+def test_direct_interpolation_positive_couplings_worked_example():
+    """Sec. 2.8's RSD on a matrix with positive off-diagonal entries, by hand (theta = 0.25).
+    Strength (negative couplings) is that of the 1D chain, so the first pass gives
+    C = {1, 3} (point 1 first: largest measure, smallest index; 0 and 2 become F, 3 gains
+    one; then 3; 4 becomes F). Strong positive couplings (a_ij >= theta * the row's largest
+    positive entry): row 0 -> {3} (0.05 < 0.125 is weak), row 2 -> {4}, row 4 -> {2}.
+    Row 0: alpha = -1/-1 = 1, beta = (0.5 + 0.05)/0.5 = 1.1 (its strong positive neighbour 3
+      is C), w_01 = -1 * (-1)/4 = 0.25, w_03 = -1.1 * 0.5/4 = -0.1375.
+    Row 2: its strong positive neighbour 4 is F, so 0.3 is lumped: a_22 -> 4.3, alpha = 1,
+      w_21 = w_23 = 1/4.3.
+    Row 4: positive neighbours 0 and 2 are F: a_44 -> 4 + 0.35, w_43 = 1/4.35."""
+    H = amg.hierarchy(_non_m_matrix(), coarse_size=1)
+    lev = H.levels[0]
+    assert lev.cf.tolist() == [0, 1, 0, 1, 0]
+    want = np.array([[0.25, -0.1375], [1, 0], [1 / 4.3, 1 / 4.3], [0, 1], [0, 1 / 4.35]])
+    assert np.allclose(lev.P.toarray(), want, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_direct_interpolation_weight_sums_on_non_m_matrices(seed):
+    """For an F row, alpha_i and beta_i make the weights sum to -(sum_{j != i} a_ij)/a_ii when
+    the row interpolates from both signs, and to -(negative sum)/(a_ii + positive sum) when
+    its positive entries are lumped; both branches occur on these matrices."""
+    rng = np.random.default_rng(seed)
+    A = synth.poisson2d(14)
+    M = A.to_scipy().tolil()
+    n = A.n
+    for _ in range(60):  # symmetric positive couplings between random pairs of points
+        i, j = rng.integers(0, n, 2)
+        if i != j:
+            v = rng.uniform(0.05, 0.8)
+            M[i, j] = M[j, i] = v
+    M = M.tocsr()
+    M.sort_indices()
+    H = amg.hierarchy(from_dense(M.toarray()), coarse_size=8)
+    lev = H.levels[0]
+    P, cf = lev.P.tocsr(), lev.cf
+    Sp, Sj = amg.strength(lev.A, 0.25)
+    seen = set()
+    for i in range(n):
+        if cf[i]:
+            continue
+        row = M.getrow(i)
+        cols, vals = row.indices, row.data
+        aii = vals[cols == i][0]
+        off = cols != i
+        neg, pos = vals[off & (vals < 0)].sum(), vals[off & (vals > 0)].sum()
+        mpos = vals[off & (vals > 0)].max(initial=0.0)
+        spos = [j for j, v in zip(cols, vals) if j != i and v > 0 and v >= 0.25 * mpos and cf[j]]
+        sneg = [j for j in Sj[Sp[i]:Sp[i + 1]] if cf[j]]
+        if not sneg:
+            continue
+        wsum = P.getrow(i).sum()
+        if spos:
+            seen.add("beta")
+            assert abs(wsum + (neg + pos) / aii) <= 1e-14
+        else:
+            seen.add("lumped" if pos > 0 else "plain")
+            assert abs(wsum + neg / (aii + pos)) <= 1e-14
+    assert {"beta", "lumped"} <= seen
