@@ -16,9 +16,9 @@
  *    stated dtype (for example torch tensors' data_ptr()). `stream` is a
  *    hipStream_t (NULL = the default stream).
  *  - Handles own their device memory until the matching *_destroy call. It is
- *    allocated and released in stream order (hipMallocAsync/hipFreeAsync) on
- *    the stream of the call that created it; destroy a handle before that
- *    stream.
+ *    allocated and released in stream order on the stream of the call that
+ *    created it (hipMallocAsync/hipFreeAsync, or the hooks of
+ *    hec_set_allocator); destroy a handle before that stream.
  *  - Every call returns an hec_status; on failure a message for the calling
  *    thread is available from hec_last_error(). No C++ exception crosses the
  *    ABI. Arguments are validated on the host before any device work.
@@ -30,6 +30,7 @@
 #ifndef HEC_H
 #define HEC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -90,6 +91,31 @@ typedef struct {
     double rel_res_est;  /* the solver's own recurrence estimate at its last step */
     double seconds;      /* wall time of the call */
 } hec_solve_info;
+
+/* ---------------------------------------------------------------- device memory */
+
+/* Allocation hooks: alloc returns `bytes` of device memory usable in stream order
+ * on `stream` (a hipStream_t), or NULL on failure (the call then fails with
+ * NOMEM); free releases a block that alloc returned, in stream order on the
+ * stream it was allocated on. ctx is passed through. */
+typedef void *(*hec_alloc_fn)(void *ctx, size_t bytes, void *stream);
+typedef void (*hec_free_fn)(void *ctx, void *ptr, size_t bytes, void *stream);
+
+/* Every device buffer the library allocates from now on (handles, solver
+ * workspaces, batch contexts, AMG levels) comes from `alloc` and goes back
+ * through `free` -- for example a binding to a framework's caching allocator.
+ * alloc == free == NULL restores the default (hipMallocAsync / hipFreeAsync on
+ * the device's default memory pool). A buffer is always released by the
+ * allocator that made it, so the hooks may change while handles exist; they
+ * must stay callable until every buffer they made is released, and may be
+ * called from any thread that calls the library. INVALID_ARG if only one of the
+ * two is NULL. Pinned host memory (flags, staging) does not go through them. */
+hec_status hec_set_allocator(hec_alloc_fn alloc, hec_free_fn free, void *ctx);
+
+/* Device bytes currently held by the given handles (any may be NULL), the
+ * matrix's cached solver workspace included: what a caller, for example a
+ * serving loop admitting requests by memory, should count for one system. */
+hec_status hec_footprint(hec_matrix A, hec_ilu M, hec_levels lv, int64_t *bytes);
 
 /* ---------------------------------------------------------------- HEC matrix */
 
@@ -217,8 +243,11 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
 
 /* Preconditioned BiCGSTAB exactly as Alg. 4 (shadow residual r0 = b - A x0),
  * "||s|| / ||r|| satisfied" read as <= rtol * ||b||; rho == 0 or (r0, v) == 0 is
- * a breakdown, after which the method restarts once from the current x before
- * reporting BREAKDOWN. FP64 only (precision must be 0). */
+ * a breakdown. When a cycle stops (breakdown, or a recurrence residual below rtol
+ * that the FP64 true residual does not confirm), the method restarts from the
+ * current x with a new shadow residual, at most 3 times (info->restarts counts
+ * them); BREAKDOWN is returned when the last cycle broke down and x is not
+ * converged, x then holding the last iterate. FP64 only (precision must be 0). */
 hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
                           const hec_solve_opts *opts, hec_solve_info *info, void *stream);
 

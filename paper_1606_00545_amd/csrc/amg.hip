@@ -11,10 +11,12 @@
 //    influences become F, the undecided points that strongly influence a new F
 //    point gain 1, those that strongly influence the new C point lose 1;
 //  * direct interpolation ("RSD"): a C point injects its coarse value; an F point
-//    i takes w_ij = -alpha_i a_ij / a_ii from its strong C neighbours j (beta_i for
-//    positive couplings), alpha_i, beta_i the ratios of the row's negative
-//    (positive) off-diagonal sum to that over the strong C neighbours; with no
-//    positive C coupling the positive entries are lumped onto the diagonal;
+//    i takes w_ij = -alpha_i a_ij / a_ii from its strong negative C neighbours j
+//    and w_ij = -beta_i a_ij / a_ii from its strong positive C neighbours (a_ij > 0
+//    and a_ij >= theta * the row's largest positive off-diagonal entry; positive
+//    couplings play no part in the coarsening), alpha_i, beta_i the ratios of the
+//    row's negative (positive) off-diagonal sum to that over those neighbours; with
+//    no strong positive C neighbour the positive entries are lumped onto the diagonal;
 //  * Galerkin: A_c = P^T A P with R = P^T, (AP)_iJ summed over row i of A in
 //    column order, (A_c)_IJ over the fine rows i in ascending order;
 // until a level has at most coarse_size rows, max_levels levels exist, or no
@@ -109,7 +111,7 @@ void rs_split(int32_t n, const std::vector<int32_t> &Sp, const std::vector<int32
 }
 
 Csr direct_interpolation(const Csr &A, const std::vector<int32_t> &Sp, const std::vector<int32_t> &Sj,
-                         const std::vector<int8_t> &cf) {
+                         const std::vector<int8_t> &cf, double theta) {
     const int32_t n = A.n;
     std::vector<int32_t> cidx(n);
     int32_t nc = 0;
@@ -126,7 +128,12 @@ Csr direct_interpolation(const Csr &A, const std::vector<int32_t> &Sp, const std
             P.p.push_back((int32_t)P.j.size());
             continue;
         }
-        for (int32_t e = Sp[i]; e < Sp[i + 1]; ++e) strong[Sj[e]] = 1;
+        for (int32_t e = Sp[i]; e < Sp[i + 1]; ++e) strong[Sj[e]] = 1;  // strong negative couplings
+        double mpos = 0.0;                                                 // and strong positive ones
+        for (int32_t e = A.p[i]; e < A.p[i + 1]; ++e)
+            if (A.j[e] != i && A.x[e] > 0.0) mpos = std::max(mpos, A.x[e]);
+        for (int32_t e = A.p[i]; e < A.p[i + 1]; ++e)
+            if (A.j[e] != i && A.x[e] > 0.0 && A.x[e] >= theta * mpos) strong[A.j[e]] = 1;
         double aii = 0.0, sneg = 0.0, spos = 0.0, cneg = 0.0, cpos = 0.0;
         for (int32_t e = A.p[i]; e < A.p[i + 1]; ++e) {
             const int32_t j = A.j[e];
@@ -152,7 +159,7 @@ Csr direct_interpolation(const Csr &A, const std::vector<int32_t> &Sp, const std
             P.x.push_back((-(v < 0 ? alpha : beta) * v) / aii);
         }
         P.p.push_back((int32_t)P.j.size());
-        for (int32_t e = Sp[i]; e < Sp[i + 1]; ++e) strong[Sj[e]] = 0;
+        for (int32_t e = A.p[i]; e < A.p[i + 1]; ++e) strong[A.j[e]] = 0;
     }
     return P;
 }
@@ -522,7 +529,7 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
                 int32_t nc = 0;
                 for (int8_t c : L->cf) nc += c;
                 if (nc > 0 && nc < nl) {
-                    L->P = amgs::direct_interpolation(L->A, Sp, Sj, L->cf);
+                    L->P = amgs::direct_interpolation(L->A, Sp, Sj, L->cf, o.theta);
                     amgs::Csr R = amgs::transpose(L->P);
                     Ac = amgs::galerkin(L->A, L->P, R);
                     L->dP = upload(L->P, -1, s);

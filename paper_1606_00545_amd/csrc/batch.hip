@@ -381,20 +381,21 @@ struct hec_batch_s {
     hec::BatchHead *h_head = nullptr;
     hec::BatchSys *h_sys = nullptr;
     hec::BatchOut *h_out = nullptr;
-    hec::BatchHead *d_head = nullptr;
-    hec::BatchSys *d_sys = nullptr;
-    hec::BatchOut *d_out = nullptr;
-    double *d_ws = nullptr;
+    int64_t dev_bytes = 0;      // device bytes of the buffers below
+    hec::DevBuf<hec::BatchHead> d_head;
+    hec::DevBuf<hec::BatchSys> d_sys;
+    hec::DevBuf<hec::BatchOut> d_out;
+    hec::DevBuf<double> d_ws;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~hec_batch_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (bs) (void)hipStreamSynchronize(bs);
-        if (d_ws) (void)hipFree(d_ws);
-        if (d_out) (void)hipFree(d_out);
-        if (d_sys) (void)hipFree(d_sys);
-        if (d_head) (void)hipFree(d_head);
+        d_ws.release();  // in order on bs, before it is destroyed
+        d_out.release();
+        d_sys.release();
+        d_head.release();
         if (h_out) (void)hipHostFree(h_out);
         if (h_sys) (void)hipHostFree(h_sys);
         if (h_head) (void)hipHostFree(h_head);
@@ -408,11 +409,11 @@ namespace {
 
 // Kernel launch plus the copies around it, on the context's stream.
 void enqueue_batch(hec_batch_s &B) {
-    HEC_HIP(hipMemcpyAsync(B.d_head, B.h_head, sizeof(BatchHead), hipMemcpyHostToDevice, B.bs));
-    HEC_HIP(hipMemcpyAsync(B.d_sys, B.h_sys, sizeof(BatchSys) * B.capacity, hipMemcpyHostToDevice, B.bs));
-    k_gmres_batch<<<B.capacity, kBT, B.lds, B.bs>>>(B.d_head, B.d_sys, B.d_out, B.max_n);
+    HEC_HIP(hipMemcpyAsync(B.d_head.get(), B.h_head, sizeof(BatchHead), hipMemcpyHostToDevice, B.bs));
+    HEC_HIP(hipMemcpyAsync(B.d_sys.get(), B.h_sys, sizeof(BatchSys) * B.capacity, hipMemcpyHostToDevice, B.bs));
+    k_gmres_batch<<<B.capacity, kBT, B.lds, B.bs>>>(B.d_head.get(), B.d_sys.get(), B.d_out.get(), B.max_n);
     HEC_CHECK_LAUNCH();
-    HEC_HIP(hipMemcpyAsync(B.h_out, B.d_out, sizeof(BatchOut) * B.capacity, hipMemcpyDeviceToHost, B.bs));
+    HEC_HIP(hipMemcpyAsync(B.h_out, B.d_out.get(), sizeof(BatchOut) * B.capacity, hipMemcpyDeviceToHost, B.bs));
 }
 
 int max_dyn_lds() {
@@ -455,13 +456,14 @@ hec_status batch_create(int32_t capacity, int32_t restart, int32_t max_n, int32_
         HEC_HIP(hipHostMalloc((void **)&B->h_sys, sizeof(BatchSys) * capacity, hipHostMallocDefault));
         HEC_HIP(hipHostMalloc((void **)&B->h_out, sizeof(BatchOut) * capacity, hipHostMallocDefault));
         std::memset(B->h_sys, 0, sizeof(BatchSys) * capacity);
-        HEC_HIP(hipMalloc((void **)&B->d_head, sizeof(BatchHead)));
-        HEC_HIP(hipMalloc((void **)&B->d_sys, sizeof(BatchSys) * capacity));
-        HEC_HIP(hipMalloc((void **)&B->d_out, sizeof(BatchOut) * capacity));
-        const size_t per = (size_t)(2 * restart + 3) * max_n;
-        if (hipMalloc((void **)&B->d_ws, sizeof(double) * per * capacity) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(HEC_ERR_NOMEM, "batch workspace allocation failed");
+        {
+            StreamScope scope(B->bs);
+            OwnerScope own(&B->dev_bytes);
+            B->d_head.alloc(1);
+            B->d_sys.alloc(capacity);
+            B->d_out.alloc(capacity);
+            B->d_ws.alloc((size_t)(2 * restart + 3) * max_n * capacity);
+            HEC_HIP(hipStreamSynchronize(B->bs));
         }
         *out = B.release();
     });
@@ -531,7 +533,7 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
             S.pivU32 = fu.piv32.get();
             S.b = b[i];
             S.x = x[i];
-            S.ws = B->d_ws + per * i;
+            S.ws = B->d_ws.get() + per * i;
         }
         BatchHead &Hh = *B->h_head;
         Hh.count = count;

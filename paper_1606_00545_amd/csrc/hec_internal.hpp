@@ -59,8 +59,9 @@ hec_status guarded(F &&body) {
 
 // The stream on which the calling thread's current entry point allocates
 // (set by StreamScope). Allocation is stream-ordered (hipMallocAsync /
-// hipFreeAsync), so setting up or releasing one system never synchronises the
-// whole device while other systems run on other streams.
+// hipFreeAsync by default, or the hooks of hec_set_allocator, which get the
+// stream), so setting up or releasing one system never synchronises the whole
+// device while other systems run on other streams.
 hipStream_t &alloc_stream();
 void ensure_pool();
 
@@ -73,33 +74,76 @@ struct StreamScope {
     ~StreamScope() { alloc_stream() = prev; }
 };
 
+// The allocator in force when a buffer was allocated (alloc == NULL: the default
+// hipMallocAsync / hipFreeAsync); a buffer is always freed by the allocator that
+// made it, whatever hec_set_allocator says by then.
+struct Allocator {
+    hec_alloc_fn alloc = nullptr;
+    hec_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+Allocator current_allocator();
+void *dev_alloc(size_t bytes, hipStream_t s, const Allocator &a);  // throws NOMEM on failure
+void dev_free(void *p, size_t bytes, hipStream_t s, const Allocator &a);
+
+// The byte counter of the handle that owns the buffers the calling thread
+// allocates (set by OwnerScope; NULL: nobody counts them). hec_footprint reports
+// these counters.
+int64_t *&alloc_owner();
+
+struct OwnerScope {
+    int64_t *prev;
+    explicit OwnerScope(int64_t *owner) : prev(alloc_owner()) { alloc_owner() = owner; }
+    ~OwnerScope() { alloc_owner() = prev; }
+};
+
 // Owning device buffer, allocated and freed in order on the stream that was
-// current when it was allocated.
+// current when it was allocated, by the allocator current then; its bytes count
+// towards the owner that was current then.
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
     hipStream_t st = nullptr;
+    Allocator al;
+    int64_t *owner = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), st(o.st) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), st(o.st), al(o.al), owner(o.owner) {
+        o.p = nullptr;
+        o.n = 0;
+        o.owner = nullptr;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; st = o.st; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; st = o.st; al = o.al; owner = o.owner;
+            o.p = nullptr; o.n = 0; o.owner = nullptr;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
-        n = count;
         st = alloc_stream();
-        if (count) HEC_HIP(hipMallocAsync((void **)&p, count * sizeof(T), st));
+        al = current_allocator();
+        if (count) {
+            p = (T *)dev_alloc(count * sizeof(T), st, al);
+            n = count;
+            owner = alloc_owner();
+            if (owner) *owner += (int64_t)(count * sizeof(T));
+        }
     }
     void release() {
-        if (p) (void)hipFreeAsync(p, st);
+        if (p) {
+            dev_free(p, n * sizeof(T), st, al);
+            if (owner) *owner -= (int64_t)(n * sizeof(T));
+        }
         p = nullptr;
         n = 0;
+        owner = nullptr;
     }
     void upload(const T *h, size_t count, hipStream_t s) {
         if (count) HEC_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
@@ -132,6 +176,7 @@ struct KrylovWSDeleter {
 }  // namespace hec
 
 struct hec_matrix_s {
+    int64_t dev_bytes = 0;    // device bytes held by the matrix (its solver workspace included)
     int32_t n = 0, K = 0, ld = 0;
     int64_t nnz = 0, nnz_rem = 0;
     int32_t n_rem_rows = 0;   // rows with a nonempty remainder of fewer than 1024 entries
@@ -166,6 +211,7 @@ std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *
 }  // namespace hec
 
 struct hec_ilu_s {
+    int64_t dev_bytes = 0;  // device bytes held by the factor
     int32_t n = 0, k = 0;   // n: size of the factor (the stacked extended blocks for RAS)
     // restricted additive Schwarz (Sec. 2.5): system size, blocks of the stacked factor
     // (rows hblocks[b] .. hblocks[b+1]-1), the system row of each stacked row, and the
@@ -227,6 +273,7 @@ struct hec_tri {
 };
 
 struct hec_levels_s {
+    int64_t dev_bytes = 0;  // device bytes held by the schedules, plans and solve scratch
     int32_t n = 0;    // system size (vectors the caller passes)
     int32_t nf = 0;   // factor size (the stacked extended blocks for RAS)
     bool ras = false;

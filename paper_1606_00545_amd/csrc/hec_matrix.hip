@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "hec_internal.hpp"
 
@@ -22,6 +23,41 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 hipStream_t &alloc_stream() {
     thread_local hipStream_t s = nullptr;
     return s;
+}
+
+int64_t *&alloc_owner() {
+    thread_local int64_t *o = nullptr;
+    return o;
+}
+
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_alloc;  // alloc == NULL: hipMallocAsync / hipFreeAsync
+}  // namespace
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+void *dev_alloc(size_t bytes, hipStream_t s, const Allocator &a) {
+    void *p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(a.ctx, bytes, (void *)s);
+        if (!p) fail(HEC_ERR_NOMEM, "the allocator set by hec_set_allocator returned NULL for " +
+                                        std::to_string(bytes) + " bytes");
+        return p;
+    }
+    HEC_HIP(hipMallocAsync(&p, bytes, s));
+    return p;
+}
+
+void dev_free(void *p, size_t bytes, hipStream_t s, const Allocator &a) {
+    if (!p) return;
+    if (a.alloc)
+        a.free(a.ctx, p, bytes, (void *)s);
+    else
+        (void)hipFreeAsync(p, s);
 }
 
 // Keep freed stream-ordered memory in the device pool for reuse instead of
@@ -513,6 +549,7 @@ template void spmv_launch<float, double, float>(const hec_matrix_s &, double, co
 std::unique_ptr<hec_matrix_s> make_hec(int32_t n, int32_t ncols, const int32_t *Ap, const int32_t *Aj,
                                        const double *Ax, int32_t ell_width, uint32_t flags, hipStream_t s) {
     auto A = std::make_unique<hec_matrix_s>();
+    OwnerScope own(&A->dev_bytes);
     A->n = n;
     A->nnz = Ap[n];
     int32_t maxrow = 0;
@@ -683,6 +720,24 @@ hec_status hec_spmv(hec_matrix A, hec_dtype vals, double alpha, const void *x, h
             CASE(1, 0, 1, float, double, float)
 #undef CASE
         }
+    });
+}
+
+hec_status hec_set_allocator(hec_alloc_fn alloc, hec_free_fn free_fn, void *ctx) {
+    return guarded([&] {
+        if ((alloc == nullptr) != (free_fn == nullptr))
+            fail(HEC_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_alloc.alloc = alloc;
+        g_alloc.free = free_fn;
+        g_alloc.ctx = alloc ? ctx : nullptr;
+    });
+}
+
+hec_status hec_footprint(hec_matrix A, hec_ilu M, hec_levels lv, int64_t *bytes) {
+    return guarded([&] {
+        if (!bytes) fail(HEC_ERR_INVALID_ARG, "bytes is NULL");
+        *bytes = (A ? A->dev_bytes : 0) + (M ? M->dev_bytes : 0) + (lv ? lv->dev_bytes : 0);
     });
 }
 

@@ -120,6 +120,7 @@ using namespace hec;
 static std::unique_ptr<hec_ilu_s> factor_csr(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax,
                                             int32_t k, uint32_t flags, hipStream_t s) {
     auto M = std::make_unique<hec_ilu_s>();
+    OwnerScope own(&M->dev_bytes);
     M->n = n;
     M->k = k;
     M->has_f32 = (flags & HEC_KEEP_F32) != 0;
@@ -353,6 +354,7 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
         auto lv = std::make_unique<hec_levels_s>();
+        OwnerScope own(&lv->dev_bytes);
         lv->n = M->n_sys;
         lv->nf = M->n;
         lv->ras = !M->hext_row.empty();

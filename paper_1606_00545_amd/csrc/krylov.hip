@@ -745,6 +745,14 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *z, double
 static std::mutex g_flag_mu;
 static std::vector<int32_t *> g_flag_pool;
 
+// A pooled block of mapped pinned memory: the SI_COUNT flags at offset 0, then at
+// kScalarsOffset bytes the host copy of the SD_SCALARS scalars (one read per GMRES
+// cycle). Blocks are never freed, only recycled (freeing pinned host memory can
+// synchronise the whole device).
+constexpr size_t kScalarsOffset = 64;
+constexpr size_t kFlagBlockBytes = kScalarsOffset + SD_SCALARS * sizeof(double);
+static_assert(SI_COUNT * sizeof(int32_t) <= kScalarsOffset, "flags overlap the scalars");
+
 static int32_t *take_flags() {
     {
         std::lock_guard<std::mutex> lk(g_flag_mu);
@@ -755,7 +763,7 @@ static int32_t *take_flags() {
         }
     }
     int32_t *p = nullptr;
-    HEC_HIP(hipHostMalloc((void **)&p, SI_COUNT * sizeof(int32_t), hipHostMallocMapped));
+    HEC_HIP(hipHostMalloc((void **)&p, kFlagBlockBytes, hipHostMallocMapped));
     return p;
 }
 
@@ -778,12 +786,11 @@ struct KrylovWS {
     DevBuf<double> part;         // partial sums, nred x kMaxRestart
     int32_t *hflags = nullptr;   // mapped pinned mirror of si
     int32_t *dflags = nullptr;   // its device address
-    double *hsd = nullptr;       // pinned host copy of the scalars (one read per GMRES cycle)
+    double *hsd = nullptr;       // pinned host copy of the scalars, in the same pooled block
     std::vector<hipEvent_t> ev;
     ~KrylovWS() {
         for (auto e : ev) (void)hipEventDestroy(e);
         if (hflags) give_flags(hflags);
-        if (hsd) (void)hipHostFree(hsd);
     }
 };
 
@@ -797,6 +804,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     bool mx = mixed || (w && w->mixed);
     bool bc = bicg || (w && w->bicg);
     A.ws.reset();
+    OwnerScope own(&A.dev_bytes);  // the workspace counts towards the matrix's footprint
     auto nw = std::unique_ptr<KrylovWS, KrylovWSDeleter>(new KrylovWS());
     nw->n = A.n;
     nw->ldv = ((int64_t)A.n + 63) / 64 * 64 + HEC_BASIS_PAD;
@@ -823,8 +831,8 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     nw->part.alloc((size_t)nw->nred * (kMaxRestart + 1));
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
     nw->hflags = take_flags();
-    HEC_HIP(hipHostMalloc((void **)&nw->hsd, SD_SCALARS * sizeof(double), hipHostMallocDefault));
-    std::memset(nw->hflags, 0, SI_COUNT * sizeof(int32_t));
+    nw->hsd = (double *)((char *)nw->hflags + kScalarsOffset);
+    std::memset(nw->hflags, 0, kFlagBlockBytes);
     HEC_HIP(hipHostGetDevicePointer((void **)&nw->dflags, nw->hflags, 0));
     nw->ev.resize(kMaxRestart + 2);
     for (auto &e : nw->ev) HEC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1059,10 +1067,11 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
         }
         set_scalar(ws, SD_TOL, o->rtol * bnorm, s);
         double res = true_residual(*A, ws, b, x, s);
-        int it = 0, restarts = 0;
+        int it = 0, cycles = 0;  // a cycle starts from the current x with a new shadow residual
         bool broke = false;
         const unsigned g = ceil_div(n, 256);
-        while (res / bnorm > o->rtol && it < o->maxit && restarts <= 3) {
+        while (res / bnorm > o->rtol && it < o->maxit && cycles < 4) {
+            ++cycles;
             OpBiStart bs{{}, r, r0, sd, si, ws.dflags};
             launch_pass<1>(ws, n, bs, 1, s, nullptr);
             HEC_HIP(hipStreamSynchronize(s));
@@ -1095,10 +1104,9 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
             }
             inf.rel_res_est = std::sqrt(std::min(read_scalar(ws, SD_RNORM2, s), read_scalar(ws, SD_SNORM2, s))) / bnorm;
             res = true_residual(*A, ws, b, x, s);
-            if (res / bnorm > o->rtol) ++restarts;
         }
         inf.iterations = it;
-        inf.restarts = restarts;
+        inf.restarts = std::max(0, cycles - 1);
         inf.rel_res_true = res / bnorm;
         if (!(res / bnorm <= o->rtol)) {
             if (broke) fail(HEC_ERR_BREAKDOWN, "BiCGSTAB breakdown (rho or (r0,v) == 0)");

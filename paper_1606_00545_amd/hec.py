@@ -29,7 +29,8 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "level_schedule", "levels_info", "levels_export", "levels_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve", "cg_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched",
-            "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy", "hec_last_error")
+            "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy",
+            "hec_set_allocator", "hec_footprint", "hec_last_error")
 BATCH_MAX_N = 8192
 
 
@@ -107,11 +108,74 @@ def load(path: str = LIB_PATH):
     L.amg_export_level.argtypes = [_vp, C.c_int32] + [_vp] * 7
     L.amg_solve.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_double, _vp, C.POINTER(SolveInfo)]
     L.amg_destroy.argtypes = [_vp]
+    L.hec_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, _vp]
+    L.hec_footprint.argtypes = [_vp, _vp, _vp, _i64p]
     for name in EXPORTED:
         if name != "hec_last_error":
             getattr(L, name).restype = C.c_int
     _lib = L
+    use_torch_allocator()
     return L
+
+
+# ---------------------------------------------------------------- device memory
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_hooks = None  # the ctypes callbacks in force (kept alive while the library may call them)
+
+
+def set_allocator(alloc=None, free=None):
+    """hec_set_allocator: `alloc(nbytes, stream) -> int` (0 on failure) and `free(ptr, nbytes,
+    stream)` serve every device buffer the library allocates from now on; None, None restores
+    the library's default (hipMallocAsync / hipFreeAsync)."""
+    global _hooks
+    L = load()
+    if alloc is None and free is None:
+        _check(L.hec_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "hec_set_allocator")
+        _hooks = None
+        return
+
+    def _a(ctx, nbytes, stream):
+        try:
+            return alloc(int(nbytes), int(stream or 0)) or None
+        except Exception:
+            return None
+
+    def _f(ctx, ptr, nbytes, stream):
+        free(int(ptr), int(nbytes), int(stream or 0))
+
+    hooks = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _check(L.hec_set_allocator(hooks[0], hooks[1], None), "hec_set_allocator")
+    _hooks = hooks  # buffers made by earlier hooks keep their own (module-level references below)
+    _all_hooks.append(hooks)
+
+
+_all_hooks = []  # every callback pair ever set: buffers are freed by the hooks that made them
+
+
+def _torch_alloc(nbytes, stream):
+    import torch
+    return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+
+def _torch_free(ptr, nbytes, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+def use_torch_allocator():
+    """Route the library's device memory through torch's caching allocator."""
+    set_allocator(_torch_alloc, _torch_free)
+
+
+def footprint(A=None, M=None, lv=None) -> int:
+    """hec_footprint: device bytes held by a matrix (its solver workspace included), a
+    factor and a schedule."""
+    out = C.c_int64()
+    _check(load().hec_footprint(A.ptr if A else None, M.ptr if M else None, lv.ptr if lv else None,
+                                C.byref(out)), "hec_footprint")
+    return out.value
 
 
 def _check(code: int, where: str):
@@ -126,14 +190,19 @@ def _stream(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
-def _dev(t, dtype=None):
-    """Device pointer of a contiguous torch CUDA tensor (None -> NULL)."""
-    if t is None:
-        return None
+def _dev(t, n, dtype=None, what="vector"):
+    """Device pointer of a contiguous torch tensor of at least n elements on the current
+    device (checked here, before any library call: a short vector would make the
+    kernels read and write past its end)."""
+    import torch
     if not t.is_cuda or not t.is_contiguous():
-        raise ValueError("vectors must be contiguous CUDA tensors")
+        raise ValueError(f"{what} must be a contiguous CUDA tensor")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{what} is on {t.device}, the current device is cuda:{torch.cuda.current_device()}")
     if dtype is not None and t.dtype != dtype:
-        raise ValueError(f"expected {dtype}, got {t.dtype}")
+        raise ValueError(f"{what}: expected {dtype}, got {t.dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, the system has {n} rows")
     return t.data_ptr()
 
 
@@ -175,17 +244,39 @@ class _Handle:
 class Matrix(_Handle):
     _destroy = "hec_destroy"
 
+    def __init__(self, ptr):
+        super().__init__(ptr)
+        n = C.c_int32()
+        _check(load().hec_info(ptr, C.byref(n), None, None, None, None), "hec_info")
+        self.n = n.value
+
 
 class Factor(_Handle):
     _destroy = "ilu_destroy"
+
+    def __init__(self, ptr):
+        super().__init__(ptr)
+        n_sys = C.c_int32()
+        _check(load().ilu_ras_export(ptr, C.byref(n_sys), None, None, None, None), "ilu_ras_export")
+        self.n = n_sys.value  # the system size (rows of the vectors it is applied to)
 
 
 class Levels(_Handle):
     _destroy = "levels_destroy"
 
+    def __init__(self, ptr):
+        super().__init__(ptr)
+        n = C.c_int32()
+        _check(load().levels_info(ptr, C.byref(n), None, None), "levels_info")
+        self.n = n.value
+
 
 class Amg(_Handle):
     _destroy = "amg_destroy"
+
+    def __init__(self, ptr):
+        super().__init__(ptr)
+        self.n = amg_info(self)["n"][0]
 
 
 class Batch(_Handle):
@@ -245,8 +336,8 @@ def hec_export(M: Matrix, f32: bool = False) -> dict:
 
 def hec_spmv(M: Matrix, x, y, alpha: float = 1.0, beta: float = 0.0, vals: int = F64, stream=None):
     """y = alpha*A*x + beta*y on the device (asynchronous on the stream)."""
-    _check(load().hec_spmv(M.ptr, vals, alpha, _dev(x), _dtype_code(x), beta, _dev(y), _dtype_code(y),
-                           _stream(stream)), "hec_spmv")
+    _check(load().hec_spmv(M.ptr, vals, alpha, _dev(x, M.n, what="x"), _dtype_code(x), beta,
+                           _dev(y, M.n, what="y"), _dtype_code(y), _stream(stream)), "hec_spmv")
     return y
 
 
@@ -324,7 +415,8 @@ def trsv_levels(M: Factor, lv: Levels, b, x, which: int = LU, stream=None):
     prec = _dtype_code(b)
     if _dtype_code(x) != prec:
         raise ValueError("b and x must have the same dtype")
-    _check(load().trsv_levels(M.ptr, lv.ptr, which, prec, _dev(b), _dev(x), _stream(stream)), "trsv_levels")
+    _check(load().trsv_levels(M.ptr, lv.ptr, which, prec, _dev(b, lv.n, what="b"), _dev(x, lv.n, what="x"),
+                              _stream(stream)), "trsv_levels")
     return x
 
 
@@ -340,7 +432,7 @@ def gmres_solve(A: Matrix, M: Factor, lv: Levels, b, x, restart: int = 30, maxit
     import torch
     o = _opts(restart, maxit, rtol, precision, x0_zero, ir_rtol, inner_rtol)
     info = SolveInfo()
-    code = load().gmres_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+    code = load().gmres_solve(A.ptr, M.ptr, lv.ptr, _dev(b, A.n, torch.float64, "b"), _dev(x, A.n, torch.float64, "x"),
                               C.byref(o), C.byref(info), _stream(stream))
     if check and code != OK:
         _check(code, "gmres_solve")
@@ -352,7 +444,7 @@ def bicgstab_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, r
     import torch
     o = _opts(1, maxit, rtol, 0, x0_zero, 0.0, 0.0)
     info = SolveInfo()
-    code = load().bicgstab_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+    code = load().bicgstab_solve(A.ptr, M.ptr, lv.ptr, _dev(b, A.n, torch.float64, "b"), _dev(x, A.n, torch.float64, "x"),
                                  C.byref(o), C.byref(info), _stream(stream))
     if check and code != OK:
         _check(code, "bicgstab_solve")
@@ -364,7 +456,7 @@ def cg_solve(A: Matrix, M: Factor, lv: Levels, b, x, maxit: int = 10000, rtol: f
     import torch
     o = _opts(1, maxit, rtol, 0, x0_zero, 0.0, 0.0)
     info = SolveInfo()
-    code = load().cg_solve(A.ptr, M.ptr, lv.ptr, _dev(b, torch.float64), _dev(x, torch.float64),
+    code = load().cg_solve(A.ptr, M.ptr, lv.ptr, _dev(b, A.n, torch.float64, "b"), _dev(x, A.n, torch.float64, "x"),
                            C.byref(o), C.byref(info), _stream(stream))
     if check and code != OK:
         _check(code, "cg_solve")
@@ -382,8 +474,8 @@ def gmres_solve_batched(B: Batch, systems, maxit: int = 10000, rtol: float = 1e-
     A = arr([s[0].ptr for s in systems])
     M = arr([s[1].ptr for s in systems])
     lv = arr([s[2].ptr for s in systems])
-    b = arr([_dev(s[3], torch.float64) for s in systems])
-    x = arr([_dev(s[4], torch.float64) for s in systems])
+    b = arr([_dev(s[3], s[0].n, torch.float64, "b") for s in systems])
+    x = arr([_dev(s[4], s[0].n, torch.float64, "x") for s in systems])
     infos = (SolveInfo * max(1, count))()
     code = load().gmres_solve_batched(B.ptr, count, A, M, lv, b, x, C.byref(o), infos, _stream(stream))
     if check and code != OK:
@@ -433,7 +525,8 @@ def amg_export_level(H: Amg, level: int) -> dict:
 def amg_solve(H: Amg, b, x, maxit: int = 100, rtol: float = 1e-8, stream=None, check: bool = True) -> dict:
     import torch
     info = SolveInfo()
-    code = load().amg_solve(H.ptr, _dev(b, torch.float64), _dev(x, torch.float64), maxit, rtol, _stream(stream),
+    code = load().amg_solve(H.ptr, _dev(b, H.n, torch.float64, "b"), _dev(x, H.n, torch.float64, "x"), maxit, rtol,
+                            _stream(stream),
                             C.byref(info))
     if check and code != OK:
         _check(code, "amg_solve")

@@ -18,6 +18,7 @@ def _declared():
         if fn.endswith(".h"):
             src = open(os.path.join(ROOT, "include", fn)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            src = re.sub(r"^\s*typedef[^;]*;", "", src, flags=re.M)  # function-pointer types
             names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M))
     return names
 
@@ -74,3 +75,28 @@ def test_bad_arguments():
     assert L.trsv_levels(None, None, 3, 0, None, None, None) == hec.INVALID_ARG
     assert L.gmres_solve(None, None, None, None, None, None, None, None) == hec.INVALID_ARG
     assert b"null" in L.hec_last_error()
+
+
+def test_device_memory_only_through_the_allocator_hooks():
+    """Every device allocation of the library goes through dev_alloc / dev_free (which call the
+    hooks of hec_set_allocator, or hipMallocAsync / hipFreeAsync by default): no other call
+    site allocates or frees device memory."""
+    csrc = os.path.join(ROOT, "paper_1606_00545_amd", "csrc")
+    calls = {}
+    for fn in sorted(os.listdir(csrc)):
+        src = open(os.path.join(csrc, fn)).read()
+        src = re.sub(r"//[^\n]*", "", src)
+        for api in ("hipMalloc", "hipMallocAsync", "hipMallocManaged", "hipExtMallocWithFlags", "hipMallocPitch",
+                    "hipFree", "hipFreeAsync", "hipMallocFromPoolAsync"):
+            k = len(re.findall(rf"\b{api}\s*\(", src))
+            if k:
+                calls[(fn, api)] = k
+    assert calls == {("hec_matrix.hip", "hipMallocAsync"): 1, ("hec_matrix.hip", "hipFreeAsync"): 1}
+
+
+def test_set_allocator_rejects_a_single_hook():
+    L = hec.load()
+    code = L.hec_set_allocator(hec._ALLOC_FN(lambda c, n, s: None), hec._FREE_FN(), None)
+    assert code == hec.INVALID_ARG
+    hec.set_allocator(None, None)  # the library default
+    hec.use_torch_allocator()      # the binding's default
