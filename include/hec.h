@@ -314,6 +314,9 @@ typedef struct {
     int32_t nu1, nu2;    /* pre- and post-smoothing sweeps; 0..64 (3 and 3, as Sec. 3.3) */
     int32_t use_graph;   /* 1: record one cycle into a HIP graph at the first solve and replay it;
                             0: launch the kernels of every cycle (1) */
+    int32_t smoother;    /* 0: damped Jacobi (omega); 1: Chebyshev polynomial, nu1 / nu2 its degree (0) */
+    double cheb_lower;   /* Chebyshev: the smoothed interval of D^{-1} A's spectrum is
+                            [cheb_lower * lmax, lmax], lmax = max_i sum_j |a_ij| / |a_ii|; in (0, 1) (0.3) */
 } hec_amg_opts;
 
 /* Sec. 2.8: AMG setup on the host for the n x n CSR matrix (Ap, Aj, Ax: host
@@ -341,10 +344,14 @@ hec_status amg_info(hec_amg H, int32_t *nlevels, int32_t *n, int64_t *nnz, int64
 hec_status amg_export_level(hec_amg H, int32_t level, int8_t *cf, int32_t *Ap, int32_t *Aj, double *Ax,
                             int32_t *Pp, int32_t *Pj, double *Px);
 
-/* Alg. 5: x = 0, then V-cycles (nu1 damped Jacobi sweeps, residual restricted by
+/* Alg. 5: x = 0, then V-cycles (nu1 smoothing sweeps, residual restricted by
  * R, coarse correction from zero, prolongated by P and added, nu2 sweeps; the
  * coarsest level solved with its inverse) until ||b - A x|| <= rtol ||b|| in FP64
- * or maxit cycles. b, x: device FP64 vectors of n elements, not overlapping. The
+ * or maxit cycles. Smoothers (Sec. 2.8): damped Jacobi, x += omega D^{-1} (b - A x)
+ * per sweep; or Chebyshev, the Chebyshev semi-iteration on D^{-1} A over
+ * [cheb_lower * lmax, lmax] (error multiplied by T_nu((theta - t) / delta) /
+ * T_nu(theta / delta), theta and delta the interval's midpoint and half-width), one
+ * product with A per sweep. b, x: device FP64 vectors of n elements, not overlapping. The
  * calls of one handle must not overlap in time (its per-level vectors are
  * shared). The handle runs the cycles on a stream of its own, ordered after the
  * caller's stream on entry and before it on return. Returns NOT_CONVERGED after maxit cycles (x holds the last iterate),

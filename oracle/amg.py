@@ -29,7 +29,20 @@ benchmark's CPU leg use it; it shares no code with the GPU library.
   has at most coarse_size rows, max_levels levels exist, or coarsening stops (no C
   point, or no reduction); the coarsest level is solved exactly.
 * vcycle / solve: Alg. 5 with damped Jacobi pre- and post-smoothing,
-  x <- x + omega D^{-1} (b - A x), nu1 and nu2 sweeps.
+  x <- x + omega D^{-1} (b - A x), nu1 and nu2 sweeps; or with the Chebyshev
+  polynomial smoother that Sec. 2.8 and the AMG tables list beside the Jacobi
+  ones ("Chev"). The paper gives no detail of it; the reading taken here is the
+  textbook Chebyshev semi-iteration (Saad, Iterative Methods for Sparse Linear
+  Systems, Sec. 12.1) on D^{-1} A over the interval [a, b] = [cheb_lower * lmax,
+  lmax], lmax = max_i sum_j |a_ij| / |a_ii| (Gershgorin's bound on the spectrum of
+  D^{-1} A): nu sweeps give x = x0 + q(D^{-1} A) D^{-1} r0 whose error is
+  p_nu(D^{-1} A) e0 with p_nu(t) = T_nu((theta - t) / delta) / T_nu(theta / delta),
+  theta = (b + a) / 2, delta = (b - a) / 2 -- the polynomial of degree nu that is
+  smallest on [a, b] among those with p(0) = 1 -- by the three-term recurrence:
+  z = D^{-1} (b - A x), d = z / theta, then nu times: x += d, z -= D^{-1} A d,
+  rho' = 1 / (2 theta / delta - rho) (rho starting at delta / theta),
+  d = rho' rho d + (2 rho' / delta) z, rho = rho'. Each sweep costs one product
+  with A, as a Jacobi sweep does.
 """
 from __future__ import annotations
 
@@ -176,12 +189,29 @@ def galerkin(M: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
     return sp.csr_matrix((np.array(Cx), np.array(Cj, np.int64), np.array(Cp, np.int64)), shape=(nc, nc))
 
 
+def gershgorin_dinv_a(M: sp.csr_matrix) -> float:
+    """max_i sum_j |a_ij| / |a_ii|: every eigenvalue of D^{-1} A lies in a disc around 1
+    of radius sum_{j != i} |a_ij| / |a_ii| for some row i (Gershgorin), so this bounds
+    its spectral radius. Row sums in column order."""
+    lmax = 0.0
+    for i in range(M.shape[0]):
+        s, d = 0.0, 0.0
+        for e in range(M.indptr[i], M.indptr[i + 1]):
+            v = float(M.data[e])
+            s += abs(v)
+            if M.indices[e] == i:
+                d = v
+        lmax = max(lmax, s / abs(d))
+    return lmax
+
+
 @dataclass
 class Level:
     A: sp.csr_matrix
     cf: np.ndarray = None
     P: sp.csr_matrix = None
     dinv: np.ndarray = field(default=None)
+    lmax: float = 0.0  # Gershgorin bound of D^{-1} A (Chebyshev smoothing only)
 
 
 @dataclass
@@ -190,13 +220,19 @@ class Hierarchy:
     omega: float
     nu1: int
     nu2: int
+    smoother: str = "jacobi"
+    cheb_lower: float = 0.3
 
 
-def hierarchy(A, theta=0.25, max_levels=8, coarse_size=64, omega=2.0 / 3.0, nu1=3, nu2=3) -> Hierarchy:
+def hierarchy(A, theta=0.25, max_levels=8, coarse_size=64, omega=2.0 / 3.0, nu1=3, nu2=3, smoother="jacobi",
+              cheb_lower=0.3) -> Hierarchy:
+    assert smoother in ("jacobi", "chebyshev")
     M = _csr(A)
     levels = []
     while True:
         lev = Level(M, dinv=1.0 / M.diagonal())
+        if smoother == "chebyshev":
+            lev.lmax = gershgorin_dinv_a(M)
         levels.append(lev)
         n = M.shape[0]
         if n <= coarse_size or len(levels) == max_levels:
@@ -209,13 +245,43 @@ def hierarchy(A, theta=0.25, max_levels=8, coarse_size=64, omega=2.0 / 3.0, nu1=
         P = direct_interpolation(M, Sp, Sj, cf, theta)
         lev.cf, lev.P = cf, P
         M = galerkin(M, P)
-    return Hierarchy(levels, omega, nu1, nu2)
+    return Hierarchy(levels, omega, nu1, nu2, smoother, cheb_lower)
 
 
 def _jacobi(lev: Level, x, b, omega, sweeps):
     for _ in range(sweeps):
         x = x + omega * lev.dinv * (b - lev.A @ x)
     return x
+
+
+def chebyshev(A, dinv, lmax, x, b, degree, cheb_lower=0.3):
+    """`degree` sweeps of the Chebyshev smoother on [cheb_lower * lmax, lmax] (the
+    recurrence in the module docstring), from x."""
+    if degree == 0:
+        return x
+    hi = lmax
+    lo = cheb_lower * lmax
+    theta = (hi + lo) / 2.0
+    delta = (hi - lo) / 2.0
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    z = dinv * (b - A @ x)
+    d = z / theta
+    for k in range(degree):
+        x = x + d
+        if k == degree - 1:
+            break
+        z = z - dinv * (A @ d)
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = (rho_new * rho) * d + (2.0 * rho_new / delta) * z
+        rho = rho_new
+    return x
+
+
+def _smooth(H: Hierarchy, lev: Level, x, b, sweeps):
+    if H.smoother == "chebyshev":
+        return chebyshev(lev.A, lev.dinv, lev.lmax, x, b, sweeps, H.cheb_lower)
+    return _jacobi(lev, x, b, H.omega, sweeps)
 
 
 def vcycle(H: Hierarchy, b, x=None, l=0):
@@ -225,11 +291,11 @@ def vcycle(H: Hierarchy, b, x=None, l=0):
     if l == len(H.levels) - 1:
         return np.linalg.solve(lev.A.toarray(), b)
     x = np.zeros_like(b) if x is None else x
-    x = _jacobi(lev, x, b, H.omega, H.nu1)
+    x = _smooth(H, lev, x, b, H.nu1)
     r = b - lev.A @ x
     xc = vcycle(H, lev.P.T @ r, None, l + 1)
     x = x + lev.P @ xc
-    return _jacobi(lev, x, b, H.omega, H.nu2)
+    return _smooth(H, lev, x, b, H.nu2)
 
 
 @dataclass

@@ -26,6 +26,12 @@
 // Solve: x = 0, then V-cycles (Alg. 5) until ||b - A x|| <= rtol ||b||: nu1
 // damped Jacobi sweeps x += omega D^{-1} (b - A x), the residual restricted with
 // R, the coarse correction (from zero) prolongated with P and added, nu2 sweeps.
+// The other smoother is the Chebyshev polynomial one of Sec. 2.8 ("Chev"), read
+// as the Chebyshev semi-iteration on D^{-1} A over [cheb_lower * lmax, lmax] with
+// lmax the Gershgorin bound max_i sum_j |a_ij| / |a_ii| (computed on the host per
+// level): z = D^{-1} (b - A x), d = z / theta, then per sweep x += d and, before
+// the next, z -= D^{-1} A d and d = c1 d + c2 z with the recurrence's coefficients
+// (host scalars, the same for every cycle); one product with A per sweep.
 // A level whose rows are of about the same length (plain ELL wastes at most 30%
 // of its slab) is stored as plain ELL, so that one launch does a whole sweep
 // (the residual and the update, into a second vector); other levels keep the
@@ -244,6 +250,41 @@ Csr galerkin(const Csr &A, const Csr &P, const Csr &R) {
 #pragma clang fp contract(on)
 
 // Inverse of a small dense matrix (row-major), Gauss-Jordan with partial pivoting.
+// max_i sum_j |a_ij| / |a_ii|, the row sums in column order: Gershgorin's bound on
+// the spectral radius of D^{-1} A (every eigenvalue lies within sum_{j != i}
+// |a_ij| / |a_ii| of 1 for some row i).
+double gershgorin_dinv_a(const Csr &A) {
+    double lmax = 0.0;
+    for (int32_t i = 0; i < A.n; ++i) {
+        double s = 0.0, d = 0.0;
+        for (int32_t e = A.p[i]; e < A.p[i + 1]; ++e) {
+            s += std::fabs(A.x[e]);
+            if (A.j[e] == i) d = A.x[e];
+        }
+        lmax = std::max(lmax, s / std::fabs(d));
+    }
+    return lmax;
+}
+
+// Coefficients of the Chebyshev smoother on [lo_frac * lmax, lmax] for `degree`
+// sweeps: theta, then (c1, c2) of sweeps 2..degree (d = c1 d + c2 z).
+void chebyshev_coefficients(double lmax, double lo_frac, int degree, double &theta, std::vector<double> &c1,
+                            std::vector<double> &c2) {
+    const double hi = lmax, lo = lo_frac * lmax;
+    theta = (hi + lo) / 2.0;
+    const double delta = (hi - lo) / 2.0;
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    c1.clear();
+    c2.clear();
+    for (int k = 1; k < degree; ++k) {
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        c1.push_back(rho_new * rho);
+        c2.push_back(2.0 * rho_new / delta);
+        rho = rho_new;
+    }
+}
+
 std::vector<double> dense_inverse(const Csr &A) {
     const int32_t n = A.n;
     std::vector<double> a((size_t)n * n, 0.0), inv((size_t)n * n, 0.0);
@@ -310,6 +351,33 @@ __global__ __launch_bounds__(256) void k_jacobi_first(int32_t n, double omega, c
     if (i < n) x[i] = omega * dinv[i] * b[i];
 }
 
+// First Chebyshev sweep: z = D^{-1} r (r = b - A x, or b from a zero iterate),
+// d = z / theta, x += d (x = d from a zero iterate). r may be z.
+__global__ __launch_bounds__(256) void k_cheb_first(int32_t n, double theta, const double *__restrict__ dinv,
+                                                    const double *r, double *z, double *__restrict__ d,
+                                                    double *__restrict__ x, int32_t zero_start) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double zi = dinv[i] * r[i];
+    z[i] = zi;
+    const double di = zi / theta;
+    d[i] = di;
+    x[i] = zero_start ? di : x[i] + di;
+}
+
+// Later Chebyshev sweeps, with w = A d: z -= D^{-1} w, d = c1 d + c2 z, x += d.
+__global__ __launch_bounds__(256) void k_cheb_step(int32_t n, double c1, double c2, const double *__restrict__ dinv,
+                                                   const double *__restrict__ w, double *__restrict__ z,
+                                                   double *__restrict__ d, double *__restrict__ x) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double zi = z[i] - dinv[i] * w[i];
+    z[i] = zi;
+    const double di = c1 * d[i] + c2 * zi;
+    d[i] = di;
+    x[i] += di;
+}
+
 __global__ __launch_bounds__(256) void k_copy(int32_t n, const double *__restrict__ a, double *__restrict__ b) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -359,6 +427,11 @@ struct hec_amg_level {
     bool fused = false;
     std::unique_ptr<hec_matrix_s> dP, dR;
     DevBuf<double> dinv, x, y, b, r;     // x, y: the iterate and the other buffer of a sweep
+    // Chebyshev smoothing: the Gershgorin bound of D^{-1} A, the sweep coefficients for
+    // nu1 and nu2 sweeps, and the product A d (the direction d lives in y, z in r)
+    double lmax = 0.0, theta = 0.0;
+    std::vector<double> c1_pre, c2_pre, c1_post, c2_post;
+    DevBuf<double> t;
 };
 
 struct hec_amg_s {
@@ -436,6 +509,26 @@ void smooth(hec_amg_level &L, double omega, int sweeps, double *&cur, const doub
     }
 }
 
+// `sweeps` Chebyshev sweeps on the iterate *cur (which stays where it is; the
+// direction goes to the level's other vector, z to r, A d to t). zero_start: the
+// iterate is zero, so the first residual is b (no product).
+void smooth_cheb(hec_amg_level &L, int sweeps, const std::vector<double> &c1, const std::vector<double> &c2,
+                 double *cur, const double *b, hipStream_t s, bool zero_start = false) {
+    if (sweeps == 0) return;
+    const hec_matrix_s &M = *L.dA;
+    const unsigned g = ceil_div(M.n, 256);
+    double *d = cur == L.x.get() ? L.y.get() : L.x.get();
+    if (!zero_start) spmv(M, -1.0, cur, 1.0, b, L.r.get(), s);  // r = b - A x
+    k_cheb_first<<<g, 256, 0, s>>>(M.n, L.theta, L.dinv.get(), zero_start ? b : L.r.get(), L.r.get(), d, cur,
+                                   zero_start ? 1 : 0);
+    HEC_CHECK_LAUNCH();
+    for (int k = 1; k < sweeps; ++k) {
+        spmv(M, 1.0, d, 0.0, L.t.get(), L.t.get(), s);  // t = A d
+        k_cheb_step<<<g, 256, 0, s>>>(M.n, c1[k - 1], c2[k - 1], L.dinv.get(), L.t.get(), L.r.get(), d, cur);
+        HEC_CHECK_LAUNCH();
+    }
+}
+
 // Alg. 5 from level l (iterate in L.x, right-hand side in L.b); returns the buffer
 // holding the result.
 double *vcycle(hec_amg_s &H, size_t l, hipStream_t s) {
@@ -445,8 +538,12 @@ double *vcycle(hec_amg_s &H, size_t l, hipStream_t s) {
         return L.x.get();
     }
     const hec_amg_opts &o = H.opts;
+    const bool cheb = o.smoother == 1;
     double *cur = L.x.get();
-    smooth(L, o.omega, o.nu1, cur, L.b.get(), s, l > 0);  // below level 0 the iterate starts at zero
+    if (cheb)
+        smooth_cheb(L, o.nu1, L.c1_pre, L.c2_pre, cur, L.b.get(), s, l > 0);
+    else
+        smooth(L, o.omega, o.nu1, cur, L.b.get(), s, l > 0);  // below level 0 the iterate starts at zero
     spmv(*L.dA, -1.0, cur, 1.0, L.b.get(), L.r.get(), s);  // r = b - A x
     hec_amg_level &C = *H.lev[l + 1];
     spmv(*L.dR, 1.0, L.r.get(), 0.0, L.r.get(), C.b.get(), s);  // b_{l+1} = R r
@@ -456,7 +553,10 @@ double *vcycle(hec_amg_s &H, size_t l, hipStream_t s) {
     }
     const double *xc = vcycle(H, l + 1, s);
     spmv(*L.dP, 1.0, xc, 1.0, cur, cur, s);  // x += P x_{l+1}
-    smooth(L, o.omega, o.nu2, cur, L.b.get(), s);
+    if (cheb)
+        smooth_cheb(L, o.nu2, L.c1_post, L.c2_post, cur, L.b.get(), s);
+    else
+        smooth(L, o.omega, o.nu2, cur, L.b.get(), s);
     return cur;
 }
 
@@ -484,11 +584,12 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
         *out = nullptr;
         validate_csr(n, Ap, Aj, Ax);
         if (n == 0) fail(HEC_ERR_INVALID_ARG, "empty matrix");
-        hec_amg_opts o{0.25, 8, 64, 2.0 / 3.0, 3, 3, 1};
+        hec_amg_opts o{0.25, 8, 64, 2.0 / 3.0, 3, 3, 1, 0, 0.3};
         if (opts) o = *opts;
         if (!(o.theta > 0.0 && o.theta <= 1.0) || o.max_levels < 1 || o.max_levels > 32 || o.coarse_size < 1 ||
             o.coarse_size > 4096 || !(o.omega > 0.0 && o.omega < 2.0) || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 64 ||
-            o.nu2 > 64 || (o.use_graph != 0 && o.use_graph != 1))
+            o.nu2 > 64 || (o.use_graph != 0 && o.use_graph != 1) || (o.smoother != 0 && o.smoother != 1) ||
+            !(o.cheb_lower > 0.0 && o.cheb_lower < 1.0))
             fail(HEC_ERR_INVALID_ARG, "bad AMG options");
         hipStream_t s = as_stream(stream);
         StreamScope scope(s);
@@ -520,6 +621,12 @@ hec_status amg_setup(int32_t n, const int32_t *Ap, const int32_t *Aj, const doub
             L->y.alloc(nl);
             L->b.alloc(nl);
             L->r.alloc(nl);
+            if (o.smoother == 1) {
+                L->lmax = amgs::gershgorin_dinv_a(L->A);
+                amgs::chebyshev_coefficients(L->lmax, o.cheb_lower, o.nu1, L->theta, L->c1_pre, L->c2_pre);
+                amgs::chebyshev_coefficients(L->lmax, o.cheb_lower, o.nu2, L->theta, L->c1_post, L->c2_post);
+                L->t.alloc(nl);
+            }
             const bool last = nl <= o.coarse_size || (int32_t)H->lev.size() + 1 == o.max_levels;
             amgs::Csr Ac;
             if (!last) {

@@ -626,10 +626,11 @@ struct OpBiXR : NoInit {
             si[SI_DONE] = 1;
             mirror(hf, SI_DONE, 1);
         } else if (t[1] == 0.0 || !isfinite(t[1])) {
+            // Alg. 4 tests rho at the start of the next pass: a breakdown only if that pass runs
             si[SI_DONE] = 1;
-            si[SI_BREAK] = 1;
+            si[SI_BREAK] = 2;
             mirror(hf, SI_DONE, 1);
-            mirror(hf, SI_BREAK, 1);
+            mirror(hf, SI_BREAK, 2);
         }
     }
 };
@@ -784,9 +785,11 @@ struct KrylovWS {
     DevBuf<double> sd;           // scalars + Hessenberg
     DevBuf<int32_t> si;
     DevBuf<double> part;         // partial sums, nred x kMaxRestart
-    int32_t *hflags = nullptr;   // mapped pinned mirror of si
+    int32_t *hflags = nullptr;   // mapped pinned mirror of si (NULL: none; flags are copied to hsi)
     int32_t *dflags = nullptr;   // its device address
-    double *hsd = nullptr;       // pinned host copy of the scalars, in the same pooled block
+    double *hsd = nullptr;       // host copy of the scalars: in the pooled pinned block, or hsd_plain
+    int32_t hsi[SI_COUNT] = {};  // host copy of si when there are no mapped flags
+    double hsd_plain[SD_SCALARS] = {};
     std::vector<hipEvent_t> ev;
     ~KrylovWS() {
         for (auto e : ev) (void)hipEventDestroy(e);
@@ -883,7 +886,7 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
         // look two iterations behind, every other iteration: stop issuing work once the
         // device is done. An event record costs the stream about 6 us (it waits for the
         // previous kernel and flushes to system scope), so only odd steps record one.
-        if (j >= 3 && (j & 1)) {
+        if (j >= 3 && (j & 1) && ws.hflags) {  // (without mapped flags every step is queued)
             HEC_HIP(hipEventSynchronize(ws.ev[j - 1]));
             if (hf(ws)[SI_DONE]) break;
         }
@@ -906,7 +909,7 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
             k_finish_scale<VT><<<gs, RB, 0, s>>>(n, w, vnext, part, g, nv, done, sd, si, ws.dflags, L);
             HEC_CHECK_LAUNCH();
         }
-        if (j & 1) HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
+        if ((j & 1) && ws.hflags) HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
     }
     k_backsolve<<<1, 64, 0, s>>>(sd, si, L);
     HEC_CHECK_LAUNCH();
@@ -964,6 +967,65 @@ static void check_solve_args(hec_matrix A, hec_ilu M, hec_levels lv, const doubl
     if (o->precision != 0 && o->precision != 1) fail(HEC_ERR_INVALID_ARG, "precision must be 0 or 1");
 }
 
+// The restarted GMRES driver on a prepared workspace: x0, the FP64 true residual, then
+// cycles (FP64, or FP32 inner solves inside FP64 refinement) until the target or maxit.
+static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const double *b, double *x,
+                      const hec_solve_opts *o, hec_solve_info &inf, hipStream_t s) {
+    const int64_t n = A.n;
+    const bool mixed = o->precision == 1;
+    const double bnorm = vec_norm(ws, n, b, s);
+    if (bnorm == 0.0) {
+        k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+        HEC_CHECK_LAUNCH();
+        HEC_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    if (o->x0_zero) {
+        k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+        HEC_CHECK_LAUNCH();
+    }
+    const double target = mixed && o->ir_rtol > 0.0 ? std::min(o->ir_rtol, o->rtol) : o->rtol;
+    double res = true_residual(A, ws, b, x, s);
+    int it = 0, cycles = 0;
+    while (res / bnorm > target && it < o->maxit) {
+        int mcyc = std::min(o->restart, o->maxit - it);
+        if (!mixed) {
+            set_scalar_async(ws, SD_TOL, target * bnorm, s);
+            gmres_cycle<double>(A, lv, ws, mcyc, o->restart, x, s, false);
+        } else {
+            // inner solve of A d = r in FP32 storage, one cycle, to inner_rtol
+            double inner = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-4;
+            set_scalar_async(ws, SD_TOL, std::max(inner * res, 0.5 * target * bnorm), s);
+            gmres_cycle<float>(A, lv, ws, mcyc, o->restart, x, s, false);
+            inf.ir_steps++;
+        }
+        // the true residual after the cycle, then one copy of the scalars and one
+        // synchronisation for the cycle's estimate, the true residual and the step count
+        spmv_launch<double, double, double>(A, -1.0, x, 1.0, b, ws.r.get(), s);
+        launch_pass<1>(ws, n, OpNorm<double>{{}, ws.r.get(), ws.sd.get() + SD_TRUE}, 1, s, nullptr);
+        int jd;
+        if (ws.hflags) {  // the step count is mirrored in the mapped flags
+            HEC_HIP(hipMemcpyAsync(ws.hsd, ws.sd.get(), SD_SCALARS * sizeof(double), hipMemcpyDeviceToHost, s));
+            HEC_HIP(hipStreamSynchronize(s));
+            jd = hf(ws)[SI_JDONE];
+        } else {  // plain copies into the workspace's host arrays
+            HEC_HIP(hipMemcpyAsync(ws.hsd, ws.sd.get(), SD_SCALARS * sizeof(double), hipMemcpyDeviceToHost, s));
+            HEC_HIP(hipMemcpyAsync(ws.hsi, ws.si.get(), SI_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HEC_HIP(hipStreamSynchronize(s));
+            jd = ws.hsi[SI_JDONE];
+        }
+        inf.rel_res_est = ws.hsd[SD_RES] / bnorm;
+        res = ws.hsd[SD_TRUE];
+        it += jd;
+        cycles++;
+        if (jd == 0) break;  // no progress possible (breakdown at the start of a cycle)
+    }
+    inf.iterations = it;
+    inf.restarts = std::max(0, cycles - 1);
+    inf.rel_res_true = res / bnorm;
+    if (!(res / bnorm <= target)) fail(HEC_ERR_NOT_CONVERGED, "GMRES did not reach the tolerance");
+}
+
 }  // namespace hec
 
 using namespace hec;
@@ -987,49 +1049,7 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
         inf.status = HEC_OK;
         if (n == 0) return;
         KrylovWS &ws = get_ws(*A, o->restart, mixed, false, s);
-        const double bnorm = vec_norm(ws, n, b, s);
-        if (bnorm == 0.0) {
-            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
-            HEC_CHECK_LAUNCH();
-            HEC_HIP(hipStreamSynchronize(s));
-            return;
-        }
-        if (o->x0_zero) {
-            k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
-            HEC_CHECK_LAUNCH();
-        }
-        const double target = mixed && o->ir_rtol > 0.0 ? std::min(o->ir_rtol, o->rtol) : o->rtol;
-        double res = true_residual(*A, ws, b, x, s);
-        int it = 0, cycles = 0;
-        while (res / bnorm > target && it < o->maxit) {
-            int mcyc = std::min(o->restart, o->maxit - it);
-            if (!mixed) {
-                set_scalar_async(ws, SD_TOL, target * bnorm, s);
-                gmres_cycle<double>(*A, *lv, ws, mcyc, o->restart, x, s, false);
-            } else {
-                // inner solve of A d = r in FP32 storage, one cycle, to inner_rtol
-                double inner = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-4;
-                set_scalar_async(ws, SD_TOL, std::max(inner * res, 0.5 * target * bnorm), s);
-                gmres_cycle<float>(*A, *lv, ws, mcyc, o->restart, x, s, false);
-                inf.ir_steps++;
-            }
-            // the true residual after the cycle, then one copy of the scalars and one
-            // synchronisation for the cycle's estimate, the true residual and the step count
-            spmv_launch<double, double, double>(*A, -1.0, x, 1.0, b, ws.r.get(), s);
-            launch_pass<1>(ws, n, OpNorm<double>{{}, ws.r.get(), ws.sd.get() + SD_TRUE}, 1, s, nullptr);
-            HEC_HIP(hipMemcpyAsync(ws.hsd, ws.sd.get(), SD_SCALARS * sizeof(double), hipMemcpyDeviceToHost, s));
-            HEC_HIP(hipStreamSynchronize(s));
-            const int jd = hf(ws)[SI_JDONE];
-            inf.rel_res_est = ws.hsd[SD_RES] / bnorm;
-            res = ws.hsd[SD_TRUE];
-            it += jd;
-            cycles++;
-            if (jd == 0) break;  // no progress possible (breakdown at the start of a cycle)
-        }
-        inf.iterations = it;
-        inf.restarts = std::max(0, cycles - 1);
-        inf.rel_res_true = res / bnorm;
-        if (!(res / bnorm <= target)) fail(HEC_ERR_NOT_CONVERGED, "GMRES did not reach the tolerance");
+        gmres_run(*A, *lv, ws, b, x, o, inf, s);
     });
     inf.status = st;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1100,7 +1120,10 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
                 }
                 HEC_HIP(hipStreamSynchronize(s));
                 it += hf(ws)[SI_JDONE];
-                broke = hf(ws)[SI_BREAK] != 0;
+                // 1: (r0, v) or the cycle's first rho was zero; 2: the rho of the pass after the
+                // last one was, which breaks down only if the iteration limit lets that pass run
+                const int32_t bk = hf(ws)[SI_BREAK];
+                broke = bk == 1 || (bk == 2 && it < o->maxit);
             }
             inf.rel_res_est = std::sqrt(std::min(read_scalar(ws, SD_RNORM2, s), read_scalar(ws, SD_SNORM2, s))) / bnorm;
             res = true_residual(*A, ws, b, x, s);

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -48,7 +49,11 @@ class SolveOpts(C.Structure):
 
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_levels", C.c_int32), ("coarse_size", C.c_int32),
-                ("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32)]
+                ("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
+                ("smoother", C.c_int32), ("cheb_lower", C.c_double)]
+
+
+SMOOTHERS = {"jacobi": 0, "chebyshev": 1}
 
 
 class SolveInfo(C.Structure):
@@ -154,19 +159,37 @@ def set_allocator(alloc=None, free=None):
 _all_hooks = []  # every callback pair ever set: buffers are freed by the hooks that made them
 
 
-def _torch_alloc(nbytes, stream):
+def _torch_hooks():
+    """alloc / free through torch's caching allocator. The torch functions are bound
+    here, not looked up per call: handles released while the interpreter shuts down
+    (when imports no longer work) still reach them; once shutdown has begun a free is
+    skipped, since the process's memory goes with it."""
     import torch
-    return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+    alloc = torch.cuda.caching_allocator_alloc
+    delete = torch.cuda.caching_allocator_delete
+    finalizing = sys.is_finalizing
+
+    def _alloc(nbytes, stream):
+        return alloc(nbytes, stream=stream)
+
+    def _free(ptr, nbytes, stream):
+        if not finalizing():
+            delete(ptr)
+
+    return _alloc, _free
+
+
+def _torch_alloc(nbytes, stream):
+    return _torch_hooks()[0](nbytes, stream)
 
 
 def _torch_free(ptr, nbytes, stream):
-    import torch
-    torch.cuda.caching_allocator_delete(ptr)
+    _torch_hooks()[1](ptr, nbytes, stream)
 
 
 def use_torch_allocator():
     """Route the library's device memory through torch's caching allocator."""
-    set_allocator(_torch_alloc, _torch_free)
+    set_allocator(*_torch_hooks())
 
 
 def footprint(A=None, M=None, lv=None) -> int:
@@ -486,9 +509,15 @@ def gmres_solve_batched(B: Batch, systems, maxit: int = 10000, rtol: float = 1e-
 # ------------------------------------------------------------------ AMG (Sec. 2.8)
 
 def amg_setup(A, theta: float = 0.25, max_levels: int = 8, coarse_size: int = 64, omega: float = 2.0 / 3.0,
-              nu1: int = 3, nu2: int = 3, use_graph: bool = True, stream=None) -> Amg:
+              nu1: int = 3, nu2: int = 3, use_graph: bool = True, smoother: str = "jacobi",
+              cheb_lower: float = 0.3, stream=None) -> Amg:
+    """smoother: "jacobi" (damped, weight omega) or "chebyshev" (polynomial of degree nu1 /
+    nu2 in D^{-1} A on [cheb_lower * lmax, lmax])."""
     n, Ap, Aj, Ax = _csr(A)
-    o = AmgOpts(theta, max_levels, coarse_size, omega, nu1, nu2, 1 if use_graph else 0)
+    if smoother not in SMOOTHERS:
+        raise ValueError(f"smoother must be one of {sorted(SMOOTHERS)}")
+    o = AmgOpts(theta, max_levels, coarse_size, omega, nu1, nu2, 1 if use_graph else 0, SMOOTHERS[smoother],
+                cheb_lower)
     out = _vp()
     _check(load().amg_setup(n, Ap.ctypes.data, Aj.ctypes.data, Ax.ctypes.data, C.byref(o),
                             _stream_or_null(stream), C.byref(out)), "amg_setup")

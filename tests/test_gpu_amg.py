@@ -2,8 +2,9 @@
 (C/F splitting, interpolation and Galerkin operators identical: the setup takes
 the same steps in the same order of operations), and V-cycle solves (cycle
 counts within one of the oracle's, FP64 residual at the tolerance, solution
-close to the oracle's); edge cases: one level, a matrix at most the coarse size,
-zero right-hand side, maxit reached, bad options, a zero diagonal."""
+close to the oracle's), with the damped Jacobi and the Chebyshev smoother; edge
+cases: one level, a matrix at most the coarse size, zero right-hand side, maxit
+reached, bad options, a zero diagonal."""
 import numpy as np
 import pytest
 
@@ -107,14 +108,54 @@ def test_one_cycle_matches_oracle_closely(nu):
     assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
+CHEB_CASES = ["poisson2d_40", "poisson3d_20", "tpfa3d_17x13x11", "aniso3d_14", "poisson2d_40_positive"]
+
+
+@pytest.mark.parametrize("name", CHEB_CASES)
+@pytest.mark.parametrize("lower", [0.3, 0.05])
+def test_chebyshev_solve_matches_oracle(name, lower):
+    mk, opt = CASES[name]
+    A = mk()
+    opt = dict(opt, smoother="chebyshev", cheb_lower=lower)
+    H = OA.hierarchy(A, **opt)
+    G = hec.amg_setup(A, **opt)
+    xt = np.random.default_rng(5).uniform(-1, 1, A.n)
+    b = H.levels[0].A @ xt
+    ro = OA.solve(H, b, rtol=1e-8, maxit=200)
+    x = empty(A.n)
+    inf = hec.amg_solve(G, dev(b), x, maxit=200, rtol=1e-8)
+    xg = host(x)
+    rr = np.linalg.norm(b - H.levels[0].A @ xg) / np.linalg.norm(b)
+    print(f"{name} chebyshev [{lower}, 1]: cycles gpu {inf['iterations']} oracle {ro.iterations} res {rr:.2e}")
+    assert inf["status"] == hec.OK and ro.converged
+    assert rr <= 1e-8 and abs(inf["iterations"] - ro.iterations) <= 1
+    assert np.linalg.norm(xg - ro.x) <= 1e-6 * np.linalg.norm(ro.x)
+
+
+@pytest.mark.parametrize("nu", [(3, 3), (0, 2), (1, 0), (2, 5)])
+def test_chebyshev_one_cycle_matches_oracle_closely(nu):
+    """One V-cycle with Chebyshev smoothing from x = 0 against the oracle's: every level's
+    sweeps, from a zero iterate below level 0, and degree 1 (a single weighted step)."""
+    A = synth.lognormal_tpfa((18, 16, 14), 2.0, np.random.default_rng(11))
+    H = OA.hierarchy(A, nu1=nu[0], nu2=nu[1], smoother="chebyshev")
+    G = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], smoother="chebyshev")
+    b = np.random.default_rng(6).uniform(-1, 1, A.n)
+    x = empty(A.n)
+    inf = hec.amg_solve(G, dev(b), x, maxit=1, rtol=0.0, check=False)
+    assert inf["status"] == hec.NOT_CONVERGED and inf["iterations"] == 1
+    xo = OA.vcycle(H, b, np.zeros(A.n))
+    assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
 @pytest.mark.parametrize("nu", [(3, 3), (2, 1), (0, 2)])
-def test_graph_replays_equal_eager_cycles(nu):
+def test_graph_replays_equal_eager_cycles(nu, smoother):
     """The recorded cycle, replayed many times with other device work and
     synchronisations in between, gives bit for bit what launching every cycle gives."""
     import torch
     A = synth.lognormal_tpfa((23, 19, 17), 2.0, np.random.default_rng(8))
-    Gg = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=True)
-    Ge = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=False)
+    Gg = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=True, smoother=smoother)
+    Ge = hec.amg_setup(A, nu1=nu[0], nu2=nu[1], use_graph=False, smoother=smoother)
     for rep in range(4):
         b = np.random.default_rng(20 + rep).uniform(-1, 1, A.n)
         xe, xg = empty(A.n), empty(A.n)
@@ -151,7 +192,8 @@ def test_edge_cases():
     inf = hec.amg_solve(G, dev(np.zeros(A.n)), x)
     assert inf["iterations"] == 0 and not host(x).any()
     # bad options and a zero diagonal
-    for kw in ({"theta": 0.0}, {"max_levels": 0}, {"omega": 2.0}, {"nu1": -1}, {"coarse_size": 0}):
+    for kw in ({"theta": 0.0}, {"max_levels": 0}, {"omega": 2.0}, {"nu1": -1}, {"coarse_size": 0},
+               {"smoother": "chebyshev", "cheb_lower": 0.0}, {"smoother": "chebyshev", "cheb_lower": 1.0}):
         kw = dict(kw)
         with pytest.raises(hec.HecError) as e:
             hec.amg_setup(A, **kw)

@@ -209,3 +209,97 @@ def test_direct_interpolation_weight_sums_on_non_m_matrices(seed):
             seen.add("lumped" if pos > 0 else "plain")
             assert abs(wsum + neg / (aii + pos)) <= 1e-14
     assert {"beta", "lumped"} <= seen
+
+
+# ---------------------------------------------------------------- Chebyshev smoother
+
+def _cheb_T(nu, y):
+    """The Chebyshev polynomial of the first kind from its trigonometric / hyperbolic form."""
+    if abs(y) <= 1.0:
+        return np.cos(nu * np.arccos(y))
+    if y > 1.0:
+        return np.cosh(nu * np.arccosh(y))
+    return (-1) ** nu * np.cosh(nu * np.arccosh(-y))
+
+
+def test_gershgorin_bound_closed_forms():
+    # 1D and 2D Dirichlet Poisson: interior rows give (2 + 1 + 1) / 2 and (4 + 4) / 4
+    assert amg.gershgorin_dinv_a(amg._csr(synth.poisson1d(50))) == 2.0
+    assert amg.gershgorin_dinv_a(amg._csr(synth.poisson2d(9))) == 2.0
+    # a hand example: rows (4 + 1 + 2) / 4, (1 + 5) / 5, (3 + 2) / 2
+    D = np.array([[4.0, -1.0, 2.0], [1.0, 5.0, 0.0], [0.0, -3.0, 2.0]])
+    assert amg.gershgorin_dinv_a(amg._csr(from_dense(D))) == 2.5
+    # it bounds the spectral radius of D^{-1} A
+    A = synth.lognormal_tpfa((9, 8, 7), 2.0, np.random.default_rng(4))
+    M = amg._csr(A).toarray()
+    rad = np.abs(np.linalg.eigvals(M / np.diag(M)[:, None])).max()
+    assert rad <= amg.gershgorin_dinv_a(amg._csr(A)) * (1 + 1e-14)
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("lower", [0.3, 0.1])
+def test_chebyshev_on_1d_poisson_eigenvectors(nu, lower):
+    """On v_j(i) = sin(i j pi / (m + 1)), an eigenvector of D^{-1} A for the 1D Dirichlet
+    Poisson matrix with eigenvalue mu_j = 1 - cos(j pi / (m + 1)), nu sweeps from x = v_j
+    with b = 0 leave p_nu(mu_j) v_j, p_nu(t) = T_nu((theta - t) / delta) / T_nu(theta / delta)
+    on the interval [lower * 2, 2] (2 = the Gershgorin bound): a wrong coefficient of the
+    recurrence changes the polynomial."""
+    m = 63
+    M = amg._csr(synth.poisson1d(m))
+    lmax = amg.gershgorin_dinv_a(M)
+    lo = lower * lmax
+    theta, delta = (lmax + lo) / 2, (lmax - lo) / 2
+    i = np.arange(1, m + 1)
+    for j in (1, 7, 20, 32, 45, 63):
+        v = np.sin(i * j * np.pi / (m + 1))
+        mu = 1.0 - np.cos(j * np.pi / (m + 1))
+        x = amg.chebyshev(M, 1.0 / M.diagonal(), lmax, v.copy(), np.zeros(m), nu, lower)
+        p = _cheb_T(nu, (theta - mu) / delta) / _cheb_T(nu, theta / delta)
+        assert np.linalg.norm(x - p * v) <= 1e-13 * np.linalg.norm(v), (j, p)
+        if lo <= mu <= lmax:  # equioscillation: |p| <= 1 / T_nu(theta / delta) on the interval
+            assert abs(p) <= 1.0 / _cheb_T(nu, theta / delta) * (1 + 1e-12)
+
+
+def test_chebyshev_on_2d_poisson_eigenvectors():
+    """The same on the 2D 5-point operator: v = sin (x) sin, mu = 1 - (cos(j pi h) + cos(k pi h)) / 2."""
+    m, nu = 20, 4
+    M = amg._csr(synth.poisson2d(m))
+    lmax = amg.gershgorin_dinv_a(M)
+    lo = 0.3 * lmax
+    theta, delta = (lmax + lo) / 2, (lmax - lo) / 2
+    h = np.pi / (m + 1)
+    g = np.arange(1, m + 1)
+    for j, k in ((1, 1), (3, 17), (10, 10), (20, 5), (20, 20)):
+        v = np.outer(np.sin(g * k * h), np.sin(g * j * h)).ravel()  # row index y, column x
+        mu = 1.0 - (np.cos(j * h) + np.cos(k * h)) / 2
+        x = amg.chebyshev(M, 1.0 / M.diagonal(), lmax, v.copy(), np.zeros(m * m), nu)
+        p = _cheb_T(nu, (theta - mu) / delta) / _cheb_T(nu, theta / delta)
+        assert np.linalg.norm(x - p * v) <= 1e-13 * np.linalg.norm(v)
+
+
+def test_chebyshev_degree_one_is_jacobi_with_weight_one_over_theta():
+    A = synth.lognormal_tpfa((11, 9), 1.5, np.random.default_rng(3))
+    M = amg._csr(A)
+    rng = np.random.default_rng(4)
+    x0, b = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    dinv = 1.0 / M.diagonal()
+    lmax = amg.gershgorin_dinv_a(M)
+    theta = (lmax + 0.3 * lmax) / 2
+    x1 = amg.chebyshev(M, dinv, lmax, x0.copy(), b, 1)
+    lev = amg.Level(M, dinv=dinv)
+    xj = amg._jacobi(lev, x0.copy(), b, 1.0 / theta, 1)
+    assert np.abs(x1 - xj).max() <= 1e-15 * np.abs(xj).max()
+
+
+def test_chebyshev_vcycle_converges_and_is_symmetric():
+    """With equal pre- and post-smoothing degrees the V-cycle is a symmetric operator
+    (the smoother's polynomial in D^{-1} A is self-adjoint in the A inner product, and
+    its adjoint is the same sweep order), and the cycle converges fast on 3D Poisson."""
+    A = synth.poisson3d(8)
+    H = amg.hierarchy(A, coarse_size=20, smoother="chebyshev", nu1=2, nu2=2)
+    n = A.n
+    E = np.stack([amg.vcycle(H, e, np.zeros(n)) for e in np.eye(n)], axis=1)
+    assert np.abs(E - E.T).max() <= 1e-12 * np.abs(E).max()
+    b = np.random.default_rng(2).uniform(-1, 1, n)
+    r = amg.solve(H, b, rtol=1e-10, maxit=30)
+    assert r.converged and r.iterations <= 10
