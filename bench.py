@@ -11,8 +11,10 @@ timed steps; p50/p99 are the per-solve latencies.
 
 Extra fields: the SpMV's achieved GB/s (algorithmic bytes, three rotating matrix
 copies so the 256 MB last-level cache cannot hold the working set), the roofline
-of the dominant kernel of the step, BiCGSTAB on the same system, and the FP64
-CPU oracle timed on a bounded sample of the same workload on this host.
+of the dominant kernel of the step, BiCGSTAB on the same system, one full solve of
+the FP64 CPU oracle on one core of this host (and its CSR product on every core),
+and two smaller records: the 2D Poisson 64^2 latency case and the 192^3 anisotropic
+ILU(1) case solved in FP64 and in mixed precision to 1e-10.
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes moved by one preconditioner solve (lower + upper k_trsv_blk) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
-TRSV_PAIR_TRAFFIC = int((157.8 + 48.5 + 165.4 + 59.3) * 1e6)
+TRSV_PAIR_TRAFFIC = None
 
 
 def parse():
@@ -42,7 +44,8 @@ def parse():
     p.add_argument("--m", type=int, default=128, help="grid edge of the 3D workload")
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-iters", type=int, default=30)
+    p.add_argument("--no-extra", action="store_true", help="skip the c1 (2D Poisson latency) and c4 (192^3 "
+                                                              "FP64 vs mixed) records of the benchmark line")
     p.add_argument("--spmv-reps", type=int, default=50)
     p.add_argument("--workload", default="diffusion128",
                    choices=["diffusion128", "poisson64", "powerlaw", "aniso192", "serving", "ras", "iluk", "formats",
@@ -131,11 +134,12 @@ def formats_table():
 
 
 def amg_table():
-    """Tables 6-7 of the paper (AMG with RS coarsening, direct interpolation and damped
-    Jacobi, V-cycle, at most 8 levels, 3 + 3 sweeps) on the paper's 3D Poisson 50^3 and
-    a 1000 x 1000 2D lognormal diffusion stand-in for ecology2: setup time, hierarchy,
-    V-cycles to 1e-8 and solve time on the GPU; the oracle's V-cycle solve on one host
-    core beside it for the 50^3 case (its pure-Python setup is too slow for 10^6 rows)."""
+    """Tables 6-7 of the paper (AMG with RS coarsening, direct interpolation and the damped
+    Jacobi or the Chebyshev smoother, V-cycle, at most 8 levels, 3 + 3 sweeps) on the
+    paper's 3D Poisson 50^3 and a 1000 x 1000 2D lognormal diffusion stand-in for
+    ecology2: setup time, hierarchy, V-cycles to 1e-8 and solve time on the GPU; the
+    oracle's V-cycle solve on one host core beside it for the 50^3 case (its pure-Python
+    setup is too slow for 10^6 rows)."""
     import torch
     import oracle.amg as OA
     from paper_1606_00545_amd import hec, synth
@@ -145,13 +149,14 @@ def amg_table():
         os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
     except (AttributeError, OSError):
         pass
-    for name, mk, cpu in (("3D Poisson 50^3 (the paper's)", lambda: synth.poisson3d(50), True),
-                          ("2D lognormal diffusion 1000^2, sigma 2 (stand-in for ecology2)",
-                           lambda: synth.lognormal_tpfa((1000, 1000), 2.0, np.random.default_rng(8)), False)):
+    mats = (("3D Poisson 50^3 (the paper's)", lambda: synth.poisson3d(50), True),
+            ("2D lognormal diffusion 1000^2, sigma 2 (stand-in for ecology2)",
+             lambda: synth.lognormal_tpfa((1000, 1000), 2.0, np.random.default_rng(8)), False))
+    for (name, mk, cpu), smoother in ((m, sm) for m in mats for sm in ("jacobi", "chebyshev")):
         A = mk()
         xt = np.random.default_rng(9).uniform(-1, 1, A.n)
         ts = time.time()
-        G = hec.amg_setup(A)
+        G = hec.amg_setup(A, smoother=smoother)
         t_setup = time.time() - ts
         info = hec.amg_info(G)
         opc = sum(info["nnz"]) / info["nnz"][0]
@@ -165,12 +170,13 @@ def amg_table():
             inf = hec.amg_solve(G, b, x, maxit=200, rtol=1e-8)
             runs.append(inf)
         best = min(runs, key=lambda r: r["seconds"])
-        row = {"matrix": name, "n": A.n, "nnz": A.nnz, "setup_s": round(t_setup, 3), "levels": info["levels"],
+        row = {"matrix": name, "smoother": smoother, "n": A.n, "nnz": A.nnz, "setup_s": round(t_setup, 3),
+               "levels": info["levels"],
                "level_rows": info["n"], "operator_complexity": round(opc, 3), "cycles": best["iterations"],
                "rel_res": best["rel_res_true"], "gpu_solve_s": round(best["seconds"], 4),
                "ms_per_cycle": round(best["seconds"] * 1e3 / max(1, best["iterations"]), 3)}
         if cpu:
-            H = OA.hierarchy(A)
+            H = OA.hierarchy(A, smoother=smoother)
             bh = b.cpu().numpy()
             tc = time.perf_counter()
             ro = OA.solve(H, bh, rtol=1e-8, maxit=200)
@@ -179,7 +185,8 @@ def amg_table():
                        speedup_vs_cpu=round(t_cpu / best["seconds"], 2))
         log(f"[bench] amg: {row}")
         res.append(row)
-    return {"amg": res, "note": "FP64; RS first pass, direct interpolation, damped Jacobi (omega 2/3), 3 + 3 sweeps, "
+    return {"amg": res, "note": "FP64; RS first pass, direct interpolation, damped Jacobi (omega 2/3) or Chebyshev "
+                                "(degree 3 on [0.3 lmax, lmax], lmax the Gershgorin bound of D^-1 A), 3 + 3 sweeps, "
                                 "at most 8 levels, coarsest <= 64 rows solved with its inverse"}
 
 
@@ -278,9 +285,9 @@ def main():
     zb = torch.empty(n, dtype=torch.float64, device=dev)
     t_trsv_l = time_launches(lambda: hec.trsv_levels(F, lv, b, zb, hec.LOWER), 20, stream)
     t_trsv_lu = time_launches(lambda: hec.trsv_levels(F, lv, b, zb, hec.LU), 20, stream)
-    # algorithmic bytes of one L-then-U solve: every off-diagonal factor entry (8 B value + 4 B index),
-    # the pivots, v read, z written, the intermediate y written and read once
-    trsv_bytes = 12 * (lu_nnz - n) + 8 * n + 8 * n + 8 * n + 16 * n
+    # algorithmic bytes of one L-then-U solve: 12 bytes (value + index) per stored factor entry, and
+    # 32 bytes per row (the right-hand side read, the intermediate L^{-1} v written and read, z written)
+    trsv_bytes = 12 * lu_nnz + 32 * n
     trsv_gbs = trsv_bytes / t_trsv_lu / 1e9
     it_per_solve = iters[-1]
     log(f"[bench] spmv {t_spmv * 1e6:.1f}us {spmv_gbs:.0f} GB/s; trsv L {t_trsv_l * 1e6:.1f}us; "
@@ -324,13 +331,13 @@ def main():
                        "bound_us": round(lat_bound * 1e6, 1), "frac": round(lat_bound / t_trsv_lu, 4),
                        "note": "t_level = lower solve of a 4096-row chain (one row per level, one part) / 4096"}
 
-    # ---- CPU oracle on a bounded sample (one GMRES cycle) ----
+    # ---- CPU oracle: one full solve of the same system on one pinned core ----
     cpu = None
+    x_oracle = None
     if not args.no_cpu_baseline:
         import oracle as O
         Ah = A
         bh = b.cpu().numpy()
-        # the oracle is single-threaded; pin it to one core of this host for the sample
         cores_avail = sorted(os.sched_getaffinity(0))
         cpu_model = "unknown"
         try:
@@ -338,23 +345,40 @@ def main():
                 cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
         except (OSError, StopIteration):
             pass
+        # the oracle is single-threaded; pin it to one core of this host
         os.sched_setaffinity(0, {cores_avail[0]})
         ts = time.time()
         Fo = O.iluk(Ah.n, Ah.Ap, Ah.Aj, Ah.Ax, 0)
         t_orc_ilu = time.time() - ts
         ts = time.time()
-        ro = O.gmres(Ah, Fo, bh, restart=30, maxit=args.cpu_sample_iters, rtol=1e-8)
+        ro = O.gmres(Ah, Fo, bh, restart=30, rtol=1e-8)
         t_orc = time.time() - ts
+        ts = time.perf_counter()
+        for _ in range(5):
+            O.csr_spmv(Ah.n, Ah.Ap, Ah.Aj, Ah.Ax, xt)
+        t_spmv1 = (time.perf_counter() - ts) / 5
         os.sched_setaffinity(0, set(cores_avail))
-        per_it = t_orc / max(ro.iterations, 1)
-        est_solve = per_it * it_per_solve
-        cpu = {"value": round(1.0 / est_solve, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle GMRES(30) ILU(0), first {ro.iterations} iterations of the same "
-                         f"{m}^3 system ({t_orc:.1f}s, {per_it * 1e3:.0f} ms/iteration), scaled to the "
-                         f"{it_per_solve} iterations of one solve; oracle ILU(0) setup {t_orc_ilu:.2f}s "
-                         f"not included; single thread pinned to one core, -O3 -ffp-contract=off",
-               "cpu_model": cpu_model, "host_cores_available": len(cores_avail)}
-        log(f"[bench] cpu oracle: {per_it * 1e3:.1f} ms/iteration -> {est_solve:.1f} s/solve")
+        # secondary figure: the same CSR product with the rows shared by every host core
+        nthr = len(cores_avail)
+        O.csr_spmv_omp(Ah.n, Ah.Ap, Ah.Aj, Ah.Ax, xt, nthr)
+        ts = time.perf_counter()
+        for _ in range(20):
+            O.csr_spmv_omp(Ah.n, Ah.Ap, Ah.Aj, Ah.Ax, xt, nthr)
+        t_spmvn = (time.perf_counter() - ts) / 20
+        x_oracle = ro.x
+        cpu = {"value": round(1.0 / t_orc, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full oracle ILU(0)-GMRES(30) solve of the same {m}^3 system from x0 = 0 to "
+                         f"1e-8 ({ro.iterations} iterations, {t_orc:.2f} s, rel_res {ro.rel_res:.2e}); the "
+                         f"oracle's ILU(0) setup ({t_orc_ilu:.2f} s) is not included; single thread pinned to "
+                         f"one core, gcc -O3 -ffp-contract=off",
+               "cpu_model": cpu_model, "host_cores_available": nthr,
+               "spmv_1core": {"us": round(t_spmv1 * 1e6, 1), "GBps": round(spmv_bytes / t_spmv1 / 1e9, 2)},
+               "spmv_all_cores": {"threads": nthr, "us": round(t_spmvn * 1e6, 1),
+                                  "GBps": round(spmv_bytes / t_spmvn / 1e9, 2),
+                                  "note": "secondary figure: the oracle's CSR product with its rows shared by "
+                                          "OpenMP threads on every available host core"}}
+        log(f"[bench] cpu oracle: full solve {t_orc:.2f} s ({ro.iterations} it); spmv 1 core "
+            f"{t_spmv1 * 1e3:.1f} ms, {nthr} threads {t_spmvn * 1e3:.2f} ms")
 
     lat_ms = np.array(lat) * 1e3
     out = {
@@ -380,6 +404,8 @@ def main():
         "us_per_iteration": round(ms_per_step * 1e3 / it_per_solve, 1),
         "rel_res": rel_res,
         "err_vs_x_true": err_true,
+        "err_vs_oracle": (float(np.linalg.norm(x.cpu().numpy() - x_oracle) / np.linalg.norm(x_oracle))
+                          if x_oracle is not None else None),
         "setup_s": {"hec_from_csr": round(t_hec, 3), "ilu_factor": round(t_ilu, 3),
                     "level_schedule": round(t_lev, 3), "note": "host CSR in (PCIe-inclusive)"},
         "spmv": spmv_roof,
@@ -390,7 +416,81 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if not args.no_extra:
+        del copies, xs, ys
+        out["c1_poisson64"] = c1_record(args)
+        out["c4_aniso192_mixed"] = c4_record(args)
     print(json.dumps(out), flush=True)
+
+
+def c1_record(args):
+    """2D 5-point Poisson 64 x 64, ILU(0)-GMRES(30) to 1e-8 from x0 = 0: per-solve latency
+    (a latency-bound case: 127 + 127 levels, every vector in cache), and the distance to
+    the oracle's solution."""
+    import torch
+    import oracle as O
+    from paper_1606_00545_amd import hec, synth
+    A, xt = synth.workload_c1()
+    Mh = hec.hec_from_csr(A)
+    F = hec.ilu_factor(A, 0)
+    lv = hec.level_schedule(F)
+    bh = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, xt)
+    b = torch.from_numpy(bh).cuda()
+    x = torch.empty_like(b)
+    for _ in range(3):
+        hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-8)
+    lat = []
+    for _ in range(max(50, args.steps)):
+        t = time.perf_counter()
+        inf = hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-8)
+        lat.append(time.perf_counter() - t)
+    lat = np.array(lat) * 1e3
+    ro = O.gmres(A, O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0), bh, restart=30, rtol=1e-8)
+    rec = {"workload": "2D 5-point Poisson 64x64 (n=4096), ILU(0), GMRES(30), rtol 1e-8, x0=0",
+           "solves": len(lat), "solves_per_s": round(1e3 / lat.mean(), 1), "p50_ms": round(float(np.median(lat)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3), "iterations": inf["iterations"],
+           "oracle_iterations": ro.iterations, "rel_res": inf["rel_res_true"],
+           "err_vs_oracle": float(np.linalg.norm(x.cpu().numpy() - ro.x) / np.linalg.norm(ro.x))}
+    log(f"[bench] c1: {rec}")
+    return rec
+
+
+def c4_record(args):
+    """3D 7-point lognormal diffusion 192^3 with z transmissibilities x 1/100, ILU(1): the
+    all-FP64 GMRES(30) solve against the mixed one (FP32 matrix, factor and basis inside,
+    FP64 residual, dots, rotations and refinement), both to 1e-10 from x0 = 0."""
+    import torch
+    from paper_1606_00545_amd import hec, synth
+    t0 = time.time()
+    A, xt = synth.workload_diffusion3d(192, sigma=2.0, seed=4, zscale=0.01)
+    t_gen = time.time() - t0
+    ts = time.time()
+    Mh = hec.hec_from_csr(A, keep_f32=True)
+    F = hec.ilu_factor(A, k=1, keep_f32=True)
+    lv = hec.level_schedule(F)
+    t_setup = time.time() - ts
+    xd = torch.from_numpy(xt).cuda()
+    b = torch.empty_like(xd)
+    hec.hec_spmv(Mh, xd, b)
+    rec = {"workload": "3D 7-point lognormal TPFA 192^3 (sigma=2, seed 4), z faces x 1/100, ILU(1), GMRES(30), "
+                       "rtol 1e-10, x0=0", "n": A.n, "nnz_lu": hec.ilu_info(F)["nnz"],
+           "setup_s": round(t_setup, 2)}
+    xs = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        x = torch.empty_like(b)
+        hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-10, precision=prec, ir_rtol=1e-10, maxit=20000)
+        inf = hec.gmres_solve(Mh, F, lv, b, x, restart=30, rtol=1e-10, precision=prec, ir_rtol=1e-10, maxit=20000)
+        r = b.clone()
+        hec.hec_spmv(Mh, x, r, -1.0, 1.0)
+        xs[name] = x
+        rec[name] = {"seconds": round(inf["seconds"], 4), "iterations": inf["iterations"],
+                     "ir_steps": inf["ir_steps"], "rel_res": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
+                     "err_vs_x_true": float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))}
+    rec["mixed"]["err_vs_fp64_solution"] = float(torch.linalg.norm(xs["mixed"] - xs["fp64"]) /
+                                                 torch.linalg.norm(xs["fp64"]))
+    rec["mixed_speedup"] = round(rec["fp64"]["seconds"] / rec["mixed"]["seconds"], 3)
+    log(f"[bench] c4 (generated in {t_gen:.1f}s): {rec}")
+    return rec
 
 
 # ---------------------------------------------------------------------------- extra records

@@ -7,7 +7,8 @@ does. It shares no code with the GPU library.
 
 Functions, each following the passage cited in ``oracle.c``:
 
-* :func:`csr_spmv`        -- Alg. 1 / Eq. (2)
+* :func:`csr_spmv`        -- Alg. 1 / Eq. (2); :func:`csr_spmv_omp` the same on several
+  threads (the benchmark's all-cores CPU figure)
 * :func:`hec_from_csr`    -- Sec. 2.1 HEC layout (ELL slab + CSR remainder)
 * :func:`iluk`            -- Sec. 2.4, Eq. (9)-(10), Alg. 2 (ILU(k), in place)
 * :func:`level_schedule`  -- Sec. 2.6, Eq. (11), Alg. 3
@@ -37,7 +38,7 @@ OK, INVALID, NOMEM, ZERO_PIVOT, BREAKDOWN, NOT_CONVERGED = range(6)
 
 
 def build_command(out: str = LIB_PATH):
-    return ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
+    return ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-fopenmp",
             "-shared", "-o", out, SRC_PATH, "-lm"]
 
 
@@ -63,6 +64,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.orc_csr_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, _f64p, C.c_double, _f64p]
         L.orc_csr_spmv.restype = None
+        L.orc_csr_spmv_omp.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, _f64p, C.c_double, _f64p,
+                                       C.c_int]
+        L.orc_csr_spmv_omp.restype = None
         L.orc_hec_sizes.argtypes = [C.c_int, _i32p, C.c_int, _ip, _ip, C.POINTER(C.c_long)]
         L.orc_hec_fill.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int,
                                    _i32p, _f64p, _i32p, _i32p, _f64p]
@@ -98,6 +102,13 @@ def csr_spmv(n, Ap, Aj, Ax, x, alpha=1.0, beta=0.0, y=None):
     """y = alpha*A*x + beta*y (Alg. 1 / Eq. (2)). Returns y (a new array if y is None)."""
     y = np.zeros(n) if y is None else _f64(y).copy()
     lib().orc_csr_spmv(n, _i32(Ap), _i32(Aj), _f64(Ax), alpha, _f64(x), beta, y)
+    return y
+
+
+def csr_spmv_omp(n, Ap, Aj, Ax, x, nthreads, alpha=1.0, beta=0.0, y=None):
+    """csr_spmv with the rows shared among nthreads OpenMP threads (same result bit for bit)."""
+    y = np.zeros(n) if y is None else _f64(y).copy()
+    lib().orc_csr_spmv_omp(n, _i32(Ap), _i32(Aj), _f64(Ax), alpha, _f64(x), beta, y, int(nthreads))
     return y
 
 

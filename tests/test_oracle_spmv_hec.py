@@ -130,3 +130,15 @@ def test_hec_stencil_has_empty_remainder():
 def test_hec_zero_rows():
     h = O.hec_from_csr(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
     assert h.K == 0 and h.ld == 0 and h.rem_ptr.tolist() == [0]
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_csr_spmv_equals_the_serial_one(threads):
+    """The all-cores CPU figure's product sums every row as the serial oracle does."""
+    rng = np.random.default_rng(12)
+    A, xt = synth.workload_diffusion3d(17, sigma=2.0, seed=3)
+    y0 = rng.uniform(-1, 1, A.n)
+    for alpha, beta in ((1.0, 0.0), (-1.0, 1.0), (0.5, -2.0)):
+        ys = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, xt, alpha, beta, y0)
+        yp = O.csr_spmv_omp(A.n, A.Ap, A.Aj, A.Ax, xt, threads, alpha, beta, y0)
+        assert np.array_equal(ys.view(np.uint64), yp.view(np.uint64))
