@@ -44,7 +44,8 @@ typedef enum {
     HEC_ERR_ZERO_PIVOT = 3,    /* ILU met an exactly zero pivot */
     HEC_ERR_BREAKDOWN = 4,     /* BiCGSTAB rho or (r0,v) became 0 (or non-finite) */
     HEC_ERR_NOT_CONVERGED = 5, /* maxit reached; x holds the last iterate */
-    HEC_ERR_HIP = 6            /* a HIP runtime call failed */
+    HEC_ERR_HIP = 6,           /* a HIP runtime call failed */
+    HEC_ERR_TIMEOUT = 7        /* a device-side wait of a triangular solve gave up (hec_set_spin_limit) */
 } hec_status;
 
 typedef enum { HEC_F64 = 0, HEC_F32 = 1 } hec_dtype;
@@ -217,6 +218,23 @@ hec_status levels_export(hec_levels lv, int32_t *lower_ptr, int32_t *lower_perm,
 
 hec_status levels_destroy(hec_levels lv);
 
+/* Triangular solves wait on the device for the rows they depend on (rows of other
+ * workgroups, and slots and progress inside their own). Every such wait gives up
+ * after `polls` polls: the launch then ends normally with invalid outputs and
+ * records the failure in the schedule, which the solvers report as
+ * HEC_ERR_TIMEOUT, and levels_check for trsv_levels. A correct schedule used on
+ * one stream at a time never gets there (a wait lasts at most one solve); the
+ * limit exists so that a broken plan, a lost store or misuse ends in a status
+ * instead of a hung device, and so that tests can force that path. polls < 0
+ * restores the default (2^26); 0 gives up at the first unready poll. Applies to
+ * launches made after the call, from any thread. */
+hec_status hec_set_spin_limit(int64_t polls);
+
+/* Synchronises `stream`, then reports (and clears) a wait of lv's triangular
+ * solves that gave up since the last check: HEC_ERR_TIMEOUT, else HEC_OK. The
+ * solvers make this check themselves before they return. */
+hec_status levels_check(hec_levels lv, void *stream);
+
 /* Alg. 3: solve with the factor level by level. A RAS factor (ilu_factor_ras)
  * accepts only HEC_LU, with b and x of the system size. which = HEC_LOWER: x = L^{-1} b
  * (unit diagonal); HEC_UPPER: x = U^{-1} b; HEC_LU: x = U^{-1} L^{-1} b (the
@@ -283,8 +301,9 @@ hec_status batch_destroy(hec_batch B);
  * depend on the rest of the batch. `stream`: the call waits for work already
  * queued on it, runs on the context's own stream and synchronises before it
  * returns; calls on one context must not overlap. info (may be NULL): `count`
- * entries. Returns HEC_ERR_NOT_CONVERGED if any system did not converge (its
- * info entry says which). */
+ * entries. Returns HEC_ERR_TIMEOUT if a wait in a system's triangular solve gave
+ * up (hec_set_spin_limit), else HEC_ERR_NOT_CONVERGED if any system did not
+ * converge (its info entry says which). */
 hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, const hec_ilu *M,
                                const hec_levels *lv, const double *const *b, double *const *x,
                                const hec_solve_opts *opts, hec_solve_info *info, void *stream);

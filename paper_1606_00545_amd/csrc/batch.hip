@@ -58,6 +58,7 @@ struct BatchSys {
 
 struct BatchHead {
     int32_t count, restart, maxit, precision, x0_zero;
+    uint32_t spin;  // polls a wait for a dependency makes before it gives up
     double rtol, target, inner_rtol;
 };
 
@@ -67,7 +68,7 @@ struct BatchOut {
 };
 
 // LDS layout of one system (dynamic): ly[max_n] | lz[max_n] | red[kBW][33] |
-// H[(m+1)][m] | cs[m] | sn[m] | g[m+1] | y[m] | sc[8]
+// H[(m+1)][m] | cs[m] | sn[m] | g[m+1] | y[m] | sc[8] (sc[7]: the give-up flag, an int)
 struct Lds {
     double *ly, *lz, *red, *H, *cs, *sn, *g, *y, *sc;
 };
@@ -159,7 +160,8 @@ __device__ __forceinline__ unsigned long long lds_load_bits(const double *p) {
 // chunk can always proceed. Lower: dst = L^{-1} src (src in global memory, unit
 // diagonal). Upper: dst = U^{-1} src (src in LDS), also stored to out.
 template <class VT, bool UPPER>
-__device__ void b_tri(const BatchSys &S, const double *src, double *dst, double *out) {
+__device__ void b_tri(const BatchSys &S, const double *src, double *dst, double *out, uint32_t spin,
+                      int *timed_out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nch = UPPER ? S.nchU : S.nchL, K = UPPER ? S.KU : S.KL, ldq = S.ldq;
     const int32_t *ch = UPPER ? S.chU : S.chL, *rowp = UPPER ? S.rowU : S.rowL, *colp = UPPER ? S.colU : S.colL;
@@ -182,7 +184,13 @@ __device__ void b_tri(const BatchSys &S, const double *src, double *dst, double 
             for (int u = 0; u < 8; ++u) {
                 if (j[u] < 0) continue;
                 unsigned long long bits = lds_load_bits(dst + j[u]);
+                uint32_t it = 0;
                 while (bits == kSent) {
+                    if (++it > spin) {  // give up: the row goes on with a NaN, the system reports it
+                        *timed_out = 1;
+                        bits = kQNaN;
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(1);
                     bits = lds_load_bits(dst + j[u]);
                 }
@@ -199,16 +207,17 @@ __device__ void b_tri(const BatchSys &S, const double *src, double *dst, double 
 
 // out = U^{-1} L^{-1} v (Eq. (7)-(8)). Ends with a barrier.
 template <class VT>
-__device__ void b_prec(const BatchSys &S, const double *v, double *out, const Lds &L) {
+__device__ void b_prec(const BatchSys &S, const double *v, double *out, const Lds &L, uint32_t spin,
+                       int *timed_out) {
     const double sent = __longlong_as_double((long long)kSent);
     for (int i = threadIdx.x; i < S.n; i += kBT) {
         L.ly[i] = sent;
         L.lz[i] = sent;
     }
     __syncthreads();
-    b_tri<VT, false>(S, v, L.ly, nullptr);
+    b_tri<VT, false>(S, v, L.ly, nullptr, spin, timed_out);
     __syncthreads();
-    b_tri<VT, true>(S, L.ly, L.lz, out);
+    b_tri<VT, true>(S, L.ly, L.lz, out, spin, timed_out);
     __syncthreads();
 }
 
@@ -217,7 +226,7 @@ __device__ void b_prec(const BatchSys &S, const double *v, double *out, const Ld
 // Returns the steps taken; *est receives the last estimate.
 template <class VT>
 __device__ int b_cycle(const BatchSys &S, int m, int mcyc, double tol, const double *r, double beta, const Lds &L,
-                       double *est) {
+                       double *est, uint32_t spin, int *timed_out) {
     const int n = S.n;
     double *V = S.ws, *Z = V + (size_t)(m + 1) * n, *w = Z + (size_t)m * n + n;
     for (int i = threadIdx.x; i < n; i += kBT) V[i] = r[i] / beta;
@@ -227,7 +236,7 @@ __device__ int b_cycle(const BatchSys &S, int m, int mcyc, double tol, const dou
     double res = beta;
     while (j < mcyc) {
         double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-        b_prec<VT>(S, vj, zj, L);
+        b_prec<VT>(S, vj, zj, L, spin, timed_out);
         b_spmv<VT>(S, zj, w, nullptr);
         // classical Gram-Schmidt, twice: h = V^T w, w -= V h
         for (int pass = 0; pass < 2; ++pass) {
@@ -332,7 +341,11 @@ __global__ __launch_bounds__(kBT) void k_gmres_batch(const BatchHead *__restrict
     const int n = S.n;
     double *r = S.ws + (size_t)(2 * m + 1) * n;
     BatchOut o{HEC_OK, 0, 0, 0, 0.0, 0.0};
-    const double bnorm = block_norm(S.b, n, L);
+    // a wait for a dependency gave up in this system's solves (a word of the scalar area;
+    // no static LDS: the kernel's dynamic LDS may take the whole workgroup limit)
+    int *const timed_out = (int *)(L.sc + 7);
+    if (threadIdx.x == 0) *timed_out = 0;
+    const double bnorm = block_norm(S.b, n, L);  // (its barriers publish the flag's reset)
     if (bnorm == 0.0 || n == 0) {
         for (int i = threadIdx.x; i < n; i += kBT) S.x[i] = 0.0;
     } else {
@@ -347,10 +360,10 @@ __global__ __launch_bounds__(kBT) void k_gmres_batch(const BatchHead *__restrict
             double est = 0.0;
             int jd;
             if (H.precision == 0) {
-                jd = b_cycle<double>(S, m, mcyc, H.target * bnorm, r, res, L, &est);
+                jd = b_cycle<double>(S, m, mcyc, H.target * bnorm, r, res, L, &est, H.spin, timed_out);
             } else {
                 const double tol = fmax(H.inner_rtol * res, 0.5 * H.target * bnorm);
-                jd = b_cycle<float>(S, m, mcyc, tol, r, res, L, &est);
+                jd = b_cycle<float>(S, m, mcyc, tol, r, res, L, &est, H.spin, timed_out);
                 o.ir_steps++;
             }
             o.rel_res_est = est / bnorm;
@@ -364,6 +377,8 @@ __global__ __launch_bounds__(kBT) void k_gmres_batch(const BatchHead *__restrict
         o.rel_res_true = res / bnorm;
         if (!(res / bnorm <= H.target)) o.status = HEC_ERR_NOT_CONVERGED;
     }
+    __syncthreads();
+    if (*timed_out) o.status = HEC_ERR_TIMEOUT;
     if (threadIdx.x == 0) out[blockIdx.x] = o;
 }
 
@@ -445,11 +460,14 @@ hec_status batch_create(int32_t capacity, int32_t restart, int32_t max_n, int32_
         B->use_graph = use_graph != 0;
         B->lds = batch_lds_bytes(max_n, restart);
         if ((int64_t)B->lds > max_dyn_lds()) fail(HEC_ERR_INVALID_ARG, "max_n too large for the workgroup's LDS");
-        static std::once_flag attr;
-        std::call_once(attr, [] {
-            (void)hipFuncSetAttribute((const void *)k_gmres_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      max_dyn_lds());
-        });
+        // once per process; a failure is reported (and taken off the runtime's last-error
+        // slot, where it would otherwise surface in the caller's next HIP call)
+        static const hipError_t attr = hipFuncSetAttribute((const void *)k_gmres_batch,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_lds());
+        if (attr != hipSuccess) {
+            (void)hipGetLastError();
+            fail(HEC_ERR_HIP, std::string("hipFuncSetAttribute(k_gmres_batch): ") + hipGetErrorString(attr));
+        }
         HEC_HIP(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
         HEC_HIP(hipEventCreateWithFlags(&B->ev, hipEventDisableTiming));
         HEC_HIP(hipHostMalloc((void **)&B->h_head, sizeof(BatchHead), hipHostMallocDefault));
@@ -541,6 +559,7 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
         Hh.maxit = o->maxit;
         Hh.precision = o->precision;
         Hh.x0_zero = o->x0_zero;
+        Hh.spin = spin_limit();
         Hh.rtol = o->rtol;
         Hh.target = mixed && o->ir_rtol > 0.0 ? std::min(o->ir_rtol, o->rtol) : o->rtol;
         Hh.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-4;
@@ -588,12 +607,18 @@ hec_status gmres_solve_batched(hec_batch B, int32_t count, const hec_matrix *A, 
             f.seconds = secs;
         }
     }
-    if (st == HEC_OK && B)
+    if (st == HEC_OK && B) {
+        for (int32_t i = 0; i < count; ++i)
+            if (B->h_out[i].status == HEC_ERR_TIMEOUT) {
+                set_last_error("a wait of a system's triangular solve gave up (hec_set_spin_limit)");
+                return HEC_ERR_TIMEOUT;
+            }
         for (int32_t i = 0; i < count; ++i)
             if (B->h_out[i].status != HEC_OK) {
                 set_last_error("a system of the batch did not converge");
                 return HEC_ERR_NOT_CONVERGED;
             }
+    }
     return st;
 }
 

@@ -272,6 +272,22 @@ struct hec_tri {
     hec::DevBuf<float> piv32;
 };
 
+namespace hec {
+// Words of hec_levels_s::sync: part tickets and finished-workgroup counters of the
+// lower (0, 1) and upper (2, 3) solves, then the error word a triangular-solve wait
+// sets when it gives up (read and cleared by the host).
+constexpr int kLevelsErrWord = 4;
+constexpr int kLevelsSyncWords = 8;
+
+// Polls a device-side wait of the triangular solves makes before it gives up
+// (hec_set_spin_limit).
+uint32_t spin_limit();
+
+// Reads and clears the error word of lv after synchronising s; HEC_ERR_TIMEOUT if a
+// triangular-solve wait gave up since the last check.
+void check_levels(const hec_levels_s &lv, hipStream_t s);
+}  // namespace hec
+
 struct hec_levels_s {
     int64_t dev_bytes = 0;  // device bytes held by the schedules, plans and solve scratch
     int32_t n = 0;    // system size (vectors the caller passes)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <atomic>
 #include <mutex>
 
 #include "hec_internal.hpp"
@@ -33,7 +34,13 @@ int64_t *&alloc_owner() {
 namespace {
 std::mutex g_alloc_mu;
 Allocator g_alloc;  // alloc == NULL: hipMallocAsync / hipFreeAsync
+// 2^26 polls: about 2 s for a wait on LDS, far longer for one on global memory; a
+// legitimate wait lasts at most one solve (milliseconds)
+constexpr uint32_t kDefaultSpin = 1u << 26;
+std::atomic<uint32_t> g_spin{kDefaultSpin};
 }  // namespace
+
+uint32_t spin_limit() { return g_spin.load(std::memory_order_relaxed); }
 
 Allocator current_allocator() {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -720,6 +727,13 @@ hec_status hec_spmv(hec_matrix A, hec_dtype vals, double alpha, const void *x, h
             CASE(1, 0, 1, float, double, float)
 #undef CASE
         }
+    });
+}
+
+hec_status hec_set_spin_limit(int64_t polls) {
+    return guarded([&] {
+        if (polls > (int64_t)UINT32_MAX) fail(HEC_ERR_INVALID_ARG, "spin limit above 2^32 - 1 polls");
+        g_spin.store(polls < 0 ? kDefaultSpin : (uint32_t)polls);
     });
 }
 

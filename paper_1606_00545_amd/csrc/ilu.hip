@@ -238,6 +238,25 @@ static void ras_stack(int32_t n, const int32_t *Ap, const int32_t *Aj, const dou
     }
 }
 
+namespace hec {
+
+void check_levels(const hec_levels_s &lv, hipStream_t s) {
+    if (!lv.sync.get()) return;
+    uint32_t *errw = const_cast<uint32_t *>(lv.sync.get()) + kLevelsErrWord;
+    uint32_t e = 0;
+    HEC_HIP(hipMemcpyAsync(&e, errw, sizeof(e), hipMemcpyDeviceToHost, s));
+    HEC_HIP(hipStreamSynchronize(s));
+    if (e) {
+        const uint32_t zero = 0;
+        HEC_HIP(hipMemcpyAsync(errw, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+        HEC_HIP(hipStreamSynchronize(s));
+        fail(HEC_ERR_TIMEOUT, "a wait of the triangular solve gave up (its dependency never became ready); "
+                              "the results of the solves since the last check are not valid");
+    }
+}
+
+}  // namespace hec
+
 extern "C" {
 
 hec_status ilu_factor(int32_t n, const int32_t *Ap, const int32_t *Aj, const double *Ax, int32_t k, uint32_t flags,
@@ -364,8 +383,8 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
             build_flat(*M, false, lv->lower, s);
             build_flat(*M, true, lv->upper, s);
         }
-        lv->sync.alloc(4);
-        HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, 4 * sizeof(uint32_t), s));
+        lv->sync.alloc(kLevelsSyncWords);
+        HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, kLevelsSyncWords * sizeof(uint32_t), s));
         lv->qL64.alloc(M->n);
         lv->qU64.alloc(M->n);
         lv->yp64.alloc(M->n);
@@ -403,6 +422,13 @@ hec_status levels_export(hec_levels lv, int32_t *lower_ptr, int32_t *lower_perm,
 hec_status levels_destroy(hec_levels lv) {
     delete lv;
     return HEC_OK;
+}
+
+hec_status levels_check(hec_levels lv, void *stream) {
+    return guarded([&] {
+        if (!lv) fail(HEC_ERR_INVALID_ARG, "null levels");
+        check_levels(*lv, as_stream(stream));
+    });
 }
 
 hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec, const void *b, void *x,

@@ -1023,6 +1023,7 @@ static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const dou
     inf.iterations = it;
     inf.restarts = std::max(0, cycles - 1);
     inf.rel_res_true = res / bnorm;
+    check_levels(lv, s);  // a triangular-solve wait that gave up invalidates the iterate
     if (!(res / bnorm <= target)) fail(HEC_ERR_NOT_CONVERGED, "GMRES did not reach the tolerance");
 }
 
@@ -1131,6 +1132,7 @@ hec_status bicgstab_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *
         inf.iterations = it;
         inf.restarts = std::max(0, cycles - 1);
         inf.rel_res_true = res / bnorm;
+        check_levels(*lv, s);
         if (!(res / bnorm <= o->rtol)) {
             if (broke) fail(HEC_ERR_BREAKDOWN, "BiCGSTAB breakdown (rho or (r0,v) == 0)");
             fail(HEC_ERR_NOT_CONVERGED, "BiCGSTAB did not reach the tolerance");
@@ -1209,6 +1211,7 @@ hec_status cg_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, dou
         inf.iterations = it;
         inf.restarts = restarts;
         inf.rel_res_true = res / bnorm;
+        check_levels(*lv, s);
         if (!(res / bnorm <= o->rtol)) {
             if (broke) fail(HEC_ERR_BREAKDOWN, "CG breakdown ((r, z) or (p, A p) not positive)");
             fail(HEC_ERR_NOT_CONVERGED, "CG did not reach the tolerance");

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhec.so")
 
-OK, INVALID_ARG, NOMEM, ZERO_PIVOT, BREAKDOWN, NOT_CONVERGED, HIP_ERROR = range(7)
+OK, INVALID_ARG, NOMEM, ZERO_PIVOT, BREAKDOWN, NOT_CONVERGED, HIP_ERROR, TIMEOUT = range(8)
 F64, F32 = 0, 1
 KEEP_F32 = 1
 COO_REMAINDER = 2   # hec_from_csr flag: remainder as COO (HYB = ELL + COO)
@@ -31,7 +31,8 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve", "cg_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched",
             "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy",
-            "hec_set_allocator", "hec_footprint", "hec_last_error")
+            "hec_set_allocator", "hec_footprint", "hec_set_spin_limit", "levels_check",
+            "hec_last_error")
 BATCH_MAX_N = 8192
 
 
@@ -115,6 +116,8 @@ def load(path: str = LIB_PATH):
     L.amg_destroy.argtypes = [_vp]
     L.hec_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, _vp]
     L.hec_footprint.argtypes = [_vp, _vp, _vp, _i64p]
+    L.hec_set_spin_limit.argtypes = [C.c_int64]
+    L.levels_check.argtypes = [_vp, _vp]
     for name in EXPORTED:
         if name != "hec_last_error":
             getattr(L, name).restype = C.c_int
@@ -144,7 +147,9 @@ def set_allocator(alloc=None, free=None):
     def _a(ctx, nbytes, stream):
         try:
             return alloc(int(nbytes), int(stream or 0)) or None
-        except Exception:
+        except Exception as e:  # the library reports NOMEM; the reason is kept for the message
+            _alloc_errors.append(f"{type(e).__name__}: {e}")
+            del _alloc_errors[:-4]
             return None
 
     def _f(ctx, ptr, nbytes, stream):
@@ -157,6 +162,7 @@ def set_allocator(alloc=None, free=None):
 
 
 _all_hooks = []  # every callback pair ever set: buffers are freed by the hooks that made them
+_alloc_errors = []  # the last exceptions raised by an allocation hook
 
 
 def _torch_hooks():
@@ -192,6 +198,18 @@ def use_torch_allocator():
     set_allocator(*_torch_hooks())
 
 
+def set_spin_limit(polls: int = -1):
+    """hec_set_spin_limit: polls a device-side wait of the triangular solves makes before
+    it gives up (negative: the default)."""
+    _check(load().hec_set_spin_limit(int(polls)), "hec_set_spin_limit")
+
+
+def levels_check(lv, stream=None):
+    """levels_check: synchronises the stream; raises HecError(TIMEOUT) if a wait of lv's
+    triangular solves gave up since the last check."""
+    _check(load().levels_check(lv.ptr, _stream(stream)), "levels_check")
+
+
 def footprint(A=None, M=None, lv=None) -> int:
     """hec_footprint: device bytes held by a matrix (its solver workspace included), a
     factor and a schedule."""
@@ -203,7 +221,11 @@ def footprint(A=None, M=None, lv=None) -> int:
 
 def _check(code: int, where: str):
     if code != OK:
-        raise HecError(code, where, load().hec_last_error().decode())
+        msg = load().hec_last_error().decode()
+        if code == NOMEM and _alloc_errors:
+            msg += f" (allocation hook: {_alloc_errors[-1]})"
+            _alloc_errors.clear()
+        raise HecError(code, where, msg)
 
 
 def _stream(stream):
