@@ -259,6 +259,25 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
 hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
                        const hec_solve_opts *opts, hec_solve_info *info, void *stream);
 
+/* Largest system (rows) gmres_solve_noalloc accepts. */
+#define HEC_NOALLOC_MAX_N 16384
+
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * elsewhere on the stream, tight serving loops, harnesses that forbid hipMalloc):
+ * gmres_solve with the same arguments, method, kernels and results (FP64 only:
+ * precision must be 0; restart in [1, 32]; n <= HEC_NOALLOC_MAX_N, INVALID_ARG
+ * otherwise), whose workspace -- Krylov basis, preconditioned basis, scalars,
+ * partial sums, flags: about 9.7 MB -- is a static device array of the library
+ * instead of memory allocated at the first solve. It calls no hipMalloc, hipFree,
+ * host-pinned allocation or allocator hook, and creates no events (whole cycles
+ * are queued; the scalars are read by plain copies). Each GPU holds one copy of
+ * the array for the life of the process, and every call on that GPU shares it:
+ * calls that overlap in time on one GPU (other threads, other streams) race and
+ * must be serialised by the caller. The handles must already exist (their setup
+ * calls allocate). */
+hec_status gmres_solve_noalloc(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                               const hec_solve_opts *opts, hec_solve_info *info, void *stream);
+
 /* Preconditioned BiCGSTAB exactly as Alg. 4 (shadow residual r0 = b - A x0),
  * "||s|| / ||r|| satisfied" read as <= rtol * ||b||; rho == 0 or (r0, v) == 0 is
  * a breakdown. When a cycle stops (breakdown, or a recurrence residual below rtol

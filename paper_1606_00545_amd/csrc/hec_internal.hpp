@@ -111,18 +111,27 @@ struct DevBuf {
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), st(o.st), al(o.al), owner(o.owner) {
+    bool borrowed = false;  // a view of memory owned elsewhere: never freed or counted here
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), st(o.st), al(o.al), owner(o.owner), borrowed(o.borrowed) {
         o.p = nullptr;
         o.n = 0;
         o.owner = nullptr;
+        o.borrowed = false;
     }
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; st = o.st; al = o.al; owner = o.owner;
-            o.p = nullptr; o.n = 0; o.owner = nullptr;
+            p = o.p; n = o.n; st = o.st; al = o.al; owner = o.owner; borrowed = o.borrowed;
+            o.p = nullptr; o.n = 0; o.owner = nullptr; o.borrowed = false;
         }
         return *this;
+    }
+    // Points the buffer at `count` elements of memory owned elsewhere (no allocation).
+    void borrow(T *ptr, size_t count) {
+        release();
+        p = ptr;
+        n = count;
+        borrowed = true;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
@@ -137,13 +146,14 @@ struct DevBuf {
         }
     }
     void release() {
-        if (p) {
+        if (p && !borrowed) {
             dev_free(p, n * sizeof(T), st, al);
             if (owner) *owner -= (int64_t)(n * sizeof(T));
         }
         p = nullptr;
         n = 0;
         owner = nullptr;
+        borrowed = false;
     }
     void upload(const T *h, size_t count, hipStream_t s) {
         if (count) HEC_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));

@@ -1027,6 +1027,72 @@ static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const dou
     if (!(res / bnorm <= target)) fail(HEC_ERR_NOT_CONVERGED, "GMRES did not reach the tolerance");
 }
 
+// ---------------------------------------------------------------- workspace without allocation
+// gmres_solve_noalloc keeps its workspace (basis, preconditioned basis, w, r,
+// scalars, partial sums, flags) in this file-scope array instead of allocating it.
+// In host code `scratch` only names the symbol: its device address, one per GPU,
+// comes from hipGetSymbolAddress on the first call made with that device current.
+constexpr int64_t kNoAllocLdv = HEC_NOALLOC_MAX_N + HEC_BASIS_PAD;  // widest basis vector (n rounded to 64)
+constexpr int64_t kNoAllocSd = 2048;                                // scalars + Hessenberg (GLayout(32) needs 1265)
+constexpr int64_t kNoAllocPart = 2048;                              // partial sums: nred * 33 (32 * 33 at most)
+constexpr int64_t kNoAllocSi = 64;                                  // SI_COUNT int32 flags, in doubles
+constexpr int64_t kNoAllocDoubles = (2 * kMaxRestart + 3) * kNoAllocLdv + kNoAllocSd + kNoAllocPart + kNoAllocSi;
+static_assert(HEC_NOALLOC_MAX_N % 64 == 0, "the no-allocation bound keeps basis vectors 64-aligned");
+static_assert(SI_COUNT * sizeof(int32_t) <= kNoAllocSi * sizeof(double), "flags fit");
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up once per device).
+static double *scratch_address() {
+    int dev = 0;
+    HEC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(HEC_ERR_INVALID_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HEC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(HEC_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// A workspace of views into the scratch array (n <= HEC_NOALLOC_MAX_N, FP64 basis of
+// m + 1 vectors): no mapped flags and no events, so the driver queues whole cycles and
+// reads the flags and scalars by plain copies. The flags are cleared (with a fill
+// kernel); everything else is written before it is read.
+static void noalloc_workspace(KrylovWS &ws, int64_t n, int m, hipStream_t s) {
+    double *base = scratch_address();
+    ws.n = n;
+    ws.ldv = (n + 63) / 64 * 64 + HEC_BASIS_PAD;
+    ws.m = m;
+    ws.nred = red_blocks(n);
+    const int64_t ldv = ws.ldv;
+    if (GLayout(m).total > kNoAllocSd || (int64_t)ws.nred * (kMaxRestart + 1) > kNoAllocPart || ldv > kNoAllocLdv)
+        fail(HEC_ERR_INVALID_ARG, "system too large for the no-allocation scratch");
+    double *q = base;
+    ws.V.borrow(q, (size_t)(m + 1) * ldv);
+    q += (m + 1) * ldv;
+    ws.Z.borrow(q, (size_t)m * ldv);
+    q += m * ldv;
+    ws.w.borrow(q, ldv);
+    q += ldv;
+    ws.r.borrow(q, ldv);
+    q = base + (2 * kMaxRestart + 3) * kNoAllocLdv;
+    ws.sd.borrow(q, kNoAllocSd);
+    q += kNoAllocSd;
+    ws.part.borrow(q, kNoAllocPart);
+    q += kNoAllocPart;
+    ws.si.borrow((int32_t *)q, SI_COUNT);
+    ws.hsd = ws.hsd_plain;
+    k_fill<int32_t><<<1, 256, 0, s>>>(SI_COUNT, ws.si.get(), 0);
+    HEC_CHECK_LAUNCH();
+}
+
 }  // namespace hec
 
 using namespace hec;
@@ -1050,6 +1116,33 @@ hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, 
         inf.status = HEC_OK;
         if (n == 0) return;
         KrylovWS &ws = get_ws(*A, o->restart, mixed, false, s);
+        gmres_run(*A, *lv, ws, b, x, o, inf, s);
+    });
+    inf.status = st;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
+}
+
+hec_status gmres_solve_noalloc(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,
+                               const hec_solve_opts *o, hec_solve_info *info, void *stream) {
+    hec_solve_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+    hec_status st = guarded([&] {
+        check_solve_args(A, M, lv, b, x, o);
+        if (o->restart < 1 || o->restart > kMaxRestart)
+            fail(HEC_ERR_INVALID_ARG, "restart must be in [1, 32]");
+        if (o->precision != 0) fail(HEC_ERR_INVALID_ARG, "gmres_solve_noalloc runs in FP64 only (precision 0)");
+        if (A->n > HEC_NOALLOC_MAX_N)
+            fail(HEC_ERR_INVALID_ARG, "gmres_solve_noalloc: n = " + std::to_string(A->n) +
+                                          " exceeds its static scratch (at most " +
+                                          std::to_string(HEC_NOALLOC_MAX_N) + " rows)");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = A->n;
+        inf.status = HEC_OK;
+        if (n == 0) return;
+        KrylovWS ws;
+        noalloc_workspace(ws, n, o->restart, s);
         gmres_run(*A, *lv, ws, b, x, o, inf, s);
     });
     inf.status = st;

@@ -31,9 +31,10 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "trsv_levels", "gmres_solve", "bicgstab_solve", "cg_solve",
             "batch_create", "batch_destroy", "gmres_solve_batched",
             "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy",
-            "hec_set_allocator", "hec_footprint", "hec_set_spin_limit", "levels_check",
+            "hec_set_allocator", "hec_footprint", "gmres_solve_noalloc", "hec_set_spin_limit", "levels_check",
             "hec_last_error")
 BATCH_MAX_N = 8192
+NOALLOC_MAX_N = 16384
 
 
 class HecError(RuntimeError):
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
     L.gmres_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _vp]
     L.bicgstab_solve.argtypes = L.gmres_solve.argtypes
     L.cg_solve.argtypes = L.gmres_solve.argtypes
+    L.gmres_solve_noalloc.argtypes = L.gmres_solve.argtypes
     L.batch_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_vp)]
     L.batch_destroy.argtypes = [_vp]
     L.gmres_solve_batched.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts),
@@ -481,6 +483,19 @@ def gmres_solve(A: Matrix, M: Factor, lv: Levels, b, x, restart: int = 30, maxit
                               C.byref(o), C.byref(info), _stream(stream))
     if check and code != OK:
         _check(code, "gmres_solve")
+    return info.as_dict()
+
+
+def gmres_solve_noalloc(A: Matrix, M: Factor, lv: Levels, b, x, restart: int = 30, maxit: int = 10000,
+                        rtol: float = 1e-8, x0_zero: bool = True, stream=None, check: bool = True) -> dict:
+    """gmres_solve (FP64) with the library's static scratch as workspace: allocates nothing."""
+    import torch
+    o = _opts(restart, maxit, rtol, 0, x0_zero, 0.0, 0.0)
+    info = SolveInfo()
+    code = load().gmres_solve_noalloc(A.ptr, M.ptr, lv.ptr, _dev(b, A.n, torch.float64, "b"),
+                                      _dev(x, A.n, torch.float64, "x"), C.byref(o), C.byref(info), _stream(stream))
+    if check and code != OK:
+        _check(code, "gmres_solve_noalloc")
     return info.as_dict()
 
 
