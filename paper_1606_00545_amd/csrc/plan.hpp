@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstddef>
@@ -42,13 +43,16 @@ constexpr int kPad = INT_MIN;     // padding entry of a row shorter than K
 #ifndef HEC_TRSV_TILE
 #define HEC_TRSV_TILE 0
 #endif
+#ifndef HEC_TRSV_SHEAR
+#define HEC_TRSV_SHEAR 1  // 0: grid tiles on the x-y axes only (sheared axes off)
+#endif
 constexpr int kTargetParts = HEC_TRSV_TARGET_PARTS;  // contiguous parts: about this many ...
 constexpr int kMinPartRows = HEC_TRSV_MIN_PART_ROWS;  // ... of at least this many rows
 constexpr int kTileParts = HEC_TRSV_TILE_PARTS;      // grid tiles: at most about this many
 constexpr int kMaxRing = HEC_TRSV_MAX_RING;          // most LDS slots in the ring
 constexpr int kMaxSolvers = 8;                       // solver wavefronts per workgroup: 1, 2, 4 or 8 ...
 constexpr int kSolvers = HEC_TRSV_SOLVERS;           // ... the kernels are built for (the planner's default)
-constexpr int kTile = HEC_TRSV_TILE;                 // grid tile side (0: from the part count)
+constexpr int kTile = HEC_TRSV_TILE;                 // grid tile side (0: the planner chooses)
 static_assert(kSolvers == 1 || kSolvers == 2 || kSolvers == 4 || kSolvers == 8, "solver count");
 
 HEC_HD constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
@@ -66,10 +70,10 @@ struct Slot {
     HEC_HD size_t bytes() const { return align16(a() + (size_t)KC * kSub * sizeof(int)); }
 };
 
-// LDS: [done[kMaxSolvers] | filled[D] | part | zero (16 B)] [part's sub-segment
-//      starts, S+1] [their dependency bounds, S+1, with NS > 1 only] [ring of
-//      recent results, W] [D slots]
-HEC_HD inline size_t ctrl_head(int D) { return align16((size_t)(kMaxSolvers + D + 1) * sizeof(int)) + 16; }
+// LDS: [done[kMaxSolvers] | filled[D] | part | abort | zero (16 B)] [part's
+//      sub-segment starts, S+1] [their dependency bounds, S+1, with NS > 1 only]
+//      [ring of recent results, W] [D slots]
+HEC_HD inline size_t ctrl_head(int D) { return align16((size_t)(kMaxSolvers + D + 2) * sizeof(int)) + 16; }
 HEC_HD inline size_t ss_bytes(int S) { return align16((size_t)(S + 1) * sizeof(int)); }
 HEC_HD inline size_t ctrl_bytes(int D, int S, int NS) { return ctrl_head(D) + (NS > 1 ? 2 : 1) * ss_bytes(S); }
 
@@ -152,11 +156,157 @@ inline void detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t
     nz = (int32_t)Z;
 }
 
+// Tile axes of a grid triangle: two combinations a = ca . (x, y, z), b = cb . (x, y, z)
+// with coefficients in 0..cmax such that every dependency of the triangle sits at a
+// and b no larger (lower triangle; no smaller for the upper one). Tiles T wide in a
+// and in b, numbered b-tile major, then never wait on a later tile. Among the valid
+// pairs, the one whose tiles (at about `target` of them) are crossed least often by a
+// path through the grid: about (range_a + range_b) / T boundaries, T = sqrt(count /
+// target) with `count` the (a, b) pairs that hold a cell (ranked by the bound
+// min((range_a + 1)(range_b + 1), n), counted exactly for the chosen pair). For ILU(0) of a 7-point
+// stencil this is (x, y), the x-y pencils; ILU(1) fill (row x depends on x + 1 in
+// the plane below) rules x-y pencils out, and a sheared pair such as (x + y + z, z)
+// takes over. Returns false when no pair is valid.
+struct TileAxes {
+    int ca[3] = {1, 0, 0}, cb[3] = {0, 1, 0};
+    int32_t T = 1;
+    int64_t ra = 0, rb = 0;  // largest a and b on the grid (both start at 0)
+};
+
+inline bool choose_tile_axes(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
+                             int32_t gny, int32_t gnz, bool upper, int64_t target, TileAxes &best) {
+    // the triangle's dependency offsets (dx, dy, dz), each once: the distinct index
+    // offsets j - i first, each with a row that has it (a grid factor's entries join
+    // grid neighbours, so an index offset stands for one grid offset)
+    std::vector<std::pair<int32_t, int32_t>> off;  // (j - i, i)
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t a = upper ? diag[i] + 1 : LUp[i], b = upper ? LUp[i + 1] : diag[i];
+        for (int32_t e = a; e < b; ++e) {
+            const int32_t o = LUj[e] - i;
+            bool have = false;
+            for (const auto &w : off) have = have || w.first == o;
+            if (!have) {
+                if (off.size() >= 256) return false;
+                off.push_back({o, i});
+            }
+        }
+    }
+    std::vector<std::array<int, 3>> D;
+    for (const auto &w : off) {
+        const int32_t i = w.second, j = i + w.first;
+        const std::array<int, 3> d{j % gnx - i % gnx, (j / gnx) % gny - (i / gnx) % gny,
+                                   j / (gnx * gny) - i / (gnx * gny)};
+        if (std::find(D.begin(), D.end(), d) == D.end()) D.push_back(d);
+    }
+    const int sg = upper ? -1 : 1;
+    double best_score = 0.0;
+    bool found = false;
+    for (int cmax = 1; cmax <= 2 && !found; ++cmax) {
+        std::vector<std::array<int, 3>> C;  // valid coefficient vectors, (1,0,0) and (0,1,0) first
+        for (int c2 = 0; c2 <= cmax; ++c2)
+            for (int c1 = 0; c1 <= cmax; ++c1)
+                for (int c0 = 0; c0 <= cmax; ++c0) {
+                    if (!c0 && !c1 && !c2) continue;
+                    if (!HEC_TRSV_SHEAR && c0 + c1 + c2 != 1) continue;
+                    bool ok = true;
+                    for (const auto &d : D) ok = ok && sg * (c0 * d[0] + c1 * d[1] + c2 * d[2]) <= 0;
+                    if (ok) C.push_back({c0, c1, c2});
+                }
+        for (size_t u = 0; u < C.size(); ++u)
+            for (size_t v = u + 1; v < C.size(); ++v) {
+                const auto &p = C[u], &q = C[v];
+                const int64_t cx = (int64_t)p[1] * q[2] - (int64_t)p[2] * q[1],
+                              cy = (int64_t)p[2] * q[0] - (int64_t)p[0] * q[2],
+                              cz = (int64_t)p[0] * q[1] - (int64_t)p[1] * q[0];
+                if (!cx && !cy && !cz) continue;  // parallel: not two axes
+                const int64_t ra = (int64_t)p[0] * (gnx - 1) + (int64_t)p[1] * (gny - 1) + (int64_t)p[2] * (gnz - 1);
+                const int64_t rb = (int64_t)q[0] * (gnx - 1) + (int64_t)q[1] * (gny - 1) + (int64_t)q[2] * (gnz - 1);
+                const double bound = (double)std::min<int64_t>((ra + 1) * (rb + 1), n);
+                const double score = (double)(ra + rb) / std::max(1.0, std::sqrt(bound / (double)target));
+                if (!found || score < best_score) {
+                    found = true;
+                    best_score = score;
+                    for (int k = 0; k < 3; ++k) {
+                        best.ca[k] = p[k];
+                        best.cb[k] = q[k];
+                    }
+                    best.ra = ra;
+                    best.rb = rb;
+                }
+            }
+    }
+    if (!found) return false;
+    // the (a, b) pairs that hold a cell, for the tile side
+    std::vector<uint8_t> seen((size_t)((best.ra + 1) * (best.rb + 1)), 0);
+    int64_t count = 0;
+    for (int32_t z = 0; z < gnz; ++z)
+        for (int32_t y = 0; y < gny; ++y)
+            for (int32_t x = 0; x < gnx; ++x) {
+                const int64_t a = (int64_t)best.ca[0] * x + (int64_t)best.ca[1] * y + (int64_t)best.ca[2] * z;
+                const int64_t b = (int64_t)best.cb[0] * x + (int64_t)best.cb[1] * y + (int64_t)best.cb[2] * z;
+                uint8_t &f = seen[(size_t)(a * (best.rb + 1) + b)];
+                count += !f;
+                f = 1;
+            }
+    best.T = (int32_t)std::max<int64_t>(1, std::lround(std::sqrt((double)count / (double)target)));
+    return true;
+}
+
+// Tile side for the chosen axes. A path through the triangle runs through every
+// level; inside a tile a level takes ceil(rows / kSub) solver steps, and each tile
+// boundary the path crosses, about (ra + rb) / T of them, costs about kHopSteps
+// steps more (a result handed between workgroups arrives some eight solver steps
+// after it was solved, measured at 128^3, one of which overlaps). Sides from
+// tmax down are tried, tmax the side that gives about `target` tiles (fewer tiles
+// would idle workgroups), while the hops alone still beat the best cost so far.
+constexpr int kHopSteps = 7;
+
+inline int32_t choose_tile_side(int32_t n, const std::vector<int32_t> &lev, int32_t nlev, const std::vector<int32_t> &ga,
+                                const std::vector<int32_t> &gb, const TileAxes &ax, int32_t tmax) {
+    int32_t best = std::max<int32_t>(1, tmax);
+    double best_cost = 0.0;
+    std::vector<int32_t> lo, hi, cnt;
+    std::vector<int64_t> off;
+    for (int32_t T = best; T >= std::max<int32_t>(1, tmax / 4); --T) {
+        const double hops = (double)(ax.ra + ax.rb) / T;
+        if (T < best && nlev + kHopSteps * hops >= best_cost) break;
+        const int64_t PA = ax.ra / T + 1, PB = ax.rb / T + 1, nt = PA * PB;
+        lo.assign((size_t)nt, INT_MAX);
+        hi.assign((size_t)nt, -1);
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t t = ga[i] / T + PA * (gb[i] / T);
+            lo[(size_t)t] = std::min(lo[(size_t)t], lev[i]);
+            hi[(size_t)t] = std::max(hi[(size_t)t], lev[i]);
+        }
+        off.assign((size_t)nt + 1, 0);
+        for (int64_t t = 0; t < nt; ++t) off[(size_t)t + 1] = off[(size_t)t] + (hi[(size_t)t] >= 0 ? hi[(size_t)t] - lo[(size_t)t] + 1 : 0);
+        if (off[(size_t)nt] > 8 * (int64_t)n) continue;  // levels scattered over the tiles: not a candidate
+        cnt.assign((size_t)off[(size_t)nt], 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t t = ga[i] / T + PA * (gb[i] / T);
+            ++cnt[(size_t)(off[(size_t)t] + lev[i] - lo[(size_t)t])];
+        }
+        int64_t groups = 0, steps = 0;
+        for (int32_t c : cnt)
+            if (c) {
+                ++groups;
+                steps += (c + kSub - 1) / kSub;
+            }
+        const double cost = (double)nlev * (double)steps / (double)std::max<int64_t>(1, groups) + kHopSteps * hops;
+        if (T == tmax || cost < best_cost) {
+            best = T;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 // The blocked execution plan of one triangle.
-//  * Parts: with a recognised grid, x-y tiles spanning all z (about kTileParts
-//    of them) numbered in the order the triangle is solved, kept only if every
-//    dependency then lies in the same or an earlier part; otherwise contiguous
-//    row ranges in that order. Parts are claimed in order at run time.
+//  * Parts: with a recognised grid, tiles of two axes (choose_tile_axes: x-y
+//    pencils spanning all z for ILU(0), sheared prisms for fill), about
+//    kTileParts of them, numbered in the order the triangle is solved, kept only
+//    if every dependency then lies in the same or an earlier part; otherwise
+//    contiguous row ranges in that order. Parts are claimed in order at run time.
 //  * Positions: each part's rows at consecutive positions, by (level, row).
 //  * Sub-segments: runs of one level inside a part, at most kSub rows.
 //  * enc[s*ldq + q]: the dependency of entry s of position q: -(local position
@@ -186,7 +336,8 @@ struct HostPlan {
 
 inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                       int32_t gny, int32_t gnz, bool upper, bool has_f32, int64_t lds_max, HostPlan &P,
-                      bool flat = false, const std::vector<int32_t> *blocks = nullptr, int solvers = kSolvers) {
+                      bool flat = false, const std::vector<int32_t> *blocks = nullptr, int solvers = kSolvers,
+                      int32_t tile = 0) {
     P = HostPlan();
     P.n = n;
     P.nlev = compute_levels(n, LUp, LUj, diag, upper, P.level_ptr, P.perm, &P.lev);
@@ -235,22 +386,36 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
             }
         } else if (gnx > 0 && (int64_t)gnx * gny * gnz == n && n >= 2 * kMinPartRows) {
             const int64_t target = std::min<int64_t>(kTileParts, n / kMinPartRows);
-            const int64_t plane = (int64_t)gnx * gny;
-            int64_t T = std::max<int64_t>(1, (int64_t)std::lround(std::sqrt((double)plane / (double)target)));
-            // the tile side comes from the part count alone: widening tiles so that a level
-            // fills every solver wavefront lengthens each tile's lead on its neighbours
-            // (measured slower at 128^3 ILU(0)); where levels are wide anyway (ILU(k > 0))
-            // the planner's solver count below takes them
-            if (kTile > 0) T = kTile;
-            const int32_t tx = (int32_t)std::min<int64_t>(T, gnx), ty = (int32_t)std::min<int64_t>(T, gny);
-            const int32_t PX = (gnx + tx - 1) / tx, PY = (gny + ty - 1) / ty;
-            ntiles = PX * PY;
-            for (int32_t i = 0; i < n; ++i) {
-                int32_t xx = i % gnx, yy = (i / gnx) % gny;
-                int32_t t = xx / tx + PX * (yy / ty);
-                part_of[i] = upper ? ntiles - 1 - t : t;
+            TileAxes ax;
+            if (choose_tile_axes(n, LUp, LUj, diag, gnx, gny, gnz, upper, target, ax)) {
+                // each row's coordinates on the two axes
+                std::vector<int32_t> ga(n), gb(n);
+                for (int32_t i = 0; i < n; ++i) {
+                    const int64_t xx = i % gnx, yy = (i / gnx) % gny, zz = i / ((int64_t)gnx * gny);
+                    ga[i] = (int32_t)(ax.ca[0] * xx + ax.ca[1] * yy + ax.ca[2] * zz);
+                    gb[i] = (int32_t)(ax.cb[0] * xx + ax.cb[1] * yy + ax.cb[2] * zz);
+                }
+                // no wider than the part count allows: wider tiles hold levels of more than
+                // kSub rows and lengthen each tile's lead on its neighbours (measured slower
+                // at 128^3 ILU(0)); narrower where the steps saved outweigh the extra hops
+                // (sheared ILU(1) tiles: 8 instead of 17 at 192^3, measured)
+                const int32_t T = tile > 0 ? tile : kTile > 0 ? kTile : choose_tile_side(n, P.lev, P.nlev, ga, gb, ax, ax.T);
+                const int64_t PA = ax.ra / T + 1, PB = ax.rb / T + 1;
+                // tile index b-major, then empty tiles dropped (numbering kept in order)
+                std::vector<int32_t> tid((size_t)(PA * PB), -1);
+                for (int32_t i = 0; i < n; ++i) {
+                    const int64_t t = ga[i] / T + PA * (gb[i] / T);
+                    part_of[i] = (int32_t)t;
+                    tid[(size_t)t] = 0;
+                }
+                for (size_t t = 0; t < tid.size(); ++t)
+                    if (tid[t] == 0) tid[t] = ntiles++;
+                for (int32_t i = 0; i < n; ++i) {
+                    const int32_t t = tid[(size_t)part_of[i]];
+                    part_of[i] = upper ? ntiles - 1 - t : t;
+                }
+                tiled = ntiles > 1;
             }
-            tiled = ntiles > 1;
             for (int32_t i = 0; i < n && tiled; ++i) {
                 int32_t a, b;
                 deps(i, a, b);

@@ -17,11 +17,12 @@ extern "C" {
 // lds_max bytes of LDS per workgroup; flat != 0 asks for the level-order layout;
 // blocks (nbounds entries, may be NULL): first rows of independent row blocks
 // followed by n, to be used as parts; solvers: solver wavefronts per workgroup
-// for parts with wide levels (1, 2, 4 or 8; 0: the library's default). Returns
-// NULL on allocation failure or a bad solver count.
+// for parts with wide levels (1, 2, 4 or 8; 0: the library's default); tile: the
+// side of grid tiles (0: the planner's choice). Returns NULL on allocation
+// failure or a bad solver count.
 void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                    int32_t gny, int32_t gnz, int32_t upper, int32_t has_f32, int64_t lds_max, int32_t flat,
-                   const int32_t *blocks, int32_t nbounds, int32_t solvers) {
+                   const int32_t *blocks, int32_t nbounds, int32_t solvers, int32_t tile) {
     if (solvers == 0) solvers = hec::plan::kSolvers;
     if (solvers != 1 && solvers != 2 && solvers != 4 && solvers != 8) return nullptr;
     HostPlan *P = new (std::nothrow) HostPlan();
@@ -30,7 +31,7 @@ void *hecplan_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int3
         std::vector<int32_t> bv;
         if (blocks && nbounds > 0) bv.assign(blocks, blocks + nbounds);
         hec::plan::make_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, has_f32 != 0, lds_max, *P, flat != 0,
-                             bv.empty() ? nullptr : &bv, solvers);
+                             bv.empty() ? nullptr : &bv, solvers, tile < 0 ? 0 : tile);
     } catch (...) {
         delete P;
         return nullptr;

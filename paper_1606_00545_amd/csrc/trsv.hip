@@ -184,6 +184,11 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
     const int wave = threadIdx.x >> 6;
     if (threadIdx.x < 4) ((int *)(smem + zero_off))[threadIdx.x] = 0;
     if (threadIdx.x == 0) *s_abort = 0;
+    // every slot's dependency addresses start at the zero word: a solver that gave up a
+    // wait may still read the header of a slot that was never filled (the reads stay in
+    // range; nothing it computes is published)
+    for (int t = threadIdx.x; t < D * KC * kSub; t += blockDim.x)
+        ((uint32_t *)(smem + slots_off + (t / (KC * kSub)) * sb + L.a()))[t % (KC * kSub)] = zero_off;
     // A wait that has spun `spin` times gives up: it marks the workgroup and the device.
     // Waves of the workgroup see the mark within 64 polls; other workgroups' long polls
     // look at the device's error word as often.
@@ -194,18 +199,16 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
     };
     auto wg_aborted = [&]() { return __hip_atomic_load(s_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0; };
     // one more poll of a wait: true when the wait must stop (given up here or elsewhere).
-    // Called in wave-uniform control flow only, so a wave stops as a whole.
+    // Called in wave-uniform control flow only, so a wave stops as a whole; the answer
+    // is made a scalar (read from the first lane) so that the compiler keeps the loops
+    // and flags that depend on it uniform (scalar branches, no exec-mask bookkeeping)
     auto spun_out = [&](uint32_t &it, bool device_wide) {
         ++it;
-        if (it > P.spin) {
-            give_up();
-            return true;
-        }
-        if ((it & 63) == 0 && (wg_aborted() || (device_wide && timed_out(P.err)))) {
-            give_up();
-            return true;
-        }
-        return false;
+        bool stop = it > P.spin;
+        if (!stop && (it & 63) == 0) stop = wg_aborted() || (device_wide && timed_out(P.err));
+        stop = __builtin_amdgcn_readfirstlane((int)stop) != 0;
+        if (stop) give_up();
+        return stop;
     };
 
     for (;;) {
@@ -342,20 +345,24 @@ __global__ __launch_bounds__(kBlkThreads) void k_trsv_blk(PlanArgs P, const T *_
                 }
                 if (kPipe && !pre && rel + NS < nss) {
                     ready = scan(rel + NS, nslot);
-                    if (!bail) load_head(rel + NS, nslot, nxt);
+                    load_head(rel + NS, nslot, nxt);  // (after a give-up: read, never used)
                 }
                 return nslot;
             };
             int slot = w0 % D;
             if constexpr (kPipe) {
+                // A give-up is looked at once per pair of steps: the data flow between the
+                // two register sets stays the same on every path (a check between the
+                // steps made the compiler copy one set into the other, measured 7% slower
+                // on the 128^3 pair); the second step of a pair then publishes nothing.
                 Head h0, h1;
                 if (w0 < nss) {
                     ready = scan(w0, slot);
-                    if (!bail) load_head(w0, slot, h0);
+                    load_head(w0, slot, h0);
                 }
                 for (int rel = w0; rel < nss && !bail; rel += 2 * NS) {
                     slot = step(rel, slot, h0, h1);
-                    if (rel + NS < nss && !bail) slot = step(rel + NS, slot, h1, h0);
+                    if (rel + NS < nss) slot = step(rel + NS, slot, h1, h0);
                 }
             } else {
                 for (int rel = w0; rel < nss; rel += NS) {

@@ -24,7 +24,7 @@ def lib():
         ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         L.hecplan_make.restype = C.c_void_p
         L.hecplan_make.argtypes = [C.c_int32, ip, ip, ip, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                   C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_int32]
+                                   C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
         L.hecplan_meta.argtypes = [C.c_void_p, np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
         L.hecplan_array.restype = C.c_int64
         L.hecplan_array.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p]
@@ -53,15 +53,17 @@ def diag_positions(F):
     return d
 
 
-def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=False, blocks=None, solvers=0):
+def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=False, blocks=None, solvers=0,
+              tile=0):
     """Plan of one triangle of the factor F (oracle Factor) as a dict of meta values and arrays
-    (solvers: solver wavefronts per workgroup for wide levels, 0: the library's default)."""
+    (solvers: solver wavefronts per workgroup for wide levels, 0: the library's default;
+    tile: grid tile side, 0: the planner's choice)."""
     L = lib()
     diag = diag_positions(F)
     bl = None if blocks is None else _i32(blocks)
     h = L.hecplan_make(F.n, _i32(F.LUp), _i32(F.LUj), diag, grid[0], grid[1], grid[2], int(upper),
                        int(has_f32), lds_max, int(flat), None if bl is None else bl.ctypes.data,
-                       0 if bl is None else bl.size, solvers)
+                       0 if bl is None else bl.size, solvers, tile)
     assert h, "planner failed"
     try:
         meta = np.zeros(17, np.int64)

@@ -8,7 +8,8 @@ oracle, every plan is checked for what the solve kernels rely on:
 * positions are a permutation; each part holds its rows by (level, row); each
   sub-segment is one level of one part with at most 64 rows;
 * every dependency outside a part lies in an earlier part (parts are claimed in
-  order, so a workgroup only waits for parts already running: no deadlock);
+  order, so a workgroup only waits for parts already running: no deadlock), also
+  for the sheared tiles that grids with ILU(k > 0) fill get;
 * the plan's LDS footprint fits the workgroup limit;
 
 and then replayed on the host in the order the kernels execute it, reading each
@@ -44,10 +45,13 @@ def sparse_random(n, per_row, seed):
 def _cases():
     yield "poisson2d_64_k0", lambda: synth.poisson2d(64), 0, {}
     yield "poisson3d_32_k0", lambda: synth.poisson3d(32), 0, {"tiled": True}
-    yield "poisson3d_24_k1", lambda: synth.poisson3d(24), 1, {}
+    # ILU(1) and ILU(2) fill rule out x-y pencils; sheared tiles (e.g. x + y + z by z) take over
+    yield "poisson3d_24_k1", lambda: synth.poisson3d(24), 1, {"tiled": True}
+    yield "poisson3d_22_k2", lambda: synth.poisson3d(22), 2, {"tiled": True}
     yield "tpfa3d_41x37x23_k0", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0, \
         {"tiled": True}
-    yield "tpfa3d_41x37x23_k1", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 1, {}
+    yield "tpfa3d_41x37x23_k1", lambda: synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 1, \
+        {"tiled": True}
     yield "tpfa2d_301x97_k2", lambda: synth.lognormal_tpfa((301, 97), 1.5, np.random.default_rng(7)), 2, {}
     yield "random_20000_k1", lambda: sparse_random(20000, 8, 8), 1, {}
     yield "powerlaw_20000_k0", lambda: synth.powerlaw_random(20000, np.random.default_rng(9)), 0, \
@@ -403,16 +407,17 @@ def test_plan_structure_and_replay(factors, name):
                                           ("random_20000_k1", 4), ("poisson2d_64_k0", 4)])
 def test_multi_solver_plans(factors, name, solvers):
     """Plans with several solver wavefronts per workgroup: taken on 3D grids whose tile
-    levels span several sub-segments, the dependency bounds and ring size checked, and
-    the solve replayed under adversarial interleavings of the solvers, bit for bit
-    against the oracle."""
+    levels span several sub-segments (tiles 12 wide, wider than the planner picks, so
+    that a level holds up to 144 rows of a tile), the dependency bounds and ring size
+    checked, and the solve replayed under adversarial interleavings of the solvers,
+    bit for bit against the oracle."""
     A, F, opt = factors(name)
     grid = _plan.detect_grid(A)
     b = np.random.default_rng(11).uniform(-1, 1, A.n)
     y_o = O.trsv_lower(F, b)
     x_o = O.trsv_upper(F, y_o)
     for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
-        P = _plan.make_plan(F, upper, grid, solvers=solvers)
+        P = _plan.make_plan(F, upper, grid, solvers=solvers, tile=12)
         if name.startswith(("poisson3d", "tpfa3d")) and name.endswith("k0"):
             assert P["NS"] == solvers  # 3D 7-point tiles: levels span several sub-segments
         if name.startswith("poisson2d"):
@@ -424,6 +429,30 @@ def test_multi_solver_plans(factors, name, solvers):
             for policy, seed in (("late", 0), ("early", 0), ("random", 1), ("random", 2)):
                 x = replay_concurrent(P, F, rhs, upper, policy, seed)
                 assert np.array_equal(x.view(np.uint64), ref.view(np.uint64)), policy
+
+
+@pytest.mark.parametrize("name,k", [("poisson3d_32_k0", 0), ("tpfa3d_41x37x23_k0", 0), ("poisson3d_24_k1", 1)])
+def test_tile_side(factors, name, k):
+    """The tile side the planner picks on a grid: no wider than the part count allows, and
+    narrow enough that a tile's level mostly fits one solver wavefront (64 rows); on a
+    7-point ILU(0) factor (levels x + y + z) a tile T wide holds at most T^2 rows of a
+    level, so T = 8 exactly fills it and every level of every part is one sub-segment."""
+    A, F, opt = factors(name)
+    grid = _plan.detect_grid(A)
+    for upper in (False, True):
+        P = _plan.make_plan(F, upper, grid)
+        lev, grow, pp = P["lev"], P["grow"], P["part_pos"]
+        rows = []  # rows of each (part, level)
+        for p in range(P["nparts"]):
+            _, c = np.unique(lev[grow[pp[p]:pp[p + 1]]], return_counts=True)
+            rows.append(c)
+        rows = np.concatenate(rows)
+        if k == 0:
+            assert rows.max() <= 64 and rows.max() >= 49, rows.max()  # T = 8 (7 would give 49)
+            assert P["nss"] == rows.size and P["NS"] == 1
+            assert _plan.make_plan(F, upper, grid, tile=12)["nparts"] < P["nparts"]
+        else:
+            assert np.mean(rows > 64) < 0.1
 
 
 def test_detect_grid():
