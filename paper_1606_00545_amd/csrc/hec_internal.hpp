@@ -255,6 +255,16 @@ struct hec_flat {
 // are laid out at consecutive positions sorted by (level, row), and each part is
 // cut into sub-segments of at most 64 rows of one level. Entry s of position q
 // is stored at s*ldq + q.
+// Wavefront plan of a grid triangle (plan.hpp's GridPlan) on the device.
+struct hec_grid {
+    bool on = false;
+    int32_t NA = 0, NB = 0, NC = 0, PA = 0, PB = 0, S = 0;
+    int64_t sa = 0, sb = 0, sc = 0;
+    hec::DevBuf<double> coef;  // [claim][step][k][lane]; k = 3 (upper): the reciprocal pivot
+    hec::DevBuf<float> coef32;
+    int64_t face_elems() const { return (int64_t)PA * PB * 2 * S * 8; }
+};
+
 struct hec_tri {
     int32_t nlev = 0;
     std::vector<int32_t> hlevel_ptr, hperm;  // Alg. 3: level start pointers, rows by (level, row)
@@ -280,6 +290,7 @@ struct hec_tri {
     hec::DevBuf<float> val32;
     hec::DevBuf<double> piv;        // upper only: u_ii per position
     hec::DevBuf<float> piv32;
+    hec_grid grid;                  // wavefront plan (7-point ILU(0) grids), used when on
 };
 
 namespace hec {
@@ -292,6 +303,10 @@ constexpr int kLevelsSyncWords = 8;
 // Polls a device-side wait of the triangular solves makes before it gives up
 // (hec_set_spin_limit).
 uint32_t spin_limit();
+
+// Whether triangular solves take the wavefront kernel where a schedule has a grid
+// plan (hec_set_trsv_grid; default on).
+bool trsv_grid_enabled();
 
 // Reads and clears the error word of lv after synchronising s; HEC_ERR_TIMEOUT if a
 // triangular-solve wait gave up since the last check.
@@ -311,6 +326,12 @@ struct hec_levels_s {
     // L^{-1} b in the upper plan's order, the upper solve's right-hand side.
     hec::DevBuf<double> qL64, qU64, yp64;
     hec::DevBuf<float> qL32, qU32, yp32;
+    // Face buffers of the wavefront solves (when both triangles have a grid plan): the
+    // values tiles hand to the next tiles, sentinel-filled before a launch. fL serves
+    // the lower solve of an L-then-U chain (filled by every upper launch), fU the upper
+    // one (filled by every lower launch) and lone solves (filled right before).
+    hec::DevBuf<double> fL64, fU64;
+    hec::DevBuf<float> fL32, fU32;
 };
 
 namespace hec {
@@ -329,6 +350,9 @@ void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipSt
 
 // Sets the internal lower-solve outputs of lv to the sentinel (once, after allocation).
 void trsv_init_levels(hec_levels_s &lv, hipStream_t s);
+
+// Builds tri.grid (the wavefront plan) when the factor's triangle admits one.
+void build_grid(const hec_ilu_s &M, bool upper, hec_grid &g, hipStream_t s);
 
 // Builds the level schedule and blocked solve plan of one triangle of M (the
 // upper plan must be built first: the lower plan records positions in it).

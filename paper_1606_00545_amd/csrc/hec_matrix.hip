@@ -41,6 +41,8 @@ std::atomic<uint32_t> g_spin{kDefaultSpin};
 }  // namespace
 
 uint32_t spin_limit() { return g_spin.load(std::memory_order_relaxed); }
+std::atomic<bool> g_trsv_grid{true};
+bool trsv_grid_enabled() { return g_trsv_grid.load(std::memory_order_relaxed); }
 
 Allocator current_allocator() {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -734,6 +736,13 @@ hec_status hec_set_spin_limit(int64_t polls) {
     return guarded([&] {
         if (polls > (int64_t)UINT32_MAX) fail(HEC_ERR_INVALID_ARG, "spin limit above 2^32 - 1 polls");
         g_spin.store(polls < 0 ? kDefaultSpin : (uint32_t)polls);
+    });
+}
+
+hec_status hec_set_trsv_grid(int32_t enable) {
+    return guarded([&] {
+        if (enable != 0 && enable != 1) fail(HEC_ERR_INVALID_ARG, "enable must be 0 or 1");
+        g_trsv_grid.store(enable != 0);
     });
 }
 

@@ -379,6 +379,11 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         lv->ras = !M->hext_row.empty();
         build_tri(*M, true, lv->upper, nullptr, s);
         build_tri(*M, false, lv->lower, &lv->upper, s);
+        if (!lv->ras) {  // the wavefront plans: both triangles or neither
+            build_grid(*M, true, lv->upper.grid, s);
+            if (lv->upper.grid.on) build_grid(*M, false, lv->lower.grid, s);
+            if (!lv->lower.grid.on) lv->upper.grid = hec_grid();
+        }
         if (!lv->ras && M->n <= HEC_BATCH_MAX_N) {  // small enough for the batched solver
             build_flat(*M, false, lv->lower, s);
             build_flat(*M, true, lv->upper, s);
@@ -393,6 +398,15 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
             lv->qU32.alloc(M->n);
             lv->yp32.alloc(M->n);
         }
+        if (lv->lower.grid.on) {
+            const int64_t nface = lv->lower.grid.face_elems();
+            lv->fL64.alloc(nface);
+            lv->fU64.alloc(nface);
+            if (M->has_f32) {
+                lv->fL32.alloc(nface);
+                lv->fU32.alloc(nface);
+            }
+        }
         trsv_init_levels(*lv, s);
         HEC_HIP(hipStreamSynchronize(s));
         *out = lv.release();
@@ -405,6 +419,13 @@ hec_status levels_info(hec_levels lv, int32_t *n, int32_t *nlev_lower, int32_t *
         if (n) *n = lv->n;
         if (nlev_lower) *nlev_lower = lv->lower.nlev;
         if (nlev_upper) *nlev_upper = lv->upper.nlev;
+    });
+}
+
+hec_status levels_grid(hec_levels lv, int32_t *grid) {
+    return guarded([&] {
+        if (!lv || !grid) fail(HEC_ERR_INVALID_ARG, "null levels or output");
+        *grid = lv->lower.grid.on && lv->upper.grid.on ? 1 : 0;
     });
 }
 

@@ -573,5 +573,121 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront plan of a grid triangle whose every dependency is one of the three grid
+// neighbours behind a row (lower: x-1, y-1, z-1; upper: x+1, y+1, z+1), as ILU(0)
+// of a 7-point stencil gives (Sec. 2.6: the level of a row is then the sum of its
+// coordinates, Eq. (11)).
+//
+// The grid is cut into tiles of kGT x kGT columns along two axes (a, b); the columns
+// run along the third (c, the longest). One wavefront takes a tile: lane (ma, mb)
+// solves its column's rows in order, the row at c-index mc at step s = mc + ma + mb.
+// The three dependencies of that row were solved one step earlier: the one behind
+// it along c by the lane itself, the ones along a and b by lanes (ma - 1, mb) and
+// (ma, mb - 1), or, on the tile's low faces, by the tiles before it, which hand the
+// values over through face buffers in global memory. The upper triangle runs the
+// same schedule in mirrored coordinates (m = kGT - 1 - local index along a and b,
+// c reversed, tiles claimed in reverse order), so one kernel serves both.
+//
+// Tiles are claimed in order: claim t is the m-tile (t % PA, t / PA); its
+// dependencies lie in claims t - 1 and t - PA, both earlier.
+constexpr int kGT = 8;                       // tile side in columns: kGT * kGT = 64 lanes
+constexpr int kGridSkew = 2 * (kGT - 1);     // steps of a tile beyond the c extent
+constexpr int kGridCoefLower = 3;            // per lane and step: back (c), below (b), left (a)
+constexpr int kGridCoefUpper = 4;            // ... and the reciprocal pivot
+
+struct GridPlan {
+    int32_t NA = 0, NB = 0, NC = 0;  // extents along a, b and c
+    int64_t sa = 0, sb = 0, sc = 0;  // row strides along a, b and c
+    int32_t PA = 0, PB = 0;          // tiles along a and b
+    int32_t S = 0;                   // steps of one tile: NC + kGridSkew
+    int32_t ncoef = 0;               // kGridCoefLower or kGridCoefUpper
+    // [claim][step][k][lane]: index into the factor's values of coefficient k of the
+    // lane's row at that step (k = 3: the pivot, whose reciprocal is used), -1: none
+    std::vector<int32_t> src;
+    int64_t nclaims() const { return (int64_t)PA * PB; }
+};
+
+// Grid coordinates of a claim's lane at a step: false when the lane holds no row then.
+// (ta, tb): the tile; (la, lb): the lane's column in it; mc: the c-index in solve order.
+struct GridCell {
+    int32_t ga, gb, gc;
+    bool valid;
+};
+HEC_HD inline GridCell grid_cell(int32_t NA, int32_t NB, int32_t NC, int32_t PA, int32_t PB, bool upper,
+                                 int64_t claim, int lane, int32_t s) {
+    const int32_t mta = (int32_t)(claim % PA), mtb = (int32_t)(claim / PA);
+    const int32_t ta = upper ? PA - 1 - mta : mta, tb = upper ? PB - 1 - mtb : mtb;
+    const int ma = lane % kGT, mb = lane / kGT;
+    const int la = upper ? kGT - 1 - ma : ma, lb = upper ? kGT - 1 - mb : mb;
+    const int32_t mc = s - ma - mb;
+    GridCell g;
+    g.ga = ta * kGT + la;
+    g.gb = tb * kGT + lb;
+    g.gc = upper ? NC - 1 - mc : mc;
+    g.valid = g.ga < NA && g.gb < NB && mc >= 0 && mc < NC;
+    return g;
+}
+
+// Builds the wavefront plan of the strict lower (upper) triangle of the factor pattern
+// on the nx x ny x nz grid. Returns false (G untouched) when it does not apply: no
+// grid, fewer than kGT columns along a tile axis, or an entry that is not one of the
+// three neighbours behind its row.
+inline bool make_grid_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
+                           int32_t gny, int32_t gnz, bool upper, GridPlan &G) {
+    if (gnx <= 0 || gny <= 0 || gnz <= 0 || (int64_t)gnx * gny * gnz != n) return false;
+    const int32_t ext[3] = {gnx, gny, gnz};
+    const int64_t str[3] = {1, gnx, (int64_t)gnx * gny};
+    int c = 2;  // the longest axis runs along the columns (ties: the largest stride)
+    for (int k = 1; k >= 0; --k)
+        if (ext[k] > ext[c]) c = k;
+    const int a = c == 0 ? 1 : 0, b = c == 2 ? 1 : 2;  // the others, by stride
+    if (ext[a] < kGT || ext[b] < kGT) return false;
+    // every strict-triangle entry must be a neighbour behind the row
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t co[3] = {i % gnx, (i / gnx) % gny, i / (gnx * gny)};
+        const int32_t e0 = upper ? diag[i] + 1 : LUp[i], e1 = upper ? LUp[i + 1] : diag[i];
+        for (int32_t e = e0; e < e1; ++e) {
+            const int64_t d = (int64_t)LUj[e] - i;
+            bool ok = false;
+            for (int k = 0; k < 3 && !ok; ++k) {
+                const int64_t want = upper ? str[k] : -str[k];
+                ok = d == want && (upper ? co[k] + 1 < ext[k] : co[k] > 0);
+            }
+            if (!ok) return false;
+        }
+    }
+    GridPlan P;
+    P.NA = ext[a];
+    P.NB = ext[b];
+    P.NC = ext[c];
+    P.sa = str[a];
+    P.sb = str[b];
+    P.sc = str[c];
+    P.PA = (P.NA + kGT - 1) / kGT;
+    P.PB = (P.NB + kGT - 1) / kGT;
+    P.S = P.NC + kGridSkew;
+    P.ncoef = upper ? kGridCoefUpper : kGridCoefLower;
+    const int64_t nc = P.nclaims();
+    P.src.assign((size_t)(nc * P.S * P.ncoef * 64), -1);
+    const int64_t sg = upper ? 1 : -1;
+    for (int64_t t = 0; t < nc; ++t)
+        for (int32_t s = 0; s < P.S; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const GridCell g = grid_cell(P.NA, P.NB, P.NC, P.PA, P.PB, upper, t, lane, s);
+                if (!g.valid) continue;
+                const int64_t row = g.ga * P.sa + g.gb * P.sb + g.gc * P.sc;
+                const int64_t dep[3] = {row + sg * P.sc, row + sg * P.sb, row + sg * P.sa};  // back, below, left
+                int32_t *o = &P.src[(size_t)(((t * P.S + s) * P.ncoef) * 64 + lane)];
+                const int32_t e0 = upper ? diag[row] + 1 : LUp[row], e1 = upper ? LUp[row + 1] : diag[row];
+                for (int32_t e = e0; e < e1; ++e)
+                    for (int k = 0; k < 3; ++k)
+                        if (LUj[e] == dep[k]) o[k * 64] = e;
+                if (upper) o[3 * 64] = diag[row];
+            }
+    G = std::move(P);
+    return true;
+}
+
 }  // namespace plan
 }  // namespace hec

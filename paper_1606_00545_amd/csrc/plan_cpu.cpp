@@ -76,6 +76,37 @@ int64_t hecplan_array(const void *h, const char *name, int32_t *dst) {
 
 void hecplan_free(void *h) { delete (HostPlan *)h; }
 
+// Wavefront plan of the strict lower (upper) triangle on the nx x ny x nz grid
+// (make_grid_plan); NULL when none applies or on allocation failure.
+void *hecplan_grid_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
+                        int32_t gny, int32_t gnz, int32_t upper) {
+    auto *G = new (std::nothrow) hec::plan::GridPlan();
+    if (!G) return nullptr;
+    try {
+        if (hec::plan::make_grid_plan(n, LUp, LUj, diag, gnx, gny, gnz, upper != 0, *G)) return G;
+    } catch (...) {
+    }
+    delete G;
+    return nullptr;
+}
+
+// meta[0..9] = NA, NB, NC, sa, sb, sc, PA, PB, S, ncoef.
+void hecplan_grid_meta(const void *h, int64_t *meta) {
+    const auto &G = *(const hec::plan::GridPlan *)h;
+    const int64_t m[10] = {G.NA, G.NB, G.NC, G.sa, G.sb, G.sc, G.PA, G.PB, G.S, G.ncoef};
+    std::memcpy(meta, m, sizeof(m));
+}
+
+// Copies the coefficient map ([claim][step][k][lane]) into dst when dst != NULL;
+// returns its length.
+int64_t hecplan_grid_src(const void *h, int32_t *dst) {
+    const auto &G = *(const hec::plan::GridPlan *)h;
+    if (dst && !G.src.empty()) std::memcpy(dst, G.src.data(), G.src.size() * sizeof(int32_t));
+    return (int64_t)G.src.size();
+}
+
+void hecplan_grid_free(void *h) { delete (hec::plan::GridPlan *)h; }
+
 // Grid recognition used to choose tiled parts: out = {nx, ny, nz}, all 0 when
 // the pattern is not a natural-order 5/7-point stencil.
 void hecplan_detect_grid(int32_t n, const int32_t *Ap, const int32_t *Aj, int32_t *out) {

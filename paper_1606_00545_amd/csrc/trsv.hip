@@ -685,6 +685,414 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront solve of a grid triangle (plan.hpp's GridPlan): one tile of 8 x 8
+// columns per workgroup, tiles claimed in order from a ticket counter (a tile
+// only waits for tiles claimed before it, held by running workgroups).
+//  * Wavefront 0 solves. At step s lane (ma, mb) solves the row at c-index
+//    s - ma - mb of its column; that row's dependencies were solved at step s - 1:
+//    the one behind it along c by the lane itself (a register), the ones along a
+//    and b by lanes (ma - 1, mb) and (ma, mb - 1), or, on the tile's low faces, by
+//    the tiles before it. Each step has a 9 x 9 grid of cells in LDS, a cell per
+//    lane (row mb, column ma; row and column 8 take the high faces' writes)
+//    holding the two values the lane reads: from the left and from below. A lane
+//    writes its result into the left slot of the cell to its right and the below
+//    slot of the cell above in the next step's grid (one LDS instruction), the
+//    face poller fills the slots no lane writes (the left slots of column 0, the
+//    below slots of row 0), and a lane reads its cell in one instruction. A single wavefront issues
+//    at most one instruction every 4 cycles, so the step is kept to a few dozen
+//    instructions: the dependency chain is one LDS round trip and three fused
+//    multiply-adds.
+//  * Wavefronts 1..kGridPollers poll the tile's incoming face values (8 on the
+//    a-face, 8 on the b-face per step) for a window of the next 4 * HEC_GRID_POLL_R
+//    steps, one lane per value and step, with device-coherent loads until they are
+//    not the sentinel, write each into its step's grid, and raise the count of
+//    leading steps that have all of theirs. (Several pollers would poll the same
+//    window independently; a wider window or more pollers send more device-coherent
+//    loads, which slowed the 128^3 solve: 209 us for the lower triangle with 16
+//    steps and 3 pollers, 157 us with 4 steps and 1.)
+//  * The other wavefronts load the coefficients (packed by claim, step and lane, so
+//    every load is a whole line) and the right-hand side of runs of steps into a
+//    ring of LDS slots. They depend on nothing but the ring, so they run ahead.
+//  * The solver stores each result to the output by row and, on the tile's high
+//    faces, to the face buffer with a device-coherent store, at the index of the
+//    step at which the next tile needs it (the corner lane's value only on the
+//    a-face, where the tile above also reads it).
+// Readiness is the value itself, as in the blocked kernel: the face buffer holds
+// the sentinel before the launch (filled by the previous launch of an L-then-U
+// chain, or by a fill kernel before a lone solve).
+#ifndef HEC_GRID_POLL_R
+#define HEC_GRID_POLL_R 1
+#endif
+#ifndef HEC_GRID_POLLERS
+#define HEC_GRID_POLLERS 1
+#endif
+#ifndef HEC_GRID_POLL_SLEEP
+#define HEC_GRID_POLL_SLEEP 2
+#endif
+constexpr int kGridWaves = 8;    // the solver, the face pollers, then loaders
+constexpr int kGridPollers = HEC_GRID_POLLERS;
+constexpr int kGridLoaders = kGridWaves - 1 - kGridPollers;
+constexpr int kGridBatch = 3;   // consecutive steps a loader has in flight
+constexpr int kGridRing = 32;   // steps in LDS (slots and grids): how far loads run ahead
+constexpr int kGridG = plan::kGT + 1;  // side of a step's grid of cells: the tile and its low faces
+static_assert((kGridRing & (kGridRing - 1)) == 0 && kGridBatch <= kGridRing, "ring");
+
+struct GridArgs {
+    int32_t NA, NB, NC, PA, PB, S, nclaims;
+    int64_t sa, sb, sc;
+    uint32_t *err;  // the schedule's error word
+    uint32_t spin;  // polls before a wait gives up
+};
+
+// b: right-hand side by row; x: results by row; face: the triangle's face buffer
+// ([claim][face][step][8], sentinel-filled); fill: nfill elements set to the
+// sentinel for a later solve (may be NULL).
+template <class T>
+struct GridIO {
+    const T *b;
+    T *x;
+    T *face;
+    T *fill;
+    int64_t nfill;
+};
+
+// Dynamic LDS of k_trsv_grid: control words, slots [ring][NCOEF + 1][64], grids
+// [ring][9 * 9][2] (a cell: the value from the left, the value from below).
+constexpr size_t kGridCtrl = 256;
+template <class T, bool UPPER>
+constexpr size_t grid_lds_bytes() {
+    constexpr int NCOEF = UPPER ? plan::kGridCoefUpper : plan::kGridCoefLower;
+    return kGridCtrl + (size_t)kGridRing * (NCOEF + 1) * 64 * sizeof(T) +
+           (size_t)kGridRing * kGridG * kGridG * 2 * sizeof(T);
+}
+
+template <class T, bool UPPER>
+__global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const T *__restrict__ coef, GridIO<T> io,
+                                                               uint32_t *sync, const int32_t *skip) {
+    using U = typename Sentinel<T>::U;
+    constexpr U SENT = Sentinel<T>::bits;
+    constexpr int NCOEF = UPPER ? plan::kGridCoefUpper : plan::kGridCoefLower;
+    constexpr int GT = plan::kGT, GG = kGridG, GA = GG * GG * 2, RM = kGridRing - 1;
+    constexpr int SLOT = (NCOEF + 1) * 64;  // elements of a slot: [NCOEF][64] coefficients, [64] rhs
+    if (skip && *skip) return;  // uniform: no workgroup touches the counters
+    if (io.fill) {
+        const T sv = from_bits<T>(SENT);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < io.nfill;
+             i += (int64_t)gridDim.x * blockDim.x)
+            io.fill[i] = sv;
+    }
+    extern __shared__ __align__(16) char gsm[];
+    int *const filled = (int *)gsm;          // [ring]: step whose coefficients and rhs a slot holds
+    int *const s_done = filled + kGridRing;  // steps the solver has finished (slots and grids below are free)
+    int *const s_faces = s_done + 1;         // leading steps whose face values are all in their grids
+    int *const s_claim = s_done + 2;
+    int *const s_abort = s_done + 3;
+    T *const slots = (T *)(gsm + kGridCtrl);
+    T *const xg = slots + kGridRing * SLOT;  // [ring][9][9][2]: row mb, column ma; left, below
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ma = lane % GT, mb = lane / GT;
+    if (threadIdx.x == 0) *s_abort = 0;
+    auto give_up = [&]() {
+        __hip_atomic_store(s_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        record_timeout(G.err);
+    };
+    // one more poll of a wait (wave-uniform callers): true when the wait must stop
+    auto spun_out = [&](uint32_t &it, bool device_wide) {
+        ++it;
+        bool stop = it > G.spin;
+        if (!stop && (it & 63) == 0)
+            stop = __hip_atomic_load(s_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
+                   (device_wide && timed_out(G.err));
+        stop = __builtin_amdgcn_readfirstlane((int)stop) != 0;
+        if (stop) give_up();
+        return stop;
+    };
+    auto lds_load = [](const int *p) {
+        return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    };
+    // waits until the solver has finished step `below` (its slot is free); false: gave up
+    auto wait_done = [&](int below) {
+        uint32_t it = 0;
+        while (lds_load(s_done) <= below) {
+            if (spun_out(it, false)) return false;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        return true;
+    };
+    for (;;) {
+        __syncthreads();
+        if (*s_abort) break;  // uniform: read by every thread after the barrier
+        if (threadIdx.x == 0) {
+            *s_claim = (int)atomicAdd(&sync[0], 1u);
+            *s_done = 0;
+            *s_faces = 0;
+        }
+        if (threadIdx.x < kGridRing) filled[threadIdx.x] = -1;
+        for (int t = threadIdx.x; t < GA; t += blockDim.x) xg[t] = (T)0;  // step 0: no previous results
+        __syncthreads();
+        const int c = *s_claim;
+        if (c >= G.nclaims) break;
+        const int mta = c % G.PA, mtb = c / G.PA;
+        const int32_t ta = UPPER ? G.PA - 1 - mta : mta, tb = UPPER ? G.PB - 1 - mtb : mtb;
+        // global a and b of the column of lane (ma', mb')
+        auto col_a = [&](int m) { return ta * GT + (UPPER ? GT - 1 - m : m); };
+        auto col_b = [&](int m) { return tb * GT + (UPPER ? GT - 1 - m : m); };
+        const bool act = col_a(ma) < G.NA && col_b(mb) < G.NB;
+        const int64_t base = (int64_t)col_a(ma) * G.sa + (int64_t)col_b(mb) * G.sb;
+        auto row_at = [&](int32_t mc) { return base + (int64_t)(UPPER ? G.NC - 1 - mc : mc) * G.sc; };
+
+        if (wave == 0) {
+            // ---------------- solver
+            __builtin_amdgcn_s_setprio(3);
+            const bool has_u = mtb < G.PB - 1;  // a tile above reads the b-face
+            // this lane's face store (if any): a-face by mb (the corner too), b-face by ma
+            const bool fst = ma == GT - 1 || (mb == GT - 1 && has_u);
+            T *const fp = io.face + ((int64_t)c * 2 + (ma == GT - 1 ? 0 : 1)) * G.S * 8 +
+                          (ma == GT - 1 ? mb : ma) - (GT - 1) * 8;  // + 8 s: the entry of step s
+            T xp = (T)0;  // this lane's result of the previous step (0: none)
+            int ready = 0, fready = 0;
+            bool bail = false;
+            // waits until step s is loaded; returns one past the run of loaded steps from s
+            // (8 flags, one per lane, in one LDS round trip)
+            auto scan = [&](int s) -> int {
+                const int u = lane & 7;
+                uint32_t it = 0;
+                for (;;) {
+                    const int want = s + u;
+                    const int f = __hip_atomic_load(&filled[want & RM], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint64_t m = __ballot(lane < 8 && want < G.S && f == want);
+                    const int ok = __builtin_ctzll(~m);
+                    if (ok > 0) {
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        return s + ok;
+                    }
+                    if (spun_out(it, false)) {
+                        bail = true;
+                        return s;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            };
+            auto wait_faces = [&](int s) -> int {  // until step s has its face values
+                uint32_t it = 0;
+                for (;;) {
+                    const int f = lds_load(s_faces);
+                    if (f > s) {
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        return f;
+                    }
+                    if (spun_out(it, false)) {
+                        bail = true;
+                        return s;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            };
+            auto ensure = [&](int s) {  // step s loaded and its faces in; false: gave up
+                if (s >= ready) ready = scan(s);
+                if (s >= fready && !bail) fready = wait_faces(s);
+                return !bail;
+            };
+            struct Step {  // one step's coefficients and right-hand side
+                T cv[NCOEF];
+                T bv;
+            };
+            auto load_step = [&](int s, Step &H) {
+                const T *sl = slots + (s & RM) * SLOT + lane;
+#pragma unroll
+                for (int k = 0; k < NCOEF; ++k) H.cv[k] = sl[k * 64];
+                H.bv = sl[NCOEF * 64];
+            };
+            // the lane's row at step s: c-index s - ma - mb, valid for (unsigned)(s - moff) < ncl
+            const int moff = ma + mb;
+            const uint32_t ncl = act ? (uint32_t)G.NC : 0u;
+            const int64_t dsc = UPPER ? -G.sc : G.sc;
+            int64_t roff = row_at(-moff);  // advanced one row along c per step
+            const int gl = (mb * GG + ma) * 2;  // this lane's cell
+            // One step: cur holds its inputs; the next step's are read into nxt while it
+            // computes. That read is speculative (unconditional, so that the compiler
+            // counts it exactly when it waits for the neighbours' values) and is repeated
+            // after the wait when the next step was not yet known to be ready. After a
+            // give-up the step still runs (so the two register sets keep one data flow)
+            // but stores nothing.
+            auto step = [&](int s, Step &cur, Step &nxt, bool odd) {
+                const T *g = xg + (s & RM) * GA + gl;
+                const T left = g[0], below = g[1];
+                const bool more = s + 1 < G.S;
+                const bool early = more && s + 1 < ready && s + 1 < fready;
+                load_step(s + 1, nxt);  // (when s + 1 = S: a slot in range, unused)
+                T acc;
+                if constexpr (!UPPER) {  // columns ascending (c along z): back, below, left
+                    acc = cur.bv - cur.cv[0] * xp;
+                    acc -= cur.cv[1] * below;
+                    acc -= cur.cv[2] * left;
+                } else {  // left, below, back; then the reciprocal pivot
+                    acc = cur.bv - cur.cv[2] * left;
+                    acc -= cur.cv[1] * below;
+                    acc -= cur.cv[0] * xp;
+                    acc *= cur.cv[3];
+                }
+                const bool valid = (uint32_t)(s - moff) < ncl;
+                const T xn = valid ? acc : (T)0;
+                T *gn = xg + ((s + 1) & RM) * GA + gl;
+                gn[2] = xn;           // left slot of the cell to the right
+                gn[2 * GG + 1] = xn;  // below slot of the cell above
+                if (valid && !bail) {
+                    io.x[roff] = xn;
+                    if (fst) store_coherent(fp + (int64_t)s * 8, xn);  // the next tiles read it at step s - 7
+                }
+                xp = xn;
+                roff += dsc;
+                // slots and grids up to s are free once read: LDS accesses of one wavefront
+                // complete in order, so the reads issued above are done before this store
+                if (odd || !more) {
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (lane == 0) __hip_atomic_store(s_done, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                if (more && !early && ensure(s + 1)) load_step(s + 1, nxt);
+            };
+            Step h0, h1;
+            if (ensure(0)) load_step(0, h0);
+            for (int s = 0; s < G.S && !bail; s += 2) {
+                step(s, h0, h1, false);
+                if (s + 1 < G.S) step(s + 1, h1, h0, true);
+            }
+            __builtin_amdgcn_s_setprio(0);
+        } else if (wave <= kGridPollers) {
+            // ---------------- face pollers: a window of 4R steps from w, step w + q + 4r in
+            // lane 16q + i for r < R; i < 8: a-face entry i (lane (0, i)), i >= 8:
+            // b-face entry i - 8 (lane (i - 8, 0)). A value goes into its step's grid once,
+            // when it has arrived and the solver is done with the grid's previous step; the
+            // window moves on by whole groups of 4 steps, and the count of leading steps
+            // with all their values is published as it grows.
+            constexpr int R = HEC_GRID_POLL_R;
+            const int q = lane >> 4, i = lane & 15, j = i & 7;
+            const bool on_a = i < GT;
+            const bool has = on_a ? mta > 0 && col_b(j) < G.NB : mtb > 0 && col_a(j) < G.NA;
+            // a-face entry j: a-face of the tile before along a; b-face entry j: b-face of the
+            // tile below, its corner (j = 7) on that tile's a-face
+            const T *const fsrc = !has              ? io.face  // (not read)
+                                  : on_a            ? io.face + ((int64_t)(c - 1) * 2 + 0) * G.S * 8 + j
+                                  : j == GT - 1     ? io.face + ((int64_t)(c - G.PA) * 2 + 0) * G.S * 8 + j
+                                                    : io.face + ((int64_t)(c - G.PA) * 2 + 1) * G.S * 8 + j;
+            // a-face: left slot of lane (0, j)'s cell; b-face: below slot of lane (j, 0)'s cell
+            const int gpos = on_a ? j * GG * 2 : j * 2 + 1;
+            int w = 0, pub = 0;
+            bool wr[R] = {};  // this lane's value of step w + q + 4r is in its grid
+            uint32_t it = 0;
+            while (pub < G.S) {
+                const int dn = lds_load(s_done);
+                U v[R];
+                bool need[R], can[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {  // all loads first, then one wait
+                    const int st = w + q + 4 * r;
+                    can[r] = !wr[r] && st < G.S && st < dn + kGridRing;
+                    need[r] = can[r] && has && st - j >= 0 && st - j < G.NC;
+                    v[r] = need[r] ? load_coherent(fsrc + (int64_t)st * 8) : (U)0;
+                }
+                uint64_t okm[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int st = w + q + 4 * r;
+                    if (can[r] && (!need[r] || v[r] != SENT)) {
+                        xg[(st & RM) * GA + gpos] = need[r] ? from_bits<T>(v[r]) : (T)0;
+                        wr[r] = true;
+                    }
+                    okm[r] = __ballot(wr[r] || st >= G.S);
+                }
+                int k = 0;  // leading steps of the window with all their values
+                bool gap = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        gap = gap || ((okm[r] >> (16 * qq)) & 0xFFFFull) != 0xFFFFull;
+                        k += gap ? 0 : 1;
+                    }
+                if (w + k > pub) {
+                    pub = min(w + k, G.S);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // after this wave's writes
+                    if (lane == 0) __hip_atomic_fetch_max(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    it = 0;
+                } else {
+                    if (spun_out(it, true)) break;
+                    __builtin_amdgcn_s_sleep(HEC_GRID_POLL_SLEEP);
+                }
+                const int gsh = k >> 2;  // whole groups done: the window moves on
+                if (gsh > 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        bool nw = false;
+#pragma unroll
+                        for (int u = 1; u < R; ++u) nw = u == gsh && r + u < R ? wr[r + u] : nw;
+                        wr[r] = nw;
+                    }
+                    w += 4 * gsh;
+                }
+            }
+        } else {
+            // ---------------- loaders: wavefront 1 + kGridPollers + l takes runs of kGridBatch consecutive
+            // steps, l * kGridBatch + i * L * kGridBatch (L loaders), each run in flight at
+            // once; a run only waits for its own slots, so loads run up to the ring's
+            // depth ahead of the solver
+            constexpr int NL = kGridLoaders, B = kGridBatch;
+            for (int s0 = (wave - 1 - kGridPollers) * B; s0 < G.S; s0 += NL * B) {
+                if (!wait_done(min(s0 + B, G.S) - 1 - kGridRing)) break;
+                T cv[B][NCOEF], bv[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int s = s0 + u;
+                    const bool in = s < G.S;
+                    const T *cp = coef + ((int64_t)c * G.S + (in ? s : s0)) * NCOEF * 64 + lane;
+#pragma unroll
+                    for (int k = 0; k < NCOEF; ++k) cv[u][k] = cp[k * 64];
+                    const int32_t mc = s - ma - mb;
+                    bv[u] = in && act && mc >= 0 && mc < G.NC ? io.b[row_at(mc)] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int s = s0 + u;
+                    if (s < G.S) {
+                        T *sl = slots + (s & RM) * SLOT + lane;
+#pragma unroll
+                        for (int k = 0; k < NCOEF; ++k) sl[k * 64] = cv[u][k];
+                        sl[NCOEF * 64] = bv[u];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane < B && s0 + lane < G.S)
+                    __hip_atomic_store(&filled[(s0 + lane) & RM], s0 + lane, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // the last workgroup out resets the counters for the next launch
+        const uint32_t d = atomicAdd(&sync[1], 1u);
+        if (d == gridDim.x - 1) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Packed coefficients of a wavefront plan: out[q] = value map[q] of the factor (0
+// where map[q] < 0); slot k = 3 of each step holds the reciprocal of the pivot.
+template <class T>
+__global__ __launch_bounds__(256) void k_grid_coef(size_t n, int ncoef, const int32_t *__restrict__ map,
+                                                   const double *__restrict__ src, T *__restrict__ out) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t m = map[q];
+    const int k = (int)((q / 64) % (size_t)ncoef);
+    T v = m >= 0 ? (T)src[m] : (T)0;
+    if (k == 3 && m >= 0) v = (T)1 / v;
+    out[q] = v;
+}
+
 // Before a single-triangle solve: the output filled with the sentinel.
 template <class T>
 __global__ __launch_bounds__(256) void k_trsv_fill(int64_t n, T *x, const int32_t *skip) {
@@ -769,6 +1177,61 @@ void launch_blk(const hec_tri &tri, uint32_t *sync, uint32_t *err, const SolveIO
     HEC_CHECK_LAUNCH();
 }
 
+template <class T, bool UPPER>
+void launch_grid(const hec_grid &g, uint32_t *sync, uint32_t *err, const GridIO<T> &io, hipStream_t s,
+                 const int32_t *skip) {
+    const int32_t nclaims = g.PA * g.PB;
+    GridArgs G{g.NA, g.NB, g.NC, g.PA, g.PB, g.S, nclaims, g.sa, g.sb, g.sc, err, spin_limit()};
+    const T *coef;
+    if constexpr (sizeof(T) == 8)
+        coef = g.coef.get();
+    else
+        coef = g.coef32.get();
+    const int grid = std::min(nclaims, 1024);
+    constexpr size_t lds = grid_lds_bytes<T, UPPER>();
+    static bool attr_set = false;  // one per instantiation
+    if (!attr_set) {
+        HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_grid<T, UPPER>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        attr_set = true;
+    }
+    k_trsv_grid<T, UPPER><<<grid, 64 * kGridWaves, lds, s>>>(G, coef, io, sync, skip);
+    HEC_CHECK_LAUNCH();
+}
+
+// The wavefront path of trsv_launch (both triangles have grid plans; not RAS).
+template <class T>
+void trsv_launch_grid(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipStream_t s,
+                      const int32_t *skip) {
+    T *fL, *fU, *yp;
+    if constexpr (sizeof(T) == 8) {
+        fL = lv.fL64.get();
+        fU = lv.fU64.get();
+        yp = lv.yp64.get();
+    } else {
+        fL = lv.fL32.get();
+        fU = lv.fU32.get();
+        yp = lv.yp32.get();
+    }
+    const int64_t nface = lv.lower.grid.face_elems();
+    uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
+    uint32_t *err = sync + kLevelsErrWord;
+    if (which == HEC_LU) {
+        // fL is sentinel-filled between chains (by level_schedule, then by every upper
+        // launch); the lower launch fills fU for the upper one
+        launch_grid<T, false>(lv.lower.grid, sync, err, GridIO<T>{b, yp, fL, fU, nface}, s, skip);
+        launch_grid<T, true>(lv.upper.grid, sync + 2, err, GridIO<T>{yp, x, fU, fL, nface}, s, skip);
+        return;
+    }
+    // a lone triangle: fU, free between calls, is filled right before
+    k_trsv_fill<T><<<ceil_div(nface, 256), 256, 0, s>>>(nface, fU, skip);
+    HEC_CHECK_LAUNCH();
+    if (which == HEC_LOWER)
+        launch_grid<T, false>(lv.lower.grid, sync, err, GridIO<T>{b, x, fU, nullptr, 0}, s, skip);
+    else
+        launch_grid<T, true>(lv.upper.grid, sync + 2, err, GridIO<T>{b, x, fU, nullptr, 0}, s, skip);
+}
+
 }  // namespace
 
 template <class T>
@@ -784,6 +1247,10 @@ void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipSt
         qL = lv.qL32.get();
         qU = lv.qU32.get();
         yp = lv.yp32.get();
+    }
+    if (lv.lower.grid.on && lv.upper.grid.on && trsv_grid_enabled()) {
+        trsv_launch_grid<T>(lv, which, b, x, s, skip);
+        return;
     }
     uint32_t *sync = const_cast<uint32_t *>(lv.sync.get());
     uint32_t *err = sync + kLevelsErrWord;
@@ -821,6 +1288,44 @@ void trsv_init_levels(hec_levels_s &lv, hipStream_t s) {
         k_trsv_fill<float><<<ceil_div(n, 256), 256, 0, s>>>(n, lv.qL32.get(), nullptr);
         HEC_CHECK_LAUNCH();
     }
+    const int64_t nface = lv.fL64.get() ? lv.lower.grid.face_elems() : 0;
+    if (nface) {
+        k_trsv_fill<double><<<ceil_div(nface, 256), 256, 0, s>>>(nface, lv.fL64.get(), nullptr);
+        HEC_CHECK_LAUNCH();
+        if (lv.fL32.get()) {
+            k_trsv_fill<float><<<ceil_div(nface, 256), 256, 0, s>>>(nface, lv.fL32.get(), nullptr);
+            HEC_CHECK_LAUNCH();
+        }
+    }
+}
+
+void build_grid(const hec_ilu_s &M, bool upper, hec_grid &g, hipStream_t s) {
+    g = hec_grid();
+    plan::GridPlan P;
+    if (!plan::make_grid_plan(M.n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, P))
+        return;
+    g.NA = P.NA;
+    g.NB = P.NB;
+    g.NC = P.NC;
+    g.PA = P.PA;
+    g.PB = P.PB;
+    g.S = P.S;
+    g.sa = P.sa;
+    g.sb = P.sb;
+    g.sc = P.sc;
+    const size_t m = P.src.size();
+    DevBuf<int32_t> dsrc(m);
+    dsrc.upload(P.src.data(), m, s);
+    g.coef.alloc(m);
+    k_grid_coef<double><<<ceil_div(m, 256), 256, 0, s>>>(m, P.ncoef, dsrc.get(), M.LUx.get(), g.coef.get());
+    HEC_CHECK_LAUNCH();
+    if (M.has_f32) {
+        g.coef32.alloc(m);
+        k_grid_coef<float><<<ceil_div(m, 256), 256, 0, s>>>(m, P.ncoef, dsrc.get(), M.LUx.get(), g.coef32.get());
+        HEC_CHECK_LAUNCH();
+    }
+    HEC_HIP(hipStreamSynchronize(s));  // dsrc and the host map end here
+    g.on = true;
 }
 
 template void trsv_launch<double>(const hec_levels_s &, uint32_t, const double *, double *, hipStream_t,

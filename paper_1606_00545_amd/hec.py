@@ -32,7 +32,7 @@ EXPORTED = ("hec_from_csr", "hec_info", "hec_export", "hec_spmv", "hec_destroy",
             "batch_create", "batch_destroy", "gmres_solve_batched",
             "amg_setup", "amg_info", "amg_export_level", "amg_solve", "amg_destroy",
             "hec_set_allocator", "hec_footprint", "gmres_solve_noalloc", "hec_set_spin_limit", "levels_check",
-            "hec_last_error")
+            "hec_set_trsv_grid", "levels_grid", "hec_last_error")
 BATCH_MAX_N = 8192
 NOALLOC_MAX_N = 16384
 
@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
     L.hec_footprint.argtypes = [_vp, _vp, _vp, _i64p]
     L.hec_set_spin_limit.argtypes = [C.c_int64]
     L.levels_check.argtypes = [_vp, _vp]
+    L.hec_set_trsv_grid.argtypes = [C.c_int32]
+    L.levels_grid.argtypes = [_vp, _i32p]
     for name in EXPORTED:
         if name != "hec_last_error":
             getattr(L, name).restype = C.c_int
@@ -204,6 +206,19 @@ def set_spin_limit(polls: int = -1):
     """hec_set_spin_limit: polls a device-side wait of the triangular solves makes before
     it gives up (negative: the default)."""
     _check(load().hec_set_spin_limit(int(polls)), "hec_set_spin_limit")
+
+
+def set_trsv_grid(enable: bool = True):
+    """hec_set_trsv_grid: triangular solves of schedules with wavefront plans use the
+    wavefront kernel (True, the default) or the level-blocked one (False)."""
+    _check(load().hec_set_trsv_grid(1 if enable else 0), "hec_set_trsv_grid")
+
+
+def levels_grid(lv) -> bool:
+    """levels_grid: whether lv carries wavefront plans for its triangles."""
+    g = C.c_int32()
+    _check(load().levels_grid(lv.ptr, C.byref(g)), "levels_grid")
+    return bool(g.value)
 
 
 def levels_check(lv, stream=None):

@@ -30,6 +30,12 @@ def lib():
         L.hecplan_array.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p]
         L.hecplan_free.argtypes = [C.c_void_p]
         L.hecplan_detect_grid.argtypes = [C.c_int32, ip, ip, ip]
+        L.hecplan_grid_make.restype = C.c_void_p
+        L.hecplan_grid_make.argtypes = [C.c_int32, ip, ip, ip, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.hecplan_grid_meta.argtypes = [C.c_void_p, np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
+        L.hecplan_grid_src.restype = C.c_int64
+        L.hecplan_grid_src.argtypes = [C.c_void_p, C.c_void_p]
+        L.hecplan_grid_free.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -79,3 +85,26 @@ def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=Fals
         L.hecplan_free(h)
     P["diag"] = diag
     return P
+
+
+GRID_META = ("NA", "NB", "NC", "sa", "sb", "sc", "PA", "PB", "S", "ncoef")
+
+
+def make_grid_plan(F, upper, grid):
+    """Wavefront plan of one triangle of F on the grid (nx, ny, nz) as a dict, or None when
+    the planner gives none."""
+    L = lib()
+    diag = diag_positions(F)
+    h = L.hecplan_grid_make(F.n, _i32(F.LUp), _i32(F.LUj), diag, grid[0], grid[1], grid[2], int(upper))
+    if not h:
+        return None
+    try:
+        meta = np.zeros(10, np.int64)
+        L.hecplan_grid_meta(h, meta)
+        G = {k: int(v) for k, v in zip(GRID_META, meta)}
+        m = L.hecplan_grid_src(h, None)
+        G["src"] = np.empty(m, np.int32)
+        L.hecplan_grid_src(h, G["src"].ctypes.data_as(C.c_void_p))
+    finally:
+        L.hecplan_grid_free(h)
+    return G

@@ -100,3 +100,21 @@ def test_set_allocator_rejects_a_single_hook():
     assert code == hec.INVALID_ARG
     hec.set_allocator(None, None)  # the library default
     hec.use_torch_allocator()      # the binding's default
+
+
+def test_trsv_kernel_switch_arguments():
+    """hec_set_trsv_grid takes 0 or 1 only (host-side check, no device work)."""
+    L = hec.load()
+    assert L.hec_set_trsv_grid(2) == hec.INVALID_ARG
+    assert L.hec_set_trsv_grid(-1) == hec.INVALID_ARG
+    assert L.hec_set_trsv_grid(1) == hec.OK
+    assert L.levels_grid(None, None) == hec.INVALID_ARG
+
+
+def test_every_binding_declares_its_argument_types():
+    """Handles are 64-bit pointers: an entry point bound without argument types would pass
+    them through ctypes' default int conversion, truncated."""
+    L = hec.load()
+    for name in hec.EXPORTED:
+        if name != "hec_last_error":
+            assert getattr(L, name).argtypes is not None, name

@@ -1,9 +1,9 @@
 """Every device-side wait of the triangular solves is bounded. Forced from the host
 with a spin limit of zero polls (a wait gives up at its first unready poll), the
 launches still end and the failure is reported as HEC_ERR_TIMEOUT (by levels_check,
-by the solvers, by the batched solver), for the blocked solve, its FP32 form and the
-per-row polling fallback; with the default limit restored, the same handles solve
-correctly again."""
+by the solvers, by the batched solver), for the wavefront solve and the blocked solve
+(each in FP64 and FP32) and the per-row polling fallback; with the default limit
+restored, the same handles solve correctly again."""
 import numpy as np
 import pytest
 
@@ -24,16 +24,26 @@ def _oracle_lu(A, k, b):
     return O.trsv_upper(Fo, O.trsv_lower(Fo, b))
 
 
-@pytest.mark.parametrize("case", ["blocked_f64", "blocked_f32", "fallback"])
+@pytest.mark.parametrize("case", ["grid_f64", "grid_f32", "blocked_f64", "blocked_f32", "fallback"])
 def test_zero_spin_limit_gives_up_and_recovers(case):
     import torch
     if case == "fallback":  # ILU(3) rows carry more than 32 entries: the per-row polling kernel
         A, k = synth.poisson3d(14), 3
     else:
         A, k = synth.workload_diffusion3d(40, sigma=2.0, seed=5)[0], 0
-    f32 = case == "blocked_f32"
+    f32 = case.endswith("f32")
     F = hec.ilu_factor(A, k=k, keep_f32=f32)
     lv = hec.level_schedule(F)
+    assert hec.levels_grid(lv) == (k == 0)
+    hec.set_trsv_grid(not case.startswith("blocked"))
+    try:
+        _give_up_and_recover(A, k, F, lv, f32)
+    finally:
+        hec.set_trsv_grid(True)
+
+
+def _give_up_and_recover(A, k, F, lv, f32):
+    import torch
     M = hec.hec_from_csr(A)
     b = _rhs(A, 3)
     dt = torch.float32 if f32 else torch.float64

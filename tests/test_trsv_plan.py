@@ -468,3 +468,124 @@ def test_detect_grid():
     D.sort_indices()
     B = synth.CSR(A.n, D.indptr.astype(np.int32), D.indices.astype(np.int32), D.data)
     assert _plan.detect_grid(B) == (0, 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# Wavefront plans (7-point ILU(0) triangles on 3D grids)
+
+def replay_grid(G, F, rhs, upper):
+    """The wavefront solve replayed on the host as the kernel runs it: claims in order,
+    steps in order, the 64 lanes of a step at once. A lane's dependencies come from its
+    own result of the previous step (behind along c), lanes (ma - 1, mb) and (ma, mb - 1)
+    of the previous step, or, on the tile's low faces, the face values that earlier
+    claims stored, at the indices the kernel uses (the corner lane's value only on the
+    a-face); a face value read must already have been stored. The subtractions run in the kernel's order (lower: back, below, left;
+    upper: left, below, back, then the pivot, here a division as in the oracle)."""
+    NA, NB, NC, PA, PB, S, nco = (G[k] for k in ("NA", "NB", "NC", "PA", "PB", "S", "ncoef"))
+    sa, sb, sc = G["sa"], G["sb"], G["sc"]
+    lanes = np.arange(64)
+    ma, mb = lanes % 8, lanes // 8
+    src = G["src"].reshape(PA * PB, S, nco, 64)
+    vals = np.where(src >= 0, F.LUx[np.maximum(src, 0)], 0.0)
+    x = np.full(F.n, np.nan)
+    written = np.zeros(F.n, np.int32)
+    faces = np.full((PA * PB, 2, S, 8), np.nan)
+    la, lb = (7 - ma, 7 - mb) if upper else (ma, mb)
+    for c in range(PA * PB):
+        mta, mtb = c % PA, c // PA
+        ta, tb = (PA - 1 - mta, PB - 1 - mtb) if upper else (mta, mtb)
+        ga, gb = ta * 8 + la, tb * 8 + lb
+        act = (ga < NA) & (gb < NB)
+        base = ga * sa + gb * sb
+        xp = np.zeros(64)
+        for s in range(S):
+            left_l = np.concatenate(([0.0], xp[:-1]))
+            below_l = np.concatenate((np.zeros(8), xp[:-8]))
+            mc = s - ma - mb
+            valid = act & (mc >= 0) & (mc < NC)
+            fa, fb = np.zeros(64), np.zeros(64)
+            if mta > 0:
+                need = (ma == 0) & valid
+                fa[need] = faces[c - 1, 0, s, mb[need]]
+                assert not np.isnan(fa[need]).any(), (c, s)
+            if mtb > 0:  # b-face of the tile below; its corner (ma = 7) on that tile's a-face
+                need = (mb == 0) & valid
+                fb[need] = np.where(ma[need] == 7, faces[c - PA, 0, s, 7], faces[c - PA, 1, s, ma[need]])
+                assert not np.isnan(fb[need]).any(), (c, s)
+            left = np.where(ma == 0, fa, left_l)
+            below = np.where(mb == 0, fb, below_l)
+            gc = (NC - 1 - mc) if upper else mc
+            row = np.where(valid, base + gc * sc, 0)
+            bv = np.where(valid, rhs[row], 0.0)
+            cv = vals[c, s]
+            if not upper:
+                acc = bv - cv[0] * xp
+                acc = acc - cv[1] * below
+                acc = acc - cv[2] * left
+            else:
+                acc = bv - cv[2] * left
+                acc = acc - cv[1] * below
+                acc = acc - cv[0] * xp
+                piv = np.where(valid, F.LUx[np.maximum(src[c, s, 3], 0)], 1.0)
+                acc = acc / piv
+            xn = np.where(valid, acc, 0.0)
+            x[row[valid]] = xn[valid]
+            written[row[valid]] += 1
+            sel = (ma == 7) & valid  # the a-face, corner included, whether or not a tile reads it
+            faces[c, 0, s - 7, mb[sel]] = xn[sel]
+            if mtb < PB - 1:
+                sel = (mb == 7) & (ma < 7) & valid
+                faces[c, 1, s - 7, ma[sel]] = xn[sel]
+            xp = xn
+    assert (written == 1).all()  # every row solved exactly once
+    return x
+
+
+@pytest.mark.parametrize("shape,exact", [((24, 24, 24), True), ((19, 13, 30), True), ((41, 37, 23), False),
+                                         ((8, 9, 8), False), ((9, 8, 10), True)])
+def test_grid_plan_replay(shape, exact):
+    """Wavefront plans of ILU(0) triangles of 7-point grids, tiles ragged along both tile
+    axes where the extents are not multiples of 8, replayed on the host in kernel order:
+    every row solved once, every face value read after it is stored, and the result equal
+    to the oracle's substitution -- bit for bit where the columns run along z (the
+    kernel's subtraction order is then the oracle's), within rounding otherwise."""
+    A = synth.lognormal_tpfa(shape, 2.0, np.random.default_rng(21))
+    F = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    grid = _plan.detect_grid(A)
+    assert grid == shape
+    b = np.random.default_rng(22).uniform(-1, 1, A.n)
+    y_o = O.trsv_lower(F, b)
+    x_o = O.trsv_upper(F, y_o)
+    for upper, rhs, ref in ((False, b, y_o), (True, y_o, x_o)):
+        G = _plan.make_grid_plan(F, upper, grid)
+        assert G is not None
+        longest = int(np.argmax(np.array(shape) + np.array([0, 1e-3, 2e-3])))  # ties: the largest stride
+        assert G["NC"] == shape[longest] and G["S"] == G["NC"] + 14
+        assert G["ncoef"] == (4 if upper else 3)
+        x = replay_grid(G, F, rhs, upper)
+        if exact:
+            assert np.array_equal(x.view(np.uint64), ref.view(np.uint64))
+        else:
+            assert np.allclose(x, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_grid_plan_refusals():
+    """Wavefront plans only where they apply: ILU(1) fill (an entry off the three
+    neighbours behind a row), a 2D grid, fewer than 8 columns along a tile axis, and a
+    matrix that is no grid all get none."""
+    A = synth.poisson3d(16)
+    F1 = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 1)
+    assert _plan.make_grid_plan(F1, False, (16, 16, 16)) is None
+    assert _plan.make_grid_plan(F1, True, (16, 16, 16)) is None
+    F0 = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    assert _plan.make_grid_plan(F0, False, (16, 16, 16)) is not None
+    A2 = synth.poisson2d(64)
+    F2 = O.iluk(A2.n, A2.Ap, A2.Aj, A2.Ax, 0)
+    assert _plan.make_grid_plan(F2, False, (64, 64, 1)) is None
+    A3 = synth.lognormal_tpfa((7, 30, 30), 1.0, np.random.default_rng(3))
+    F3 = O.iluk(A3.n, A3.Ap, A3.Aj, A3.Ax, 0)
+    assert _plan.make_grid_plan(F3, False, (7, 30, 30)) is None
+    R = sparse_random(4096, 6, 5)
+    FR = O.iluk(R.n, R.Ap, R.Aj, R.Ax, 0)
+    assert _plan.make_grid_plan(FR, False, (16, 16, 16)) is None  # wrong offsets for this "grid"
+    assert _plan.make_grid_plan(FR, False, (0, 0, 0)) is None
