@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes moved by one preconditioner solve (lower + upper k_trsv_blk) on the 128^3 system, measured with
+# HBM bytes moved by one preconditioner solve (lower + upper launch) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
 TRSV_PAIR_TRAFFIC = None
@@ -295,8 +295,10 @@ def main():
     # share of the step spent in the triangular solves (one L-then-U solve per Arnoldi step)
     trsv_share = t_trsv_lu * it_per_solve / (ms_per_step / 1e3)
 
-    roof = {"kernel": "k_trsv_blk<double,false,4> + k_trsv_blk<double,true,4> "
-                      "(one preconditioner solve: the lower and the upper launch)",
+    grid = hec.levels_grid(lv)  # the wavefront kernel (7-point ILU(0) on a grid) or the level-blocked one
+    kname = ("k_trsv_grid<double,false> + k_trsv_grid<double,true>" if grid else
+             "k_trsv_blk<double,false,4> + k_trsv_blk<double,true,4>")
+    roof = {"kernel": kname + " (one preconditioner solve: the lower and the upper launch)",
             "bound": "hbm", "achieved": round(trsv_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(trsv_gbs / HBM_PEAK_GBS, 5), "traffic": TRSV_PAIR_TRAFFIC if m == 128 else None,
             "traffic_note": "HBM bytes of one lower + one upper launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
@@ -317,19 +319,27 @@ def main():
                  "bytes": spmv_bytes, "gflops": round(2 * nnz / t_spmv / 1e9, 1),
                  "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(spmv_gbs / copy_gbs, 4)}
 
-    # latency bound of the triangular solve: the cost of one level measured on a chain (a 1D
-    # Poisson factor: 4096 levels of one row in one part), times the levels of both triangles
-    Ac = synth.poisson1d(4096)
+    # latency bound of the triangular solve: the cost of one level on a solve that has nothing to
+    # wait for but its own previous level, times the levels of both triangles. Wavefront kernel: one
+    # tile of 8 x 8 columns, 4096 long (4110 steps, no other tile); blocked kernel: a chain (1D Poisson,
+    # 4096 levels of one row in one part)
+    if grid:
+        Ac = synth.lognormal_tpfa((8, 8, 4096), 2.0, np.random.default_rng(2))
+        what = "lower solve of one 8 x 8 x 4096 tile (4110 wavefront steps, nothing to wait for) / 4110"
+    else:
+        Ac = synth.poisson1d(4096)
+        what = "lower solve of a 4096-row chain (one row per level, one part) / 4096"
     Fc = hec.ilu_factor(Ac, k=0)
     lvc = hec.level_schedule(Fc)
     bc = torch.ones(Ac.n, dtype=torch.float64, device=dev)
     zc = torch.empty_like(bc)
     t_chain = time_launches(lambda: hec.trsv_levels(Fc, lvc, bc, zc, hec.LOWER), 20, stream)
-    t_level = t_chain / hec.levels_info(lvc)["nlev_lower"]
+    t_level = t_chain / (4096 + 14 if grid else hec.levels_info(lvc)["nlev_lower"])
     lat_bound = (li["nlev_lower"] + li["nlev_upper"]) * t_level
     roof["latency"] = {"t_level_us": round(t_level * 1e6, 4),
                        "bound_us": round(lat_bound * 1e6, 1), "frac": round(lat_bound / t_trsv_lu, 4),
-                       "note": "t_level = lower solve of a 4096-row chain (one row per level, one part) / 4096"}
+                       "note": "t_level = " + what}
+    del Fc, lvc
 
     # ---- CPU oracle: one full solve of the same system on one pinned core ----
     cpu = None

@@ -267,9 +267,11 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
 /* ---------------------------------------------------------------- Krylov solvers */
 
 /* Restarted GMRES(m) (Sec. 2.7), right-preconditioned with M = LU:
- * x = x0 + M^{-1} V y minimising ||b - A x|| over each cycle; classical
- * Gram-Schmidt applied twice, Givens rotations, convergence decided by the FP64
- * true residual. precision = 1: iterative refinement in FP64 around inner
+ * x = x0 + Z y, Z = M^{-1} applied to the Arnoldi vectors, minimising
+ * ||b - A x|| over each cycle; classical Gram-Schmidt applied twice (with an FP64
+ * basis the second application to each vector is delayed into the next step,
+ * which equals the plain form in exact arithmetic), Givens rotations,
+ * convergence decided by the FP64 true residual. precision = 1: iterative refinement in FP64 around inner
  * GMRES solves that use the FP32 copies of A and of the factor (both handles
  * built with HEC_KEEP_F32) and an FP32 Krylov basis. b, x: device FP64.
  * ||b|| == 0 gives x = 0, OK, 0 iterations. On NOT_CONVERGED x holds the last

@@ -35,6 +35,7 @@ constexpr int kMaxRedBlocks = 1024;
 #define HEC_BASIS_PAD 1088
 #endif
 constexpr int kMaxRestart = 32;  // the orthogonalisation keeps up to 32 basis coefficients in registers
+constexpr int kDSums = 2 * kMaxRestart + 4;  // sums of one Gram-Schmidt dot pass: 2 per final vector + 3
 
 inline int red_blocks(int64_t n) {
     int64_t b = (n + RB * 2 - 1) / (RB * 2);
@@ -51,12 +52,13 @@ enum : int {
     SD_RHO = 5, SD_RHO_PREV = 6, SD_ALPHA = 7, SD_OMEGA = 8,       // BiCGSTAB
     SD_SNORM2 = 9, SD_RNORM2 = 10, SD_CGBETA = 11,                 // CG: beta
     SD_TRUE = 12,                                                  // GMRES: true residual norm after a cycle
+    SD_PROV = 13,  // GMRES: norm of the last once-orthogonalised vector (its column's provisional subdiagonal)
     SD_SCALARS = 16
 };
 
 struct GLayout {
     int m;
-    int H, cs, sn, g, y, h1, h2, total;
+    int H, cs, sn, g, y, h1, h2, ds, total;  // ds: the sums of a Gram-Schmidt dot pass
     explicit GLayout(int m_ = 0) : m(m_) {
         H = SD_SCALARS;
         cs = H + (m + 1) * m;
@@ -65,7 +67,8 @@ struct GLayout {
         y = g + m + 1;
         h1 = y + m;
         h2 = h1 + kMaxRestart;
-        total = h2 + kMaxRestart;
+        ds = h2 + kMaxRestart;
+        total = ds + kDSums;
     }
     __host__ __device__ int Hij(int i, int j) const { return H + j * (m + 1) + i; }
 };
@@ -192,11 +195,12 @@ struct OpCycleStart : NoInit {
 // earlier rotations applied to the column, a new rotation zeroing h_{j+1,j}, g
 // updated, and the convergence test |g_{j+1}| <= tol (or hn == 0). The column and
 // the rotations are read in parallel into LDS; one thread applies the rotations.
-__device__ void givens_block(int j, double hn, double *sd, int32_t *si, int32_t *hf, const GLayout &L) {
+__device__ void givens_col(int j, double hn, const double *src, double *sd, int32_t *si, int32_t *hf,
+                           const GLayout &L) {
     __shared__ double col[kMaxRestart + 1];
     __shared__ double rcs[kMaxRestart], rsn[kMaxRestart];
     const int t = threadIdx.x;
-    if (t <= j) col[t] = sd[L.h1 + t] + sd[L.h2 + t];
+    if (t <= j) col[t] = src[t];
     if (t < j) {
         rcs[t] = sd[L.cs + t];
         rsn[t] = sd[L.sn + t];
@@ -234,6 +238,14 @@ __device__ void givens_block(int j, double hn, double *sd, int32_t *si, int32_t 
     }
     __syncthreads();
     if (t <= j) sd[L.Hij(t, j)] = col[t];
+}
+
+// The same with the column h1 + h2 (the two Gram-Schmidt passes' coefficients).
+__device__ void givens_block(int j, double hn, double *sd, int32_t *si, int32_t *hf, const GLayout &L) {
+    __shared__ double sum[kMaxRestart + 1];
+    if ((int)threadIdx.x <= j) sum[threadIdx.x] = sd[L.h1 + threadIdx.x] + sd[L.h2 + threadIdx.x];
+    __syncthreads();
+    givens_col(j, hn, sum, sd, si, hf, L);
 }
 
 // Element i of a vector; NT: a non-temporal (streaming) load.
@@ -419,6 +431,215 @@ __global__ __launch_bounds__(RB) void k_finish_scale(int64_t n, const VT *__rest
     if (!vnext) return;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
         vnext[i] = (VT)((double)w[i] / hn);
+}
+
+// ------------------------------------------------ Gram-Schmidt with delayed reorthogonalisation
+// Classical Gram-Schmidt applied twice, with the second application to each vector
+// lagged into the next Arnoldi step (delayed CGS2, Hernandez, Roman and Tomas 2007), so
+// that a step reads the basis twice instead of three times. At step s the basis holds
+// the final vectors V_0 .. V_{s-1} (nf = s of them) and u = V_s, orthogonalised once and
+// scaled to unit norm. One dot pass gives a = V_f^T u, t = V_f^T w, c = u.u, d = u.w and
+// e = w.w for w = A z_s, z_s = M^{-1} u. Then u' = (u - V_f a) / alpha, alpha^2 = c - a.a,
+// is the final v_s; the previous column is completed for it (A z_{s-1} was expressed with
+// u: its entries gain its subdiagonal times a, its subdiagonal is multiplied by alpha);
+// w is orthogonalised once against [V_f, u'] with the coefficients t and
+// h_ss = (d - a.t) / alpha, and its norm follows from Pythagoras, beta^2 = e - t.t - h_ss^2
+// (w is orthogonalised a second time, against the final basis, in the next step). One
+// update pass writes v_s = u' and v_{s+1} = (w - V_f (t - a h_ss / alpha) - u h_ss / alpha)
+// / beta. The stored z_s = M^{-1} u keeps A Z = V H exact (as flexible GMRES does), so
+// x = x0 + Z y is unchanged in kind. A cycle ends with a dot pass over u alone that
+// completes the last column.
+
+// Dot pass: per workgroup the 2 nf + 3 partial sums [a_0..a_{nf-1}, t_0.., c, d, e] at
+// part[k * gridDim.x + block]; w == NULL (a cycle's tail): t, d, e are 0.
+template <class VT, int NB>
+__global__ __launch_bounds__(RB) void k_dgs_dots(int64_t n, const VT *__restrict__ V, int64_t ldv, int nf,
+                                                 const VT *__restrict__ w, double *part, const int32_t *skip) {
+    constexpr int U = kMaxRestart / NB;
+    constexpr int64_t TR = 64 * U;
+    if (skip && *skip) return;
+    __shared__ double red[4][2 * NB + 4];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    double aa[NB], at[NB], sc[4];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) aa[k] = at[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sc[k] = 0.0;
+    constexpr bool NT = NB == kMaxRestart || sizeof(VT) == 4;
+    const VT *u = V + (int64_t)nf * ldv;
+    const int64_t nsteps = (n + TR - 1) / TR;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + q; t < nsteps; t += (int64_t)gridDim.x * 4) {
+        VT vk[U][NB];
+        VT uv[U], wv[U];
+        const bool inside = (t + 1) * TR <= n;
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int64_t i = t * TR + 64 * c + lane;
+            const bool live = inside || i < n;
+            uv[c] = live ? load_elem<VT, NT>(u, i) : (VT)0;
+            wv[c] = live && w ? load_elem<VT, NT>(w, i) : (VT)0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) vk[c][k] = live && k < nf ? load_elem<VT, NT>(V + k * ldv, i) : (VT)0;
+        }
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const double ud = (double)uv[c], wd = (double)wv[c];
+            sc[0] += ud * ud;
+            sc[1] += ud * wd;
+            sc[2] += wd * wd;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                aa[k] += (double)vk[c][k] * ud;
+                at[k] += (double)vk[c][k] * wd;
+            }
+        }
+    }
+    const double va = multi_wave_sum<NB>(aa, lane);
+    const double vt = multi_wave_sum<NB>(at, lane);
+    const double vs = multi_wave_sum<4>(sc, lane);
+    if ((lane & (64 / NB - 1)) == 0) {
+        red[q][cgs_sum_index<NB>(lane)] = va;
+        red[q][NB + cgs_sum_index<NB>(lane)] = vt;
+    }
+    if ((lane & 15) == 0) red[q][2 * NB + cgs_sum_index<4>(lane)] = vs;
+    __syncthreads();
+    const int cnt = 2 * nf + 3;
+    if ((int)threadIdx.x < cnt) {
+        const int k = threadIdx.x;
+        const int src = k < nf ? k : k < 2 * nf ? NB + (k - nf) : 2 * NB + (k - 2 * nf);
+        part[(size_t)k * gridDim.x + blockIdx.x] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+    }
+}
+
+// Update pass of step s (nf = s), after the dot pass's sums were finished into sd[L.ds].
+// Every workgroup first forms the step's scalars from those sums in the same order (so all
+// agree); workgroup 0 also completes column s-1 (its Givens step and convergence test) and
+// stores column s, provisional until the next step (a happy breakdown, beta = 0, completes
+// it at once). Then v_s = u' and v_{s+1} are written in one pass over the rows.
+// w == NULL: the cycle's tail (column s-1 only; no vector work).
+template <class VT, int NB>
+__global__ __launch_bounds__(RB) void k_dgs_update(int64_t n, VT *V, int64_t ldv, int nf, const VT *__restrict__ w,
+                                                   const int32_t *skip, double *sd, int32_t *si, int32_t *hf,
+                                                   GLayout L) {
+    constexpr int U = kMaxRestart / NB;
+    constexpr int64_t TR = 64 * U;
+    if (skip && *skip) return;
+    __shared__ double ca[NB], ct[NB], sv[4], col[kMaxRestart + 1];
+    const double *ds = sd + L.ds;
+    if (threadIdx.x == 0) {
+        double alpha = 1.0;  // v_0 = r / ||r|| is final as it stands
+        if (nf > 0) {
+            double aa = 0.0;
+            for (int k = 0; k < nf; ++k) aa += ds[k] * ds[k];
+            alpha = sqrt(fmax(ds[2 * nf] - aa, 0.0));
+            if (!(alpha > 0.0)) alpha = 1.0;  // u in the span of V_f: only after a breakdown the flags already stop
+        }
+        double h = 0.0, beta = 0.0;
+        if (w) {
+            double at = 0.0, tt = 0.0;
+            for (int k = 0; k < nf; ++k) {
+                at += ds[k] * ds[nf + k];
+                tt += ds[nf + k] * ds[nf + k];
+            }
+            h = (ds[2 * nf + 1] - at) / alpha;
+            beta = sqrt(fmax(ds[2 * nf + 2] - tt - h * h, 0.0));
+        }
+        sv[0] = alpha;
+        sv[1] = h;
+        sv[2] = beta;
+    }
+    __syncthreads();
+    const double alpha = sv[0], h = sv[1], beta = sv[2];
+    const double cu = h / alpha;
+    if ((int)threadIdx.x < nf) {
+        const int k = threadIdx.x;
+        ca[k] = ds[k];
+        ct[k] = ds[nf + k] - ds[k] * cu;
+    }
+    if (blockIdx.x == 0) {
+        // column s - 1, complete now: entries += its provisional subdiagonal times a
+        if (nf > 0) {
+            const double hp = sd[SD_PROV];
+            if ((int)threadIdx.x < nf) col[threadIdx.x] = sd[L.h2 + threadIdx.x] + hp * ds[threadIdx.x];
+            __syncthreads();
+            givens_col(nf - 1, hp * alpha, col, sd, si, hf, L);
+        }
+        __syncthreads();
+        if (w && !si[SI_DONE]) {
+            // column s, provisional: [t, h]; the subdiagonal beta is completed next step
+            if ((int)threadIdx.x < nf) sd[L.h2 + threadIdx.x] = ds[nf + threadIdx.x];
+            if (threadIdx.x == 0) {
+                sd[L.h2 + nf] = h;
+                sd[SD_PROV] = beta;
+            }
+            __syncthreads();
+            if (beta == 0.0) {  // happy breakdown: nothing left to orthogonalise, the column is final
+                if ((int)threadIdx.x <= nf) col[threadIdx.x] = sd[L.h2 + threadIdx.x];
+                __syncthreads();
+                givens_col(nf, 0.0, col, sd, si, hf, L);
+            }
+        }
+    }
+    __syncthreads();
+    if (!w) return;
+    const double bdiv = beta > 0.0 ? beta : 1.0;
+    VT *const u = V + (int64_t)nf * ldv;
+    VT *const vn = u + ldv;
+    constexpr bool NT = NB == kMaxRestart || sizeof(VT) == 4;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t nsteps = (n + TR - 1) / TR;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + q; t < nsteps; t += (int64_t)gridDim.x * 4) {
+        VT vk[U][NB];
+        VT uv[U], wv[U];
+        const bool inside = (t + 1) * TR <= n;
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int64_t i = t * TR + 64 * c + lane;
+            const bool live = inside || i < n;
+            uv[c] = live ? load_elem<VT, NT>(u, i) : (VT)0;
+            wv[c] = live ? load_elem<VT, NT>(w, i) : (VT)0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) vk[c][k] = live && k < nf ? load_elem<VT, NT>(V + k * ldv, i) : (VT)0;
+        }
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            double sa = 0.0, st = 0.0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (k < nf) {
+                    sa += (double)vk[c][k] * ca[k];
+                    st += (double)vk[c][k] * ct[k];
+                }
+            const int64_t i = t * TR + 64 * c + lane;
+            if (i < n) {
+                const double ud = (double)uv[c];
+                if (nf > 0) u[i] = (VT)((ud - sa) / alpha);
+                vn[i] = (VT)(((double)wv[c] - st - ud * cu) / bdiv);
+            }
+        }
+    }
+}
+
+template <class VT>
+void launch_dgs(unsigned gd, unsigned gu, int64_t n, VT *V, int64_t ldv, int nf, const VT *w, double *part,
+                const int32_t *skip, double *sd, int32_t *si, int32_t *hf, const GLayout &L, hipStream_t s) {
+    auto go = [&](auto nb) {
+        constexpr int NB = decltype(nb)::value;
+        k_dgs_dots<VT, NB><<<gd, RB, 0, s>>>(n, V, ldv, nf, w, part, skip);
+        HEC_CHECK_LAUNCH();
+        k_cgs_finish<<<2 * nf + 3, RB, 0, s>>>(part, gd, sd + L.ds, skip);
+        HEC_CHECK_LAUNCH();
+        k_dgs_update<VT, NB><<<w ? gu : 1u, RB, 0, s>>>(n, V, ldv, nf, w, skip, sd, si, hf, L);
+        HEC_CHECK_LAUNCH();
+    };
+    if (nf <= 4)
+        go(std::integral_constant<int, 4>());
+    else if (nf <= 8)
+        go(std::integral_constant<int, 8>());
+    else if (nf <= 16)
+        go(std::integral_constant<int, 16>());
+    else
+        go(std::integral_constant<int, 32>());
 }
 
 // A Gram-Schmidt pass with the smallest vector bound NB >= nv.
@@ -831,7 +1052,7 @@ static KrylovWS &get_ws(hec_matrix_s &A, int m, bool mixed, bool bicg, hipStream
     GLayout L(std::max(mm, 1));
     nw->sd.alloc(std::max(L.total, SD_SCALARS + 8));
     nw->si.alloc(SI_COUNT);
-    nw->part.alloc((size_t)nw->nred * (kMaxRestart + 1));
+    nw->part.alloc((size_t)nw->nred * kDSums);
     HEC_HIP(hipMemsetAsync(nw->si.get(), 0, SI_COUNT * sizeof(int32_t), s));
     nw->hflags = take_flags();
     nw->hsd = (double *)((char *)nw->hflags + kScalarsOffset);
@@ -882,34 +1103,60 @@ static int gmres_cycle(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, int mcyc
     HEC_CHECK_LAUNCH();
     // no wait here: if the start is already converged, the queued steps return at entry
     // (the device's done flag) and the cycle adds no columns to x
-    for (int j = 0; j < mcyc; ++j) {
-        // look two iterations behind, every other iteration: stop issuing work once the
-        // device is done. An event record costs the stream about 6 us (it waits for the
-        // previous kernel and flushes to system scope), so only odd steps record one.
-        if (j >= 3 && (j & 1) && ws.hflags) {  // (without mapped flags every step is queued)
-            HEC_HIP(hipEventSynchronize(ws.ev[j - 1]));
-            if (hf(ws)[SI_DONE]) break;
+    if constexpr (sizeof(VT) == 8) {
+        // FP64 basis: delayed reorthogonalisation, two passes over the basis per step
+        const unsigned gd = ws.nred;
+        const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(n, (int64_t)RB * 8), kMaxRedBlocks);
+        for (int j = 0; j <= mcyc; ++j) {
+            // look two iterations behind, every other iteration: stop issuing work once the
+            // device is done. An event record costs the stream about 6 us (it waits for the
+            // previous kernel and flushes to system scope), so only odd steps record one.
+            if (j >= 3 && (j & 1) && ws.hflags) {  // (without mapped flags every step is queued)
+                HEC_HIP(hipEventSynchronize(ws.ev[j - 1]));
+                if (hf(ws)[SI_DONE]) break;
+            }
+            // step j: z_j = M^{-1} v_j, w = A z_j, then the two Gram-Schmidt passes (delayed
+            // reorthogonalisation); j == mcyc: only the pass that completes the last column
+            const bool tail = j == mcyc;
+            if (!tail) {
+                VT *vj = V + j * ldv, *zj = Z + j * ldv;
+                trsv_launch<VT>(lv, HEC_LU, vj, zj, s, done);
+                spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
+            }
+            launch_dgs<VT>(gd, gu, n, V, ldv, j, tail ? nullptr : w, ws.part.get(), done, sd, si, ws.dflags, L, s);
+            if ((j & 1) && ws.hflags) HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
         }
-        VT *vj = V + j * ldv, *zj = Z + j * ldv;
-        trsv_launch<VT>(lv, HEC_LU, vj, zj, s, done);
-        spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
-        const int nv = j + 1;
-        const unsigned g = ws.nred;
-        double *part = ws.part.get();
-        launch_cgs<VT, 1>(g, n, V, ldv, w, nv, nullptr, part, done, s);
-        k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h1, done);
-        HEC_CHECK_LAUNCH();
-        launch_cgs<VT, 2>(g, n, V, ldv, w, nv, sd + L.h1, part, done, s);
-        k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h2, done);
-        HEC_CHECK_LAUNCH();
-        launch_cgs<VT, 3>(g, n, V, ldv, w, nv, sd + L.h2, part, done, s);
-        {
-            VT *vnext = j + 1 < mcyc ? V + (j + 1) * ldv : nullptr;  // the cycle's last step scales nothing
-            const unsigned gs = vnext ? (unsigned)std::min<int64_t>(ceil_div(n, (int64_t)RB * 8), kMaxRedBlocks) : 1u;
-            k_finish_scale<VT><<<gs, RB, 0, s>>>(n, w, vnext, part, g, nv, done, sd, si, ws.dflags, L);
+    } else {
+        // FP32 basis: classical Gram-Schmidt twice in each step (three passes: the
+        // delayed form's fused dot pass keeps twice the FP64 accumulators of a pass
+        // here, and on FP32 data it ran 5x slower than these: 189 against 38 us)
+        for (int j = 0; j < mcyc; ++j) {
+            if (j >= 3 && (j & 1) && ws.hflags) {
+                HEC_HIP(hipEventSynchronize(ws.ev[j - 1]));
+                if (hf(ws)[SI_DONE]) break;
+            }
+            VT *vj = V + j * ldv, *zj = Z + j * ldv;
+            trsv_launch<VT>(lv, HEC_LU, vj, zj, s, done);
+            spmv_launch<VT, VT, VT>(A, 1.0, zj, 0.0, w, w, s, done);
+            const int nv = j + 1;
+            const unsigned g = ws.nred;
+            double *part = ws.part.get();
+            launch_cgs<VT, 1>(g, n, V, ldv, w, nv, nullptr, part, done, s);
+            k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h1, done);
             HEC_CHECK_LAUNCH();
+            launch_cgs<VT, 2>(g, n, V, ldv, w, nv, sd + L.h1, part, done, s);
+            k_cgs_finish<<<nv, RB, 0, s>>>(part, g, sd + L.h2, done);
+            HEC_CHECK_LAUNCH();
+            launch_cgs<VT, 3>(g, n, V, ldv, w, nv, sd + L.h2, part, done, s);
+            {
+                VT *vnext = j + 1 < mcyc ? V + (j + 1) * ldv : nullptr;  // the cycle's last step scales nothing
+                const unsigned gs =
+                    vnext ? (unsigned)std::min<int64_t>(ceil_div(n, (int64_t)RB * 8), kMaxRedBlocks) : 1u;
+                k_finish_scale<VT><<<gs, RB, 0, s>>>(n, w, vnext, part, g, nv, done, sd, si, ws.dflags, L);
+                HEC_CHECK_LAUNCH();
+            }
+            if ((j & 1) && ws.hflags) HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
         }
-        if ((j & 1) && ws.hflags) HEC_HIP(hipEventRecord(ws.ev[j + 1], s));
     }
     k_backsolve<<<1, 64, 0, s>>>(sd, si, L);
     HEC_CHECK_LAUNCH();
@@ -1034,7 +1281,7 @@ static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const dou
 // comes from hipGetSymbolAddress on the first call made with that device current.
 constexpr int64_t kNoAllocLdv = HEC_NOALLOC_MAX_N + HEC_BASIS_PAD;  // widest basis vector (n rounded to 64)
 constexpr int64_t kNoAllocSd = 2048;                                // scalars + Hessenberg (GLayout(32) needs 1265)
-constexpr int64_t kNoAllocPart = 2048;                              // partial sums: nred * 33 (32 * 33 at most)
+constexpr int64_t kNoAllocPart = 4096;                              // partial sums: nred * 68 (32 * 68 at most)
 constexpr int64_t kNoAllocSi = 64;                                  // SI_COUNT int32 flags, in doubles
 constexpr int64_t kNoAllocDoubles = (2 * kMaxRestart + 3) * kNoAllocLdv + kNoAllocSd + kNoAllocPart + kNoAllocSi;
 static_assert(HEC_NOALLOC_MAX_N % 64 == 0, "the no-allocation bound keeps basis vectors 64-aligned");
@@ -1072,7 +1319,7 @@ static void noalloc_workspace(KrylovWS &ws, int64_t n, int m, hipStream_t s) {
     ws.m = m;
     ws.nred = red_blocks(n);
     const int64_t ldv = ws.ldv;
-    if (GLayout(m).total > kNoAllocSd || (int64_t)ws.nred * (kMaxRestart + 1) > kNoAllocPart || ldv > kNoAllocLdv)
+    if (GLayout(m).total > kNoAllocSd || (int64_t)ws.nred * kDSums > kNoAllocPart || ldv > kNoAllocLdv)
         fail(HEC_ERR_INVALID_ARG, "system too large for the no-allocation scratch");
     double *q = base;
     ws.V.borrow(q, (size_t)(m + 1) * ldv);
