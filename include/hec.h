@@ -212,8 +212,8 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out);
 
 hec_status levels_info(hec_levels lv, int32_t *n, int32_t *nlev_lower, int32_t *nlev_upper);
 
-/* *grid = 1 when lv carries wavefront plans for both triangles (the kernel that
- * hec_set_trsv_grid selects), else 0. */
+/* *grid = 1 when lv carries wavefront plans for both triangles (see
+ * hec_set_trsv_grid), else 0 (level-blocked plans). */
 hec_status levels_grid(hec_levels lv, int32_t *grid);
 
 /* Copy the schedules to host buffers: ptr arrays of nlev+1, perm arrays of n. */
@@ -234,18 +234,18 @@ hec_status levels_destroy(hec_levels lv);
  * launches made after the call, from any thread. */
 hec_status hec_set_spin_limit(int64_t polls);
 
-/* Chooses the triangular-solve kernel for schedules that carry a wavefront plan.
- * level_schedule gives one to both triangles of a factor on a natural-order 3D
- * grid (detected from A) whose strict triangles hold only the three grid
- * neighbours behind each row, as ILU(0) of a 7-point stencil does (Sec. 2.6: the
- * level of a row is then the sum of its coordinates, Eq. (11)). Such a solve runs
- * tiles of 8 x 8 grid columns, one wavefront each, whose lanes step through the
- * levels together, passing results between neighbouring lanes through LDS.
- * enable = 1 (the default) uses it; 0 uses the level-blocked kernel that serves
- * every other factor. Both perform each row's subtractions (fused multiply-adds)
- * and may differ in rounding only where their order differs. Applies to
- * solves issued after the call, from any thread; a solve already captured in a
- * graph keeps its kernel. INVALID_ARG unless enable is 0 or 1. */
+/* Chooses the triangular-solve kernel of the schedules level_schedule builds after
+ * the call (from any thread). With enable = 1 (the default), a factor on a
+ * natural-order 3D grid (detected from A) whose strict triangles hold only the
+ * three grid neighbours behind each row, as ILU(0) of a 7-point stencil does
+ * (Sec. 2.6: the level of a row is then the sum of its coordinates, Eq. (11)),
+ * gets wavefront plans for both triangles: tiles of 8 x 8 grid columns, one
+ * wavefront each, whose lanes step through the levels together, passing results
+ * between neighbouring lanes through LDS. Every other factor, and every factor
+ * with enable = 0, gets the level-blocked plans. A schedule keeps the kind it was
+ * built with (levels_grid reports it). Both kernels perform each row's
+ * subtractions (fused multiply-adds) and may differ in rounding only where their
+ * order differs. INVALID_ARG unless enable is 0 or 1. */
 hec_status hec_set_trsv_grid(int32_t enable);
 
 /* Synchronises `stream`, then reports (and clears) a wait of lv's triangular

@@ -290,7 +290,8 @@ struct hec_tri {
     hec::DevBuf<float> val32;
     hec::DevBuf<double> piv;        // upper only: u_ii per position
     hec::DevBuf<float> piv32;
-    hec_grid grid;                  // wavefront plan (7-point ILU(0) grids), used when on
+    hec_grid grid;                  // wavefront plan (7-point ILU(0) grids); when on, the blocked
+                                    // plan above is not built (levels only)
 };
 
 namespace hec {
@@ -304,8 +305,8 @@ constexpr int kLevelsSyncWords = 8;
 // (hec_set_spin_limit).
 uint32_t spin_limit();
 
-// Whether triangular solves take the wavefront kernel where a schedule has a grid
-// plan (hec_set_trsv_grid; default on).
+// Whether level_schedule gives wavefront plans where they apply (hec_set_trsv_grid;
+// default on).
 bool trsv_grid_enabled();
 
 // Reads and clears the error word of lv after synchronising s; HEC_ERR_TIMEOUT if a
@@ -353,6 +354,9 @@ void trsv_init_levels(hec_levels_s &lv, hipStream_t s);
 
 // Builds tri.grid (the wavefront plan) when the factor's triangle admits one.
 void build_grid(const hec_ilu_s &M, bool upper, hec_grid &g, hipStream_t s);
+
+// Only the level schedule of a triangle (Eq. (11), Alg. 3): nlev, hlevel_ptr, hperm.
+void level_only(const hec_ilu_s &M, bool upper, hec_tri &tri);
 
 // Builds the level schedule and blocked solve plan of one triangle of M (the
 // upper plan must be built first: the lower plan records positions in it).

@@ -377,12 +377,17 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         lv->n = M->n_sys;
         lv->nf = M->n;
         lv->ras = !M->hext_row.empty();
-        build_tri(*M, true, lv->upper, nullptr, s);
-        build_tri(*M, false, lv->lower, &lv->upper, s);
-        if (!lv->ras) {  // the wavefront plans: both triangles or neither
+        if (!lv->ras && trsv_grid_enabled()) {  // the wavefront plans: both triangles or neither
             build_grid(*M, true, lv->upper.grid, s);
             if (lv->upper.grid.on) build_grid(*M, false, lv->lower.grid, s);
             if (!lv->lower.grid.on) lv->upper.grid = hec_grid();
+        }
+        if (lv->lower.grid.on) {  // the level schedules only (levels_export, the batched copies)
+            level_only(*M, true, lv->upper);
+            level_only(*M, false, lv->lower);
+        } else {
+            build_tri(*M, true, lv->upper, nullptr, s);
+            build_tri(*M, false, lv->lower, &lv->upper, s);
         }
         if (!lv->ras && M->n <= HEC_BATCH_MAX_N) {  // small enough for the batched solver
             build_flat(*M, false, lv->lower, s);

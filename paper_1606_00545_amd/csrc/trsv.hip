@@ -1248,7 +1248,7 @@ void trsv_launch(const hec_levels_s &lv, uint32_t which, const T *b, T *x, hipSt
         qU = lv.qU32.get();
         yp = lv.yp32.get();
     }
-    if (lv.lower.grid.on && lv.upper.grid.on && trsv_grid_enabled()) {
+    if (lv.lower.grid.on && lv.upper.grid.on) {
         trsv_launch_grid<T>(lv, which, b, x, s, skip);
         return;
     }
@@ -1297,6 +1297,11 @@ void trsv_init_levels(hec_levels_s &lv, hipStream_t s) {
             HEC_CHECK_LAUNCH();
         }
     }
+}
+
+void level_only(const hec_ilu_s &M, bool upper, hec_tri &tri) {
+    tri.nlev = plan::compute_levels(M.n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), upper, tri.hlevel_ptr,
+                                    tri.hperm);
 }
 
 void build_grid(const hec_ilu_s &M, bool upper, hec_grid &g, hipStream_t s) {

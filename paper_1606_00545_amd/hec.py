@@ -209,8 +209,8 @@ def set_spin_limit(polls: int = -1):
 
 
 def set_trsv_grid(enable: bool = True):
-    """hec_set_trsv_grid: triangular solves of schedules with wavefront plans use the
-    wavefront kernel (True, the default) or the level-blocked one (False)."""
+    """hec_set_trsv_grid: schedules built after the call get wavefront plans where they
+    apply (True, the default) or level-blocked plans only (False)."""
     _check(load().hec_set_trsv_grid(1 if enable else 0), "hec_set_trsv_grid")
 
 

@@ -6,18 +6,23 @@ stream, with its HEC matrix, ILU factor, level schedule and Krylov workspace
 resident in HBM for the duration of its solve. A request is admitted in arrival
 order as soon as a slot is free and its estimated device footprint fits in the
 remaining memory budget (so the head of the queue can never be starved by later,
-smaller requests). Admitted requests run concurrently: their kernels overlap on
+smaller requests). Once its handles are built, the reservation becomes what the
+library reports they hold (hec_footprint) plus the Krylov workspace the solve
+adds, and the difference goes back to the budget; after the solve the library's
+figure (workspace included) is recorded. Admitted requests run concurrently: their kernels overlap on
 the device, and the host side of one request's setup (symbolic ILU, level
 schedules) runs while others compute, since every library call releases the
 Python interpreter lock.
 
 Small systems (n <= batch_max_n, when batching is on) take another route: a
 slot prepares the system (HEC matrix, factor, level schedules, right-hand side)
-and hands it to the batcher, which solves every prepared small system waiting at
-that moment (up to the batch capacity, after waiting at most batch_wait for more
-to arrive) in one persistent launch replayed from a hipGraph
-(gmres_solve_batched), one workgroup per system. The slot is free again as soon
-as it has handed the system over.
+and hands it to the batcher, which solves the prepared small systems in one
+persistent launch replayed from a hipGraph (gmres_solve_batched), one workgroup
+per system. Once a system is ready the batcher holds the launch for more, for as
+long as about batch_target systems take to arrive at the recent hand-over rate
+(an exponential average), at most batch_wait: at a high arrival rate launches fill
+up, at a low one a system does not wait for company that is not coming. The slot
+is free again as soon as it has handed the system over.
 
 Each result is independent of what else is in flight: every kernel's reduction
 order depends only on the request's own size, and a batched system is solved by
@@ -65,25 +70,38 @@ class Result:
         return self.done - self.arrival
 
 
-def footprint_bytes(n: int, nnz: int, restart: int = 30, precision: int = 0, nnz_lu: int | None = None) -> int:
-    """Upper estimate of the device memory one request holds while it is solved.
+def workspace_bytes(n: int, restart: int = 30, precision: int = 0) -> int:
+    """Upper estimate of the Krylov workspace a GMRES solve adds to the matrix handle:
+    V (m+1 vectors, padded) and Z (m vectors), work vectors, FP32 copies in mixed precision."""
+    f64 = 8
+    ws_b = (2 * restart + 1) * (n + 2048) * f64 + 16 * n * f64
+    if precision:
+        ws_b += (2 * restart + 1) * (n + 2048) * 4 + 4 * n * 4
+    return ws_b + (1 << 20)
 
-    HEC matrix (ELL slab + remainder, up to 1.3x padding), ILU factor and its two
-    level-ordered triangle copies, Krylov workspace V (m+1 vectors) and Z (m
-    vectors), work vectors; FP32 copies in mixed precision.
+
+def footprint_bytes(n: int, nnz: int, restart: int = 30, precision: int = 0, nnz_lu: int | None = None) -> int:
+    """Upper estimate of the device memory one request holds while it is solved, for
+    admission before its handles exist (the library reports the real figure once they
+    do; the serving tests check that it never exceeds this).
+
+    HEC matrix (ELL slab + remainder, up to 1.3x padding), ILU factor, its level-ordered
+    triangle plans (up to 1.3x padding) and, on a 3D grid, the wavefront plans (packed
+    coefficients with the tiles' skew, face buffers), the Krylov workspace; FP32 copies
+    in mixed precision.
     """
     nnz_lu = nnz if nnz_lu is None else nnz_lu
     f64 = 8
     hec_b = int(1.3 * nnz) * (4 + f64) + 8 * n
     ilu_b = nnz_lu * (4 + f64) + 16 * n
     lev_b = 2 * (int(1.3 * nnz_lu) * (4 + f64) + 32 * n)
-    ws_b = (2 * restart + 1) * n * f64 + 16 * n * f64
+    grid_b = 2 * 4 * int(1.5 * n) * f64 + 4 * int(1.5 * n) * f64
     if precision:
         hec_b += int(1.3 * nnz) * 4
         ilu_b += nnz_lu * 4
         lev_b += int(1.3 * nnz_lu) * 4
-        ws_b += (2 * restart + 1) * n * 4 + 4 * n * 4
-    return hec_b + ilu_b + lev_b + ws_b + (1 << 20)
+        grid_b += 2 * 4 * int(1.5 * n) * 4 + 4 * int(1.5 * n) * 4
+    return hec_b + ilu_b + lev_b + grid_b + workspace_bytes(n, restart, precision) + (1 << 20)
 
 
 @dataclass
@@ -93,7 +111,8 @@ class Server:
     restart: int = 30
     batch_max_n: int = 0          # 0: no batching; else systems with n <= batch_max_n are batched
     batch_capacity: int = 256     # systems per batched launch
-    batch_wait: float = 0.002     # seconds the batcher waits for more systems once one is ready
+    batch_wait: float = 0.002     # longest hold of a batched launch for more systems (seconds)
+    batch_target: int = 16        # systems a hold waits for at the recent hand-over rate
     results: list = field(default_factory=list)
 
     def __post_init__(self):
@@ -105,7 +124,12 @@ class Server:
         self._batchq: deque = deque()   # prepared small systems, in hand-over order
         self._workers_done = False
         self._streams: list = []        # kept alive until every handle made on them is destroyed
-        self.peak_mem = 0
+        self.peak_mem = 0               # largest reservation in flight (estimates, then library figures)
+        self.peak_reported = 0          # largest sum of library-reported footprints in flight
+        self._reported = 0
+        self.reported: dict = {}        # rid -> library-reported device bytes after the solve
+        self._small_rate = 0.0          # exponential average of small-system hand-overs per second
+        self._last_small = None
         self.peak_inflight = 0
         self.batches: list = []         # sizes of the batched launches
         self.errors: list = []
@@ -130,11 +154,31 @@ class Server:
                     return None
                 self._cv.wait()
 
-    def _release(self, fp):
+    def _release(self, fp, reported=0):
         with self._cv:
             self._free_mem += fp
+            self._reported -= reported
             self._inflight -= 1
             self._cv.notify_all()
+
+    def _settle(self, fp, handles_bytes, n, precision):
+        """After setup: the reservation becomes the library's figure for the handles plus the
+        workspace estimate (never more than admitted: the estimate is an upper bound).
+        Returns the new reservation."""
+        new = min(fp, handles_bytes + workspace_bytes(n, self.restart, precision))
+        with self._cv:
+            self._free_mem += fp - new
+            self._reported += handles_bytes
+            self.peak_reported = max(self.peak_reported, self._reported)
+            self._cv.notify_all()
+        return new
+
+    def _record(self, rid, fp_bytes, handles_bytes):
+        """After the solve: the library's figure with the workspace."""
+        with self._cv:
+            self.reported[rid] = fp_bytes
+            self._reported += fp_bytes - handles_bytes
+            self.peak_reported = max(self.peak_reported, self._reported)
 
     def submit(self, req: Request):
         fp = footprint_bytes(req.A.n, req.A.nnz, self.restart, req.precision)
@@ -162,18 +206,24 @@ class Server:
             if self.batch_max_n and req.A.n <= self.batch_max_n:
                 self._prepare_small(req, fp, t_adm, slot, stream)
                 continue
+            hb = 0
             try:
                 with torch.cuda.stream(stream):
                     keep = req.precision == 1
                     M = hec.hec_from_csr(req.A, keep_f32=keep, stream=stream)
                     F = hec.ilu_factor(req.A, k=0, keep_f32=keep, stream=stream)
                     lv = hec.level_schedule(F, stream=stream)
+                    hb = hec.footprint(M, F, lv)
+                    fp = self._settle(fp, hb, req.A.n, req.precision)
                     bd = torch.from_numpy(req.b).to("cuda", non_blocking=False)
                     x = torch.empty_like(bd)
                     info = hec.gmres_solve(M, F, lv, bd, x, restart=self.restart, rtol=req.rtol,
                                            precision=req.precision, stream=stream, check=False)
                     xh = x.cpu().numpy()
                     stream.synchronize()
+                    fb = hec.footprint(M, F, lv)
+                    self._record(req.rid, fb, hb)
+                    hb = fb
                     del bd, x
                     lv.close(); F.close(); M.close()
                     stream.synchronize()
@@ -185,7 +235,7 @@ class Server:
                 with self._cv:
                     self.errors.append((req.rid, repr(e)))
             finally:
-                self._release(fp)
+                self._release(fp, hb)
 
     # ------------------------------------------------------------ small systems
     def _prepare_small(self, req, fp, t_adm, slot, stream):
@@ -196,6 +246,7 @@ class Server:
                 M = hec.hec_from_csr(req.A, keep_f32=keep, stream=stream)
                 F = hec.ilu_factor(req.A, k=0, keep_f32=keep, stream=stream)
                 lv = hec.level_schedule(F, stream=stream)
+                hb = hec.footprint(M, F, lv)  # the batch context holds the Krylov workspace
                 bd = torch.from_numpy(req.b).to("cuda", non_blocking=False)
                 x = torch.empty_like(bd)
                 stream.synchronize()
@@ -205,7 +256,17 @@ class Server:
             self._release(fp)
             return
         with self._cv:
-            self._batchq.append((req, fp, t_adm, slot, M, F, lv, bd, x))
+            now = time.perf_counter()
+            if self._last_small is not None:  # recent hand-over rate (exponential average over ~8)
+                gap = max(now - self._last_small, 1e-6)
+                self._small_rate = 0.875 * self._small_rate + 0.125 / gap
+            self._last_small = now
+            new = min(fp, hb)
+            self._free_mem += fp - new
+            self._reported += hb
+            self.reported[req.rid] = hb
+            self.peak_reported = max(self.peak_reported, self._reported)
+            self._batchq.append((req, new, t_adm, slot, M, F, lv, bd, x, hb))
             self._cv.notify_all()
 
     def _take_batch(self):
@@ -215,8 +276,12 @@ class Server:
                 if self._workers_done:
                     return None
                 self._cv.wait()
-            deadline = time.perf_counter() + self.batch_wait
-            while len(self._batchq) < self.batch_capacity and not self._workers_done:
+            # hold for about batch_target systems at the recent hand-over rate, at most batch_wait
+            hold = self.batch_wait
+            if self._small_rate > 0:
+                hold = min(hold, self.batch_target / self._small_rate)
+            deadline = time.perf_counter() + hold
+            while len(self._batchq) < min(self.batch_capacity, self.batch_target) and not self._workers_done:
                 left = deadline - time.perf_counter()
                 if left <= 0:
                     break
@@ -259,7 +324,7 @@ class Server:
                 for it in group:
                     for h in (it[6], it[5], it[4]):
                         h.close()
-                    self._release(it[1])
+                    self._release(it[1], it[9])
         for B in contexts.values():
             B.close()
 

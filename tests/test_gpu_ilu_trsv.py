@@ -23,6 +23,9 @@ def _cases():
     yield "random_k1", random_sparse(500, 0.008, np.random.default_rng(5)), 1
     # several parts in the blocked solve, ragged last part
     yield "tpfa3d_41x37x23_k0", synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0
+    # the same factor with level-blocked plans (the wavefront plans switched off when it is scheduled)
+    yield "tpfa3d_41x37x23_k0_blocked", synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 0
+    yield "tpfa3d_k0_blocked", synth.lognormal_tpfa((17, 13, 11), 2.0, np.random.default_rng(2)), 0
     yield "tpfa3d_41x37x23_k1", synth.lognormal_tpfa((41, 37, 23), 2.0, np.random.default_rng(6)), 1
     yield "tpfa2d_301x97_k2", synth.lognormal_tpfa((301, 97), 1.5, np.random.default_rng(7)), 2
     yield "random_20000_k1", random_sparse(20000, 0.0004, np.random.default_rng(8)), 1
@@ -37,7 +40,12 @@ def built():
     for name, (A, k) in CASES.items():
         F = O.iluk(A.n, A.Ap, A.Aj, A.Ax, k)
         M = hec.ilu_factor(A, k=k, keep_f32=True)
-        lv = hec.level_schedule(M)
+        hec.set_trsv_grid(not name.endswith("_blocked"))
+        try:
+            lv = hec.level_schedule(M)
+        finally:
+            hec.set_trsv_grid(True)
+        assert hec.levels_grid(lv) == (name in ("tpfa3d_k0", "tpfa3d_41x37x23_k0"))
         out[name] = (A, k, F, M, lv)
     return out
 
@@ -92,7 +100,7 @@ def test_trsv_fp64_matches_oracle(built, name):
         assert (np.abs(y_o - U @ z) <= gam * (np.abs(U) @ np.abs(z)) + 1e-300).all()
 
 
-@pytest.mark.parametrize("name", ["tpfa3d_k0", "tpfa3d_k1", "random_k1"])
+@pytest.mark.parametrize("name", ["tpfa3d_k0", "tpfa3d_k0_blocked", "tpfa3d_k1", "random_k1"])
 def test_trsv_fp32_copy(built, name):
     """FP32 factor + FP32 vectors: same schedule; error against FP64 stated by a
     forward-error bound cond-free check on the residual of the FP32 result."""

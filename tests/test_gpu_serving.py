@@ -50,15 +50,21 @@ def test_results_identical_alone_and_in_the_mix():
         assert _rel_res(r.A, got.x, r.b) <= 1e-8
 
 
-def test_admission_respects_the_memory_budget():
-    reqs = _requests()
-    fps = [serve.footprint_bytes(r.A.n, r.A.nnz) for r in reqs]
+@pytest.mark.parametrize("precision", [0, 1])
+def test_admission_respects_the_memory_budget(precision):
+    """Admission reserves the estimate; once the handles exist the reservation becomes the
+    library-reported footprint (plus the workspace estimate). The estimate bounds what the
+    library reports after the solve (workspace included), and the reported bytes in flight
+    never exceed the budget."""
+    reqs = _requests(precisions=(precision,))
+    fps = [serve.footprint_bytes(r.A.n, r.A.nnz, precision=precision) for r in reqs]
     budget = max(fps) + min(fps)  # at most the largest and the smallest together
     srv = serve.Server(slots=6, mem_budget=budget)
     res = srv.run(reqs)
     assert not srv.errors and len(res) == len(reqs)
-    assert srv.peak_mem <= budget
-    for r in reqs:
+    assert srv.peak_mem <= budget and srv.peak_reported <= budget
+    for r, fp in zip(reqs, fps):
+        assert 0 < srv.reported[r.rid] <= fp, (r.rid, srv.reported[r.rid], fp)
         got = next(x for x in res if x.rid == r.rid)
         assert _rel_res(r.A, got.x, r.b) <= 1e-8
 
@@ -88,7 +94,7 @@ def test_batched_route_identical_alone_and_in_the_mix():
         assert len(res) == 1 and not srv.errors
         assert len(srv.batches) == (1 if r.A.n <= 4096 else 0)
         alone[r.rid] = res[0].x
-    srv = serve.Server(slots=6, batch_max_n=4096, batch_capacity=8, batch_wait=0.05)
+    srv = serve.Server(slots=6, batch_max_n=4096, batch_capacity=8, batch_wait=0.5, batch_target=4)
     got = {res.rid: res for res in srv.run(reqs)}
     assert not srv.errors and len(got) == len(reqs)
     assert max(srv.batches) > 1  # several small systems shared a launch

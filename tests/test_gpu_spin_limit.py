@@ -33,13 +33,13 @@ def test_zero_spin_limit_gives_up_and_recovers(case):
         A, k = synth.workload_diffusion3d(40, sigma=2.0, seed=5)[0], 0
     f32 = case.endswith("f32")
     F = hec.ilu_factor(A, k=k, keep_f32=f32)
-    lv = hec.level_schedule(F)
-    assert hec.levels_grid(lv) == (k == 0)
-    hec.set_trsv_grid(not case.startswith("blocked"))
+    hec.set_trsv_grid(not case.startswith("blocked"))  # read when the schedule is built
     try:
-        _give_up_and_recover(A, k, F, lv, f32)
+        lv = hec.level_schedule(F)
     finally:
         hec.set_trsv_grid(True)
+    assert hec.levels_grid(lv) == case.startswith("grid")
+    _give_up_and_recover(A, k, F, lv, f32)
 
 
 def _give_up_and_recover(A, k, F, lv, f32):

@@ -67,14 +67,24 @@ def test_wavefront_fp64_matches_oracle(built, shape):
 
 @pytest.mark.parametrize("shape", [(24, 24, 24), (41, 37, 23)])
 def test_wavefront_agrees_with_blocked_kernel(built, shape):
+    """The switch is read when a schedule is built: a second schedule of the same factor
+    built with it off has level-blocked plans and gives the same results within rounding."""
     A, F, M, lv = built[shape]
+    hec.set_trsv_grid(False)
+    try:
+        lvb = hec.level_schedule(M)
+    finally:
+        hec.set_trsv_grid(True)
+    assert hec.levels_grid(lv) and not hec.levels_grid(lvb)
+    gb, bb = hec.levels_export(lv), hec.levels_export(lvb)  # the same level schedules either way
+    for k in ("lower_ptr", "lower_perm", "upper_ptr", "upper_perm"):
+        assert np.array_equal(gb[k], bb[k])
     bd = dev(np.random.default_rng(32).uniform(-1, 1, A.n))
     xg, xb = empty(A.n), empty(A.n)
     hec.trsv_levels(M, lv, bd, xg, hec.LU)
-    hec.set_trsv_grid(False)
-    hec.trsv_levels(M, lv, bd, xb, hec.LU)
-    hec.set_trsv_grid(True)
+    hec.trsv_levels(M, lvb, bd, xb, hec.LU)
     hec.levels_check(lv)
+    hec.levels_check(lvb)
     xg, xb = host(xg), host(xb)
     assert np.linalg.norm(xg - xb) <= 1e-13 * np.linalg.norm(xb)
 
