@@ -703,13 +703,15 @@ def serving(args):
         st = serve.latency_stats(res)
         ok = sum(1 for r in res if r.info["status"] == 0 and r.info["rel_res_true"] <= 1e-8)
         small = [r.latency * 1e3 for r in res if r.n <= args.batch_max_n]
+        bad = [(r.rid, r.n, int(r.info["status"]), float(r.info["rel_res_true"])) for r in res
+               if not (r.info["status"] == 0 and r.info["rel_res_true"] <= 1e-8)]
         return {"completed": len(res), "converged": ok, "errors": len(srv.errors),
                 "solves_per_s": round(len(res) / span, 3) if span else None,
                 "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
                 "small_p50_ms": round(float(np.percentile(small, 50)), 2) if small else None,
                 "peak_inflight": srv.peak_inflight, "batched_launches": len(srv.batches),
                 "mean_batch": round(float(np.mean(srv.batches)), 1) if srv.batches else 0,
-                "peak_reported_GB": round(srv.peak_reported / 1e9, 2)}
+                "peak_reported_GB": round(srv.peak_reported / 1e9, 2), "not_converged": bad[:5]}
 
     out = {"requests": len(systems), "slots": args.slots, "batch_max_n": args.batch_max_n,
            "batch_wait_s": args.batch_wait}

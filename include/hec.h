@@ -273,7 +273,10 @@ hec_status trsv_levels(hec_ilu M, hec_levels lv, uint32_t which, hec_dtype prec,
  * which equals the plain form in exact arithmetic), Givens rotations,
  * convergence decided by the FP64 true residual. precision = 1: iterative refinement in FP64 around inner
  * GMRES solves that use the FP32 copies of A and of the factor (both handles
- * built with HEC_KEEP_F32) and an FP32 Krylov basis. b, x: device FP64.
+ * built with HEC_KEEP_F32) and an FP32 Krylov basis. A refinement that stalls
+ * (eight steps in a row without halving the smallest true residual so far)
+ * gives up and the solve starts again in FP64 from x = 0; the iterations of
+ * both phases are counted. b, x: device FP64.
  * ||b|| == 0 gives x = 0, OK, 0 iterations. On NOT_CONVERGED x holds the last
  * iterate. `info` may be NULL. */
 hec_status gmres_solve(hec_matrix A, hec_ilu M, hec_levels lv, const double *b, double *x,

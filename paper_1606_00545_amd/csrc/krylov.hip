@@ -1234,9 +1234,17 @@ static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const dou
     const double target = mixed && o->ir_rtol > 0.0 ? std::min(o->ir_rtol, o->rtol) : o->rtol;
     double res = true_residual(A, ws, b, x, s);
     int it = 0, cycles = 0;
+    // mixed precision: a refinement that stalls (eight steps in a row without halving the
+    // smallest true residual so far: the FP32 inner solves no longer resolve the
+    // correction) gives up, and the solve starts again in FP64 from x = 0 (restarted FP64
+    // cycles from the stalled iterate were measured far slower: its residual is left in
+    // the components GMRES(m) converges worst, 3700 further steps against 627 from zero)
+    bool fp64_tail = false;
+    int stalls = 0;
+    double res_mark = res;
     while (res / bnorm > target && it < o->maxit) {
         int mcyc = std::min(o->restart, o->maxit - it);
-        if (!mixed) {
+        if (!mixed || fp64_tail) {
             set_scalar_async(ws, SD_TOL, target * bnorm, s);
             gmres_cycle<double>(A, lv, ws, mcyc, o->restart, x, s, false);
         } else {
@@ -1265,6 +1273,18 @@ static void gmres_run(hec_matrix_s &A, hec_levels_s &lv, KrylovWS &ws, const dou
         res = ws.hsd[SD_TRUE];
         it += jd;
         cycles++;
+        if (mixed && !fp64_tail) {
+            if (res <= 0.5 * res_mark) {
+                res_mark = res;
+                stalls = 0;
+            } else if (++stalls >= 8) {
+                fp64_tail = true;
+                k_fill<double><<<ceil_div(n, 256), 256, 0, s>>>(n, x, 0.0);
+                HEC_CHECK_LAUNCH();
+                res = true_residual(A, ws, b, x, s);  // r = b for the FP64 cycles that follow
+                continue;
+            }
+        }
         if (jd == 0) break;  // no progress possible (breakdown at the start of a cycle)
     }
     inf.iterations = it;

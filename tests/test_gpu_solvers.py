@@ -254,3 +254,22 @@ def test_bicgstab_breakdown_status_after_three_restarts():
     with pytest.raises(hec.HecError) as e:
         hec.bicgstab_solve(Mh, F, lv, dev(b), empty(n), rtol=1e-10)
     assert e.value.code == hec.BREAKDOWN
+
+
+def test_mixed_refinement_that_stalls_finishes_in_fp64():
+    """A 2D lognormal system (428 x 428, sigma 2.56: request 1132 of the serving trace) on
+    which the FP32 inner solves stop resolving the correction just above 1e-8: the
+    refinement finishes with FP64 cycles and reaches the tolerance, like the FP64 solve."""
+    spec = synth.serving_requests(2000)[1132]
+    A, xt = synth.request_system(spec)
+    assert A.n == 183184
+    b = O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, xt)
+    M = hec.hec_from_csr(A, keep_f32=True)
+    F = hec.ilu_factor(A, k=0, keep_f32=True)
+    lv = hec.level_schedule(F)
+    for prec in (1, 0):
+        x = empty(A.n)
+        info = hec.gmres_solve(M, F, lv, dev(b), x, rtol=1e-8, precision=prec)
+        assert info["status"] == hec.OK and info["rel_res_true"] <= 1e-8, (prec, info)
+        r = b - O.csr_spmv(A.n, A.Ap, A.Aj, A.Ax, host(x))
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b)
