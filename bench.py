@@ -22,6 +22,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -56,6 +57,11 @@ def parse():
     p.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     p.add_argument("--batch-max-n", type=int, default=8192, help="serving: largest batched system")
     p.add_argument("--batch-wait", type=float, default=0.05, help="serving: longest hold of a batched launch (s)")
+    p.add_argument("--loops", choices=["both", "closed", "open"], default="both",
+                   help="serving: closed-loop and/or open-loop runs")
+    p.add_argument("--open-rate", choices=["sequential", "closed"], default="sequential",
+                   help="serving: open-loop arrivals at 0.7x the FP64 sequential-service throughput (measured "
+                        "with one slot on the first 200 requests) or at 0.7x the closed-loop FP64 throughput")
     return p.parse_args()
 
 
@@ -679,8 +685,9 @@ def serving(args):
     requests: FP64 with every request on its own stream ("fp64"), FP64 with small
     systems batched into persistent launches ("fp64_batched"), and mixed precision
     with batching ("mixed_batched"). Closed loop (all requests queued at t=0) gives
-    throughput; open loop (Poisson arrivals at 0.7x the closed-loop FP64 throughput of
-    the same server) gives p50/p99 latency at a stated load."""
+    throughput; open loop (Poisson arrivals at 0.7x the FP64 sequential-service
+    throughput, measured with one slot on the first 200 requests; or 0.7x the
+    closed-loop FP64 throughput) gives p50/p99 latency at a stated load."""
     from paper_1606_00545_amd import serve, synth
 
     t0 = time.time()
@@ -698,7 +705,18 @@ def serving(args):
                 for (rid, A, b), t in zip(systems, arrivals)]
         srv = serve.Server(slots=slots, batch_max_n=bmax, batch_wait=args.batch_wait)
         t = time.perf_counter()
-        res = srv.run(reqs, t0=t)
+        stop = threading.Event()
+
+        def progress():  # a line every 30 s while a run lasts (long open-loop runs)
+            while not stop.wait(30.0):
+                log(f"[bench] serving: {len(srv.results)} of {len(reqs)} done after {time.perf_counter() - t:.0f} s")
+        mon = threading.Thread(target=progress, daemon=True)
+        mon.start()
+        try:
+            res = srv.run(reqs, t0=t)
+        finally:
+            stop.set()
+            mon.join()
         span = max(r.done for r in res) if res else 0.0
         st = serve.latency_stats(res)
         ok = sum(1 for r in res if r.info["status"] == 0 and r.info["rel_res_true"] <= 1e-8)
@@ -716,17 +734,31 @@ def serving(args):
     out = {"requests": len(systems), "slots": args.slots, "batch_max_n": args.batch_max_n,
            "batch_wait_s": args.batch_wait}
     closed = {}
-    for name, prec, bmax in configs:
+    for name, prec, bmax in configs if args.loops != "open" else ():
         closed[name] = run(prec, bmax, np.zeros(len(systems)))
         log(f"[bench] serving closed-loop {name}: {closed[name]}")
-    # open loop at 0.7x the closed-loop FP64 throughput (per-stream route)
-    rate = 0.7 * closed["fp64"]["solves_per_s"]
+    out["closed_loop"] = closed
+    if args.loops == "closed":
+        return out
+    if args.open_rate == "sequential" or not closed:  # FP64 one request at a time, on a prefix of the trace
+        head = systems[:200]
+        reqs = [serve.Request(rid, A, b, precision=0, rtol=1e-8, arrival=0.0) for rid, A, b in head]
+        srv = serve.Server(slots=1)
+        t = time.perf_counter()
+        res = srv.run(reqs, t0=t)
+        seq_rate = len(res) / max(r.done for r in res)
+        out["sequential_fp64_solves_per_s"] = round(seq_rate, 3)
+        log(f"[bench] serving sequential fp64 on {len(head)} requests: {seq_rate:.2f}/s")
+        rate = 0.7 * seq_rate
+    else:  # 0.7x the closed-loop FP64 throughput (per-stream route)
+        rate = 0.7 * closed["fp64"]["solves_per_s"]
+    out["open_rate_basis"] = args.open_rate
     arrivals = synth.poisson_arrivals(len(systems), rate)
     opened = {}
     for name, prec, bmax in configs:
         opened[name] = run(prec, bmax, arrivals)
         log(f"[bench] serving open-loop {name} at {rate:.2f}/s: {opened[name]}")
-    out.update({"closed_loop": closed, "open_loop_rate_per_s": round(rate, 3), "open_loop": opened})
+    out.update({"open_loop_rate_per_s": round(rate, 3), "open_loop": opened})
     return out
 
 

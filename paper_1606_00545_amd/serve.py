@@ -20,7 +20,8 @@ and hands it to the batcher, which solves the prepared small systems in one
 persistent launch replayed from a hipGraph (gmres_solve_batched), one workgroup
 per system. Once a system is ready the batcher holds the launch for more, for as
 long as about batch_target systems take to arrive at the recent hand-over rate
-(an exponential average), at most batch_wait: at a high arrival rate launches fill
+(an exponential average), at most batch_wait, and not at all when fewer than one
+more system is expected within batch_wait: at a high arrival rate launches fill
 up, at a low one a system does not wait for company that is not coming. The slot
 is free again as soon as it has handed the system over.
 
@@ -276,10 +277,13 @@ class Server:
                 if self._workers_done:
                     return None
                 self._cv.wait()
-            # hold for about batch_target systems at the recent hand-over rate, at most batch_wait
+            # hold for about batch_target systems at the recent hand-over rate, at most
+            # batch_wait; not at all when fewer than one more is expected within batch_wait
             hold = self.batch_wait
             if self._small_rate > 0:
                 hold = min(hold, self.batch_target / self._small_rate)
+                if self._small_rate * self.batch_wait < 1.0:
+                    hold = 0.0
             deadline = time.perf_counter() + hold
             while len(self._batchq) < min(self.batch_capacity, self.batch_target) and not self._workers_done:
                 left = deadline - time.perf_counter()
