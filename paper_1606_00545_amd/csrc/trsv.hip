@@ -702,7 +702,10 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
 //    below slots of row 0), and a lane reads its cell in one instruction. A single wavefront issues
 //    at most one instruction every 4 cycles, so the step is kept to a few dozen
 //    instructions: the dependency chain is one LDS round trip and three fused
-//    multiply-adds.
+//    multiply-adds. Where a whole tile's 64 rows are all valid for 8 steps (the bulk
+//    of a long column) the steps run as an unrolled block of about 20 instructions
+//    each: no masks, ring offsets fixed at compile time, one release per block
+//    (0.13 us a step against 0.19 us for the general step).
 //  * Wavefronts 1..kGridPollers poll the tile's incoming face values (8 on the
 //    a-face, 8 on the b-face per step) for a window of the next 4 * HEC_GRID_POLL_R
 //    steps, one lane per value and step, with device-coherent loads until they are
@@ -736,7 +739,7 @@ constexpr int kGridLoaders = kGridWaves - 1 - kGridPollers;
 constexpr int kGridBatch = 3;   // consecutive steps a loader has in flight
 constexpr int kGridRing = 32;   // steps in LDS (slots and grids): how far loads run ahead
 constexpr int kGridG = plan::kGT + 1;  // side of a step's grid of cells: the tile and its low faces
-static_assert((kGridRing & (kGridRing - 1)) == 0 && kGridBatch <= kGridRing, "ring");
+static_assert((kGridRing & (kGridRing - 1)) == 0 && kGridRing % 8 == 0 && kGridBatch <= kGridRing, "ring");
 
 struct GridArgs {
     int32_t NA, NB, NC, PA, PB, S, nclaims;
@@ -953,11 +956,79 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                 }
                 if (more && !early && ensure(s + 1)) load_step(s + 1, nxt);
             };
+            // Eight steps at which every lane's row is valid (a tile with all 64 columns in
+            // the grid, 2 (GT - 1) <= s0 and s0 + 8 <= NC), with the coefficients of all of
+            // them and the next loaded: no masks, no load bookkeeping, ring offsets fixed at
+            // compile time (the ring holds whole blocks of 8), one release of the slots at
+            // the end. Only the face values are checked step by step, as they arrive.
+            // On entry H0 holds step s0's coefficients; on exit step s0 + 8's.
+            auto block8 = [&](int s0, Step &H0, Step &H1) {
+                T *const gb = xg + (s0 & RM) * GA + gl;
+                T *const gx = xg + ((s0 + 8) & RM) * GA + gl;
+                const T *const sb = slots + (s0 & RM) * SLOT + lane;
+                const T *const sx = slots + ((s0 + 8) & RM) * SLOT + lane;
+                T *const fb = fp + (int64_t)s0 * 8;
+                T *xo = io.x + roff;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int s = s0 + u;
+                    if (s >= fready) {
+                        fready = wait_faces(s);
+                        if (bail) break;
+                    }
+                    Step &cur = (u & 1) ? H1 : H0;
+                    Step &nxt = (u & 1) ? H0 : H1;
+                    const T *g = gb + u * GA;
+                    const T left = g[0], below = g[1];
+                    const T *sl = u < 7 ? sb + (u + 1) * SLOT : sx;
+#pragma unroll
+                    for (int k = 0; k < NCOEF; ++k) nxt.cv[k] = sl[k * 64];
+                    nxt.bv = sl[NCOEF * 64];
+                    T acc;
+                    if constexpr (!UPPER) {
+                        acc = cur.bv - cur.cv[0] * xp;
+                        acc -= cur.cv[1] * below;
+                        acc -= cur.cv[2] * left;
+                    } else {
+                        acc = cur.bv - cur.cv[2] * left;
+                        acc -= cur.cv[1] * below;
+                        acc -= cur.cv[0] * xp;
+                        acc *= cur.cv[3];
+                    }
+                    T *gn = u < 7 ? gb + (u + 1) * GA : gx;
+                    gn[2] = acc;
+                    gn[2 * GG + 1] = acc;
+                    *xo = acc;
+                    xo += dsc;
+                    // an arithmetic result is never the signalling-NaN sentinel (IEEE mode
+                    // quiets NaN operands), so no check is needed before publishing it
+                    if (fst) {
+                        U bits;
+                        __builtin_memcpy(&bits, &acc, sizeof(T));
+                        __hip_atomic_store((U *)(fb + u * 8), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    xp = acc;
+                }
+                roff += 8 * dsc;
+                if (!bail) {
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (lane == 0) __hip_atomic_store(s_done, s0 + 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
+            const bool full = __ballot(act) == ~0ull;
             Step h0, h1;
             if (ensure(0)) load_step(0, h0);
-            for (int s = 0; s < G.S && !bail; s += 2) {
-                step(s, h0, h1, false);
-                if (s + 1 < G.S) step(s + 1, h1, h0, true);
+            for (int s0 = 0; s0 < G.S && !bail; s0 += 8) {
+                if (full && s0 >= 2 * (GT - 1) && s0 + 8 <= G.NC) {
+                    while (ready <= s0 + 8 && !bail) ready = scan(ready);
+                    if (!bail) block8(s0, h0, h1);
+                } else {
+                    for (int s = s0; s < min(s0 + 8, G.S) && !bail; s += 2) {
+                        if (s >= ready || s >= fready) ensure(s);  // after a block: step s's faces
+                        step(s, h0, h1, false);
+                        if (s + 1 < G.S) step(s + 1, h1, h0, true);
+                    }
+                }
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (wave <= kGridPollers) {

@@ -17,9 +17,10 @@ pytestmark = pytest.mark.gpu
 U64 = 2.0 ** -53
 
 # (shape, seed): columns along z (cubic, ragged 19 x 13), along x (41 longest), along y,
-# one tile with a ragged second one, and the smallest grid with a plan
+# one tile with a ragged second one, the smallest grid with a plan, and long columns (many
+# steps at which every lane of a whole tile has a row, next to ragged tiles)
 SHAPES = [((24, 24, 24), 1), ((19, 13, 30), 2), ((41, 37, 23), 3), ((13, 45, 16), 4), ((9, 8, 10), 5),
-          ((8, 8, 8), 6)]
+          ((8, 8, 8), 6), ((19, 13, 70), 7)]
 
 
 @pytest.fixture(scope="module")
