@@ -263,6 +263,7 @@ struct hec_grid {
     hec::DevBuf<double> coef;  // [claim][step][k][lane]; k = 3 (upper): the reciprocal pivot
     hec::DevBuf<float> coef32;
     int64_t face_elems() const { return (int64_t)PA * PB * 2 * S * 8; }
+    int64_t pad_elems() const { return (int64_t)PA * PB * S * 64; }  // positions (claim, step, lane)
 };
 
 struct hec_tri {
@@ -324,7 +325,8 @@ struct hec_levels_s {
     // Internal vectors over the factor's rows. qL/qU: each triangle's results in its own
     // plan's position order, the copy dependent rows poll (qL is sentinel-filled between
     // solves; qU is filled by every lower launch, or before a lone upper solve). yp:
-    // L^{-1} b in the upper plan's order, the upper solve's right-hand side.
+    // L^{-1} b in the upper plan's order, the upper solve's right-hand side (with the
+    // wavefront plans: by claim, step and lane of the lower plan, padded).
     hec::DevBuf<double> qL64, qU64, yp64;
     hec::DevBuf<float> qL32, qU32, yp32;
     // Face buffers of the wavefront solves (when both triangles have a grid plan): the

@@ -380,6 +380,9 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         if (!lv->ras && trsv_grid_enabled()) {  // the wavefront plans: both triangles or neither
             build_grid(*M, true, lv->upper.grid, s);
             if (lv->upper.grid.on) build_grid(*M, false, lv->lower.grid, s);
+            const hec_grid &gl = lv->lower.grid, &gu = lv->upper.grid;
+            if (gl.on && (gl.PA != gu.PA || gl.PB != gu.PB || gl.S != gu.S))  // (one padded order serves both)
+                lv->lower.grid = hec_grid();
             if (!lv->lower.grid.on) lv->upper.grid = hec_grid();
         }
         if (lv->lower.grid.on) {  // the level schedules only (levels_export, the batched copies)
@@ -397,11 +400,12 @@ hec_status level_schedule(hec_ilu M, void *stream, hec_levels *out) {
         HEC_HIP(hipMemsetAsync(lv->sync.get(), 0, kLevelsSyncWords * sizeof(uint32_t), s));
         lv->qL64.alloc(M->n);
         lv->qU64.alloc(M->n);
-        lv->yp64.alloc(M->n);
+        const int64_t ny = lv->lower.grid.on ? std::max<int64_t>(M->n, lv->lower.grid.pad_elems()) : M->n;
+        lv->yp64.alloc(ny);
         if (M->has_f32) {
             lv->qL32.alloc(M->n);
             lv->qU32.alloc(M->n);
-            lv->yp32.alloc(M->n);
+            lv->yp32.alloc(ny);
         }
         if (lv->lower.grid.on) {
             const int64_t nface = lv->lower.grid.face_elems();

@@ -750,7 +750,11 @@ struct GridArgs {
 
 // b: right-hand side by row; x: results by row; face: the triangle's face buffer
 // ([claim][face][step][8], sentinel-filled); fill: nfill elements set to the
-// sentinel for a later solve (may be NULL).
+// sentinel for a later solve (may be NULL). bpad / xpad: b / x in padded tile-step
+// order instead, the lower plan's position (claim * S + step) * 64 + lane, which the
+// upper plan visits in reverse (its claim c, step s, lane l is the lower plan's
+// position total - 1 - (c S + s) 64 - l): the intermediate of an L-then-U chain, read
+// and written 512 contiguous bytes a step instead of a row-by-row gather.
 template <class T>
 struct GridIO {
     const T *b;
@@ -758,6 +762,7 @@ struct GridIO {
     T *face;
     T *fill;
     int64_t nfill;
+    int32_t bpad, xpad;
 };
 
 // Dynamic LDS of k_trsv_grid: control words, slots [ring][NCOEF + 1][64], grids
@@ -844,6 +849,9 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
         const bool act = col_a(ma) < G.NA && col_b(mb) < G.NB;
         const int64_t base = (int64_t)col_a(ma) * G.sa + (int64_t)col_b(mb) * G.sb;
         auto row_at = [&](int32_t mc) { return base + (int64_t)(UPPER ? G.NC - 1 - mc : mc) * G.sc; };
+        // this lane's padded tile-step position at step 0, and its change per step
+        const int64_t pq = (int64_t)c * G.S * 64 + lane;
+        const int64_t p0 = UPPER ? (int64_t)G.nclaims * G.S * 64 - 1 - pq : pq, pd = UPPER ? -64 : 64;
 
         if (wave == 0) {
             // ---------------- solver
@@ -911,8 +919,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             // the lane's row at step s: c-index s - ma - mb, valid for (unsigned)(s - moff) < ncl
             const int moff = ma + mb;
             const uint32_t ncl = act ? (uint32_t)G.NC : 0u;
-            const int64_t dsc = UPPER ? -G.sc : G.sc;
-            int64_t roff = row_at(-moff);  // advanced one row along c per step
+            const int64_t dsc = io.xpad ? pd : UPPER ? -G.sc : G.sc;
+            int64_t roff = io.xpad ? p0 : row_at(-moff);  // the output of step 0, advanced by dsc a step
             const int gl = (mb * GG + ma) * 2;  // this lane's cell
             // One step: cur holds its inputs; the next step's are read into nxt while it
             // computes. That read is speculative (unconditional, so that the compiler
@@ -1121,7 +1129,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
 #pragma unroll
                     for (int k = 0; k < NCOEF; ++k) cv[u][k] = cp[k * 64];
                     const int32_t mc = s - ma - mb;
-                    bv[u] = in && act && mc >= 0 && mc < G.NC ? io.b[row_at(mc)] : (T)0;
+                    bv[u] = in && act && mc >= 0 && mc < G.NC ? io.b[io.bpad ? p0 + s * pd : row_at(mc)] : (T)0;
                 }
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
@@ -1290,8 +1298,9 @@ void trsv_launch_grid(const hec_levels_s &lv, uint32_t which, const T *b, T *x, 
     if (which == HEC_LU) {
         // fL is sentinel-filled between chains (by level_schedule, then by every upper
         // launch); the lower launch fills fU for the upper one
-        launch_grid<T, false>(lv.lower.grid, sync, err, GridIO<T>{b, yp, fL, fU, nface}, s, skip);
-        launch_grid<T, true>(lv.upper.grid, sync + 2, err, GridIO<T>{yp, x, fU, fL, nface}, s, skip);
+        // the intermediate goes through yp in padded tile-step order
+        launch_grid<T, false>(lv.lower.grid, sync, err, GridIO<T>{b, yp, fL, fU, nface, 0, 1}, s, skip);
+        launch_grid<T, true>(lv.upper.grid, sync + 2, err, GridIO<T>{yp, x, fU, fL, nface, 1, 0}, s, skip);
         return;
     }
     // a lone triangle: fU, free between calls, is filled right before
