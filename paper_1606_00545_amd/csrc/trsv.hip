@@ -702,10 +702,11 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
 //    below slots of row 0), and a lane reads its cell in one instruction. A single wavefront issues
 //    at most one instruction every 4 cycles, so the step is kept to a few dozen
 //    instructions: the dependency chain is one LDS round trip and three fused
-//    multiply-adds. Where a whole tile's 64 rows are all valid for 8 steps (the bulk
-//    of a long column) the steps run as an unrolled block of about 20 instructions
-//    each: no masks, ring offsets fixed at compile time, one release per block
-//    (0.13 us a step against 0.19 us for the general step).
+//    multiply-adds. Steps run as unrolled blocks of 8 with ring offsets fixed at
+//    compile time and one release per block: about 20 instructions a step where a
+//    whole tile's 64 rows are all valid for the 8 steps (the bulk of a long column),
+//    a few more with validity masks elsewhere (0.12 us a step against 0.19 us for
+//    the general step, which only a column's last, partial block takes).
 //  * Wavefronts 1..kGridPollers poll the tile's incoming face values (8 on the
 //    a-face, 8 on the b-face per step) for a window of the next 4 * HEC_GRID_POLL_R
 //    steps, one lane per value and step, with device-coherent loads until they are
@@ -964,13 +965,16 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                 }
                 if (more && !early && ensure(s + 1)) load_step(s + 1, nxt);
             };
-            // Eight steps at which every lane's row is valid (a tile with all 64 columns in
-            // the grid, 2 (GT - 1) <= s0 and s0 + 8 <= NC), with the coefficients of all of
-            // them and the next loaded: no masks, no load bookkeeping, ring offsets fixed at
-            // compile time (the ring holds whole blocks of 8), one release of the slots at
-            // the end. Only the face values are checked step by step, as they arrive.
+            // Eight steps s0 .. s0 + 7 (s0 + 8 < S) with the coefficients of all of them and
+            // the next loaded: no load bookkeeping, ring offsets fixed at compile time (the
+            // ring holds whole blocks of 8), one release of the slots at the end; only the
+            // face values are checked step by step, as they arrive. MASKED: lanes whose row
+            // at a step is not valid publish zeros and store nothing; unmasked blocks are
+            // those at which every lane's row is valid (a tile with all 64 columns in the
+            // grid, 2 (GT - 1) <= s0 and s0 + 8 <= NC: the bulk of a long column).
             // On entry H0 holds step s0's coefficients; on exit step s0 + 8's.
-            auto block8 = [&](int s0, Step &H0, Step &H1) {
+            auto block8 = [&](auto masked, int s0, Step &H0, Step &H1) {
+                constexpr bool MASKED = decltype(masked)::value;
                 T *const gb = xg + (s0 & RM) * GA + gl;
                 T *const gx = xg + ((s0 + 8) & RM) * GA + gl;
                 const T *const sb = slots + (s0 & RM) * SLOT + lane;
@@ -1003,14 +1007,16 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                         acc -= cur.cv[0] * xp;
                         acc *= cur.cv[3];
                     }
+                    const bool valid = !MASKED || (uint32_t)(s - moff) < ncl;
+                    if constexpr (MASKED) acc = valid ? acc : (T)0;
                     T *gn = u < 7 ? gb + (u + 1) * GA : gx;
                     gn[2] = acc;
                     gn[2 * GG + 1] = acc;
-                    *xo = acc;
+                    if (valid) *xo = acc;
                     xo += dsc;
                     // an arithmetic result is never the signalling-NaN sentinel (IEEE mode
                     // quiets NaN operands), so no check is needed before publishing it
-                    if (fst) {
+                    if (valid && fst) {
                         U bits;
                         __builtin_memcpy(&bits, &acc, sizeof(T));
                         __hip_atomic_store((U *)(fb + u * 8), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1027,10 +1033,15 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             Step h0, h1;
             if (ensure(0)) load_step(0, h0);
             for (int s0 = 0; s0 < G.S && !bail; s0 += 8) {
-                if (full && s0 >= 2 * (GT - 1) && s0 + 8 <= G.NC) {
+                const bool whole = full && s0 >= 2 * (GT - 1) && s0 + 8 <= G.NC;
+                if (whole || s0 + 8 < G.S) {
                     while (ready <= s0 + 8 && !bail) ready = scan(ready);
-                    if (!bail) block8(s0, h0, h1);
-                } else {
+                    if (bail) break;
+                    if (whole)
+                        block8(std::integral_constant<bool, false>{}, s0, h0, h1);
+                    else
+                        block8(std::integral_constant<bool, true>{}, s0, h0, h1);
+                } else {  // the last, partial block
                     for (int s = s0; s < min(s0 + 8, G.S) && !bail; s += 2) {
                         if (s >= ready || s >= fready) ensure(s);  // after a block: step s's faces
                         step(s, h0, h1, false);
