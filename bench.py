@@ -357,10 +357,20 @@ def main():
         bh = b.cpu().numpy()
         cores_avail = sorted(os.sched_getaffinity(0))
         cpu_model = "unknown"
-        try:
+        try:  # the first processor's identification (a virtual machine may shorten the model name)
+            info = {}
             with open("/proc/cpuinfo") as f:
-                cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-        except (OSError, StopIteration):
+                for l in f:
+                    if not l.strip():
+                        break
+                    k, _, v = l.partition(":")
+                    info[k.strip()] = v.strip()
+            cpu_model = info.get("model name", "unknown")
+            ids = [f"{k} {info[k]}" for k in ("vendor_id", "cpu family", "model", "stepping", "cpu MHz", "cache size")
+                   if k in info]
+            if ids:
+                cpu_model += " (" + ", ".join(ids) + ")"
+        except OSError:
             pass
         # the oracle is single-threaded; pin it to one core of this host
         os.sched_setaffinity(0, {cores_avail[0]})
