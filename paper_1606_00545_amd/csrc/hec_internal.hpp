@@ -258,6 +258,7 @@ struct hec_flat {
 // Wavefront plan of a grid triangle (plan.hpp's GridPlan) on the device.
 struct hec_grid {
     bool on = false;
+    int32_t TA = 8;  // tile side along a: 8 (8 x 8 tiles, 3D grid) or 64 (64 x 1, 2D grid)
     int32_t NA = 0, NB = 0, NC = 0, PA = 0, PB = 0, S = 0;
     int64_t sa = 0, sb = 0, sc = 0;
     hec::DevBuf<double> coef;  // [claim][step][k][lane]; k = 3 (upper): the reciprocal pivot

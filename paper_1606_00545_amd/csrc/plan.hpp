@@ -579,28 +579,32 @@ inline void make_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const i
 // of a 7-point stencil gives (Sec. 2.6: the level of a row is then the sum of its
 // coordinates, Eq. (11)).
 //
-// The grid is cut into tiles of kGT x kGT columns along two axes (a, b); the columns
-// run along the third (c, the longest). One wavefront takes a tile: lane (ma, mb)
-// solves its column's rows in order, the row at c-index mc at step s = mc + ma + mb.
+// The grid is cut into tiles of TA x TB columns along two axes (a, b); the columns
+// run along the third (c, the longest): 8 x 8 on a 3D grid, 64 x 1 on a 2D grid (b
+// is then the unit axis, and a tile is 64 columns side by side). One wavefront takes
+// a tile: lane (ma, mb) = (lane % TA, lane / TA) solves its column's rows in order,
+// the row at c-index mc at step s = mc + ma + mb.
 // The three dependencies of that row were solved one step earlier: the one behind
 // it along c by the lane itself, the ones along a and b by lanes (ma - 1, mb) and
 // (ma, mb - 1), or, on the tile's low faces, by the tiles before it, which hand the
 // values over through face buffers in global memory. The upper triangle runs the
-// same schedule in mirrored coordinates (m = kGT - 1 - local index along a and b,
-// c reversed, tiles claimed in reverse order), so one kernel serves both.
+// same schedule in mirrored coordinates (m = TA - 1, TB - 1 - local index along a
+// and b, c reversed, tiles claimed in reverse order), so one kernel serves both.
 //
 // Tiles are claimed in order: claim t is the m-tile (t % PA, t / PA); its
 // dependencies lie in claims t - 1 and t - PA, both earlier.
-constexpr int kGT = 8;                       // tile side in columns: kGT * kGT = 64 lanes
-constexpr int kGridSkew = 2 * (kGT - 1);     // steps of a tile beyond the c extent
+constexpr int kGT = 8;                       // tile side on a 3D grid: kGT * kGT = 64 lanes
+constexpr int kGT2 = 64;                     // tile side along a on a 2D grid (64 x 1)
+constexpr int kGT2Min = 16;                  // a 2D grid needs this many columns along a
 constexpr int kGridCoefLower = 3;            // per lane and step: back (c), below (b), left (a)
 constexpr int kGridCoefUpper = 4;            // ... and the reciprocal pivot
 
 struct GridPlan {
     int32_t NA = 0, NB = 0, NC = 0;  // extents along a, b and c
     int64_t sa = 0, sb = 0, sc = 0;  // row strides along a, b and c
+    int32_t TA = kGT, TB = kGT;      // tile sides along a and b (TA * TB = 64)
     int32_t PA = 0, PB = 0;          // tiles along a and b
-    int32_t S = 0;                   // steps of one tile: NC + kGridSkew
+    int32_t S = 0;                   // steps of one tile: NC + (TA - 1) + (TB - 1)
     int32_t ncoef = 0;               // kGridCoefLower or kGridCoefUpper
     // [claim][step][k][lane]: index into the factor's values of coefficient k of the
     // lane's row at that step (k = 3: the pivot, whose reciprocal is used), -1: none
@@ -614,16 +618,17 @@ struct GridCell {
     int32_t ga, gb, gc;
     bool valid;
 };
-HEC_HD inline GridCell grid_cell(int32_t NA, int32_t NB, int32_t NC, int32_t PA, int32_t PB, bool upper,
+HEC_HD inline GridCell grid_cell(int32_t NA, int32_t NB, int32_t NC, int32_t PA, int32_t PB, int TA, bool upper,
                                  int64_t claim, int lane, int32_t s) {
+    const int TB = 64 / TA;
     const int32_t mta = (int32_t)(claim % PA), mtb = (int32_t)(claim / PA);
     const int32_t ta = upper ? PA - 1 - mta : mta, tb = upper ? PB - 1 - mtb : mtb;
-    const int ma = lane % kGT, mb = lane / kGT;
-    const int la = upper ? kGT - 1 - ma : ma, lb = upper ? kGT - 1 - mb : mb;
+    const int ma = lane % TA, mb = lane / TA;
+    const int la = upper ? TA - 1 - ma : ma, lb = upper ? TB - 1 - mb : mb;
     const int32_t mc = s - ma - mb;
     GridCell g;
-    g.ga = ta * kGT + la;
-    g.gb = tb * kGT + lb;
+    g.ga = ta * TA + la;
+    g.gb = tb * TB + lb;
     g.gc = upper ? NC - 1 - mc : mc;
     g.valid = g.ga < NA && g.gb < NB && mc >= 0 && mc < NC;
     return g;
@@ -631,8 +636,8 @@ HEC_HD inline GridCell grid_cell(int32_t NA, int32_t NB, int32_t NC, int32_t PA,
 
 // Builds the wavefront plan of the strict lower (upper) triangle of the factor pattern
 // on the nx x ny x nz grid. Returns false (G untouched) when it does not apply: no
-// grid, fewer than kGT columns along a tile axis, or an entry that is not one of the
-// three neighbours behind its row.
+// grid, fewer than kGT columns along a tile axis of a 3D grid (kGT2Min along a of a
+// 2D one), or an entry that is not one of the neighbours behind its row.
 inline bool make_grid_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, const int32_t *diag, int32_t gnx,
                            int32_t gny, int32_t gnz, bool upper, GridPlan &G) {
     if (gnx <= 0 || gny <= 0 || gnz <= 0 || (int64_t)gnx * gny * gnz != n) return false;
@@ -642,7 +647,8 @@ inline bool make_grid_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, co
     for (int k = 1; k >= 0; --k)
         if (ext[k] > ext[c]) c = k;
     const int a = c == 0 ? 1 : 0, b = c == 2 ? 1 : 2;  // the others, by stride
-    if (ext[a] < kGT || ext[b] < kGT) return false;
+    const bool flat = ext[b] == 1;  // a 2D grid (b the unit axis): tiles of 64 x 1
+    if (flat ? ext[a] < kGT2Min : ext[a] < kGT || ext[b] < kGT) return false;
     // every strict-triangle entry must be a neighbour behind the row
     for (int32_t i = 0; i < n; ++i) {
         const int32_t co[3] = {i % gnx, (i / gnx) % gny, i / (gnx * gny)};
@@ -664,9 +670,11 @@ inline bool make_grid_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, co
     P.sa = str[a];
     P.sb = str[b];
     P.sc = str[c];
-    P.PA = (P.NA + kGT - 1) / kGT;
-    P.PB = (P.NB + kGT - 1) / kGT;
-    P.S = P.NC + kGridSkew;
+    P.TA = flat ? kGT2 : kGT;
+    P.TB = 64 / P.TA;
+    P.PA = (P.NA + P.TA - 1) / P.TA;
+    P.PB = (P.NB + P.TB - 1) / P.TB;
+    P.S = P.NC + (P.TA - 1) + (P.TB - 1);
     P.ncoef = upper ? kGridCoefUpper : kGridCoefLower;
     const int64_t nc = P.nclaims();
     P.src.assign((size_t)(nc * P.S * P.ncoef * 64), -1);
@@ -674,7 +682,7 @@ inline bool make_grid_plan(int32_t n, const int32_t *LUp, const int32_t *LUj, co
     for (int64_t t = 0; t < nc; ++t)
         for (int32_t s = 0; s < P.S; ++s)
             for (int lane = 0; lane < 64; ++lane) {
-                const GridCell g = grid_cell(P.NA, P.NB, P.NC, P.PA, P.PB, upper, t, lane, s);
+                const GridCell g = grid_cell(P.NA, P.NB, P.NC, P.PA, P.PB, P.TA, upper, t, lane, s);
                 if (!g.valid) continue;
                 const int64_t row = g.ga * P.sa + g.gb * P.sb + g.gc * P.sc;
                 const int64_t dep[3] = {row + sg * P.sc, row + sg * P.sb, row + sg * P.sa};  // back, below, left

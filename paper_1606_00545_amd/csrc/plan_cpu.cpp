@@ -90,10 +90,10 @@ void *hecplan_grid_make(int32_t n, const int32_t *LUp, const int32_t *LUj, const
     return nullptr;
 }
 
-// meta[0..9] = NA, NB, NC, sa, sb, sc, PA, PB, S, ncoef.
+// meta[0..11] = NA, NB, NC, sa, sb, sc, PA, PB, S, ncoef, TA, TB.
 void hecplan_grid_meta(const void *h, int64_t *meta) {
     const auto &G = *(const hec::plan::GridPlan *)h;
-    const int64_t m[10] = {G.NA, G.NB, G.NC, G.sa, G.sb, G.sc, G.PA, G.PB, G.S, G.ncoef};
+    const int64_t m[12] = {G.NA, G.NB, G.NC, G.sa, G.sb, G.sc, G.PA, G.PB, G.S, G.ncoef, G.TA, G.TB};
     std::memcpy(meta, m, sizeof(m));
 }
 

@@ -739,7 +739,6 @@ constexpr int kGridPollers = HEC_GRID_POLLERS;
 constexpr int kGridLoaders = kGridWaves - 1 - kGridPollers;
 constexpr int kGridBatch = 3;   // consecutive steps a loader has in flight
 constexpr int kGridRing = 32;   // steps in LDS (slots and grids): how far loads run ahead
-constexpr int kGridG = plan::kGT + 1;  // side of a step's grid of cells: the tile and its low faces
 static_assert((kGridRing & (kGridRing - 1)) == 0 && kGridRing % 8 == 0 && kGridBatch <= kGridRing, "ring");
 
 struct GridArgs {
@@ -767,22 +766,28 @@ struct GridIO {
 };
 
 // Dynamic LDS of k_trsv_grid: control words, slots [ring][NCOEF + 1][64], grids
-// [ring][9 * 9][2] (a cell: the value from the left, the value from below).
+// [ring][TB + 1][TA + 1][2] (a cell: the value from the left, the value from below).
 constexpr size_t kGridCtrl = 256;
-template <class T, bool UPPER>
+template <class T, bool UPPER, int TA>
 constexpr size_t grid_lds_bytes() {
     constexpr int NCOEF = UPPER ? plan::kGridCoefUpper : plan::kGridCoefLower;
     return kGridCtrl + (size_t)kGridRing * (NCOEF + 1) * 64 * sizeof(T) +
-           (size_t)kGridRing * kGridG * kGridG * 2 * sizeof(T);
+           (size_t)kGridRing * (TA + 1) * (64 / TA + 1) * 2 * sizeof(T);
 }
 
-template <class T, bool UPPER>
+// TA: tile side along a (8: 8 x 8 tiles of a 3D grid; 64: 64 x 1 tiles of a 2D grid,
+// whose b-face is empty: its cells are zeroed once per tile and never written again).
+template <class T, bool UPPER, int TA>
 __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const T *__restrict__ coef, GridIO<T> io,
                                                                uint32_t *sync, const int32_t *skip) {
     using U = typename Sentinel<T>::U;
     constexpr U SENT = Sentinel<T>::bits;
     constexpr int NCOEF = UPPER ? plan::kGridCoefUpper : plan::kGridCoefLower;
-    constexpr int GT = plan::kGT, GG = kGridG, GA = GG * GG * 2, RM = kGridRing - 1;
+    static_assert(TA == plan::kGT || TA == plan::kGT2, "tile shape");
+    constexpr int TB = 64 / TA, GG = TA + 1, GA = (TA + 1) * (TB + 1) * 2, RM = kGridRing - 1;
+    // face entries per step in the face buffer: 8 and 8 on a 3D grid, the one a-face entry
+    // on a 2D grid (no tile has a tile above it there)
+    constexpr int FS = TA == TB ? TA : TB;
     constexpr int SLOT = (NCOEF + 1) * 64;  // elements of a slot: [NCOEF][64] coefficients, [64] rhs
     if (skip && *skip) return;  // uniform: no workgroup touches the counters
     if (io.fill) {
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
     T *const slots = (T *)(gsm + kGridCtrl);
     T *const xg = slots + kGridRing * SLOT;  // [ring][9][9][2]: row mb, column ma; left, below
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ma = lane % GT, mb = lane / GT;
+    const int ma = lane % TA, mb = lane / TA;
     if (threadIdx.x == 0) *s_abort = 0;
     auto give_up = [&]() {
         __hip_atomic_store(s_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -838,15 +843,16 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             *s_faces = 0;
         }
         if (threadIdx.x < kGridRing) filled[threadIdx.x] = -1;
-        for (int t = threadIdx.x; t < GA; t += blockDim.x) xg[t] = (T)0;  // step 0: no previous results
+        // step 0: no previous results (a 2D tile: every grid, whose b-face cells stay zero)
+        for (int t = threadIdx.x; t < (TB == 1 ? kGridRing * GA : GA); t += blockDim.x) xg[t] = (T)0;
         __syncthreads();
         const int c = *s_claim;
         if (c >= G.nclaims) break;
         const int mta = c % G.PA, mtb = c / G.PA;
         const int32_t ta = UPPER ? G.PA - 1 - mta : mta, tb = UPPER ? G.PB - 1 - mtb : mtb;
         // global a and b of the column of lane (ma', mb')
-        auto col_a = [&](int m) { return ta * GT + (UPPER ? GT - 1 - m : m); };
-        auto col_b = [&](int m) { return tb * GT + (UPPER ? GT - 1 - m : m); };
+        auto col_a = [&](int m) { return ta * TA + (UPPER ? TA - 1 - m : m); };
+        auto col_b = [&](int m) { return tb * TB + (UPPER ? TB - 1 - m : m); };
         const bool act = col_a(ma) < G.NA && col_b(mb) < G.NB;
         const int64_t base = (int64_t)col_a(ma) * G.sa + (int64_t)col_b(mb) * G.sb;
         auto row_at = [&](int32_t mc) { return base + (int64_t)(UPPER ? G.NC - 1 - mc : mc) * G.sc; };
@@ -859,9 +865,9 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             __builtin_amdgcn_s_setprio(3);
             const bool has_u = mtb < G.PB - 1;  // a tile above reads the b-face
             // this lane's face store (if any): a-face by mb (the corner too), b-face by ma
-            const bool fst = ma == GT - 1 || (mb == GT - 1 && has_u);
-            T *const fp = io.face + ((int64_t)c * 2 + (ma == GT - 1 ? 0 : 1)) * G.S * 8 +
-                          (ma == GT - 1 ? mb : ma) - (GT - 1) * 8;  // + 8 s: the entry of step s
+            const bool fst = ma == TA - 1 || (mb == TB - 1 && has_u);
+            T *const fp = io.face + ((int64_t)c * 2 + (ma == TA - 1 ? 0 : 1)) * G.S * 8 +
+                          (ma == TA - 1 ? mb - (TA - 1) * FS : ma - (TB - 1) * FS);  // + FS s: the entry of step s
             T xp = (T)0;  // this lane's result of the previous step (0: none)
             int ready = 0, fready = 0;
             bool bail = false;
@@ -953,7 +959,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                 gn[2 * GG + 1] = xn;  // below slot of the cell above
                 if (valid && !bail) {
                     io.x[roff] = xn;
-                    if (fst) store_coherent(fp + (int64_t)s * 8, xn);  // the next tiles read it at step s - 7
+                    if (fst) store_coherent(fp + (int64_t)s * FS, xn);  // the next tile reads it at step s - TA + 1
                 }
                 xp = xn;
                 roff += dsc;
@@ -971,7 +977,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             // face values are checked step by step, as they arrive. MASKED: lanes whose row
             // at a step is not valid publish zeros and store nothing; unmasked blocks are
             // those at which every lane's row is valid (a tile with all 64 columns in the
-            // grid, 2 (GT - 1) <= s0 and s0 + 8 <= NC: the bulk of a long column).
+            // grid, TA + TB - 2 <= s0 and s0 + 8 <= NC: the bulk of a long column).
             // On entry H0 holds step s0's coefficients; on exit step s0 + 8's.
             auto block8 = [&](auto masked, int s0, Step &H0, Step &H1) {
                 constexpr bool MASKED = decltype(masked)::value;
@@ -979,7 +985,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                 T *const gx = xg + ((s0 + 8) & RM) * GA + gl;
                 const T *const sb = slots + (s0 & RM) * SLOT + lane;
                 const T *const sx = slots + ((s0 + 8) & RM) * SLOT + lane;
-                T *const fb = fp + (int64_t)s0 * 8;
+                T *const fb = fp + (int64_t)s0 * FS;
                 T *xo = io.x + roff;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -1019,7 +1025,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                     if (valid && fst) {
                         U bits;
                         __builtin_memcpy(&bits, &acc, sizeof(T));
-                        __hip_atomic_store((U *)(fb + u * 8), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store((U *)(fb + u * FS), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                     xp = acc;
                 }
@@ -1033,7 +1039,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             Step h0, h1;
             if (ensure(0)) load_step(0, h0);
             for (int s0 = 0; s0 < G.S && !bail; s0 += 8) {
-                const bool whole = full && s0 >= 2 * (GT - 1) && s0 + 8 <= G.NC;
+                const bool whole = full && s0 >= TA + TB - 2 && s0 + 8 <= G.NC;
                 if (whole || s0 + 8 < G.S) {
                     while (ready <= s0 + 8 && !bail) ready = scan(ready);
                     if (bail) break;
@@ -1050,6 +1056,47 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                 }
             }
             __builtin_amdgcn_s_setprio(0);
+        } else if (TB == 1 && wave <= kGridPollers) {
+            // ---------------- face poller of a 2D tile: its one face value per step (the left
+            // value of lane 0), from the tile before along a. Lane l < 32 polls step w + l; a
+            // value goes into its step's grid once, when it has arrived and the solver is done
+            // with the grid's previous use; the window moves on by the leading steps that have
+            // their value, whose count is published.
+            if (wave == 1) {
+                const bool has = mta > 0;
+                const T *const fsrc = has ? io.face + (int64_t)(c - 1) * 2 * G.S * 8 : io.face;
+                int w = 0, pub = 0;
+                bool wr = false;  // this lane's value of step w + lane is in its grid
+                uint32_t it = 0;
+                while (pub < G.S) {
+                    const int dn = lds_load(s_done);
+                    const int st = w + lane;
+                    const bool can = lane < 32 && !wr && st < G.S && st < dn + kGridRing;
+                    const bool need = can && has && st < G.NC;
+                    const U v = need ? load_coherent(fsrc + st) : (U)0;
+                    if (can && (!need || v != SENT)) {
+                        xg[(st & RM) * GA] = need ? from_bits<T>(v) : (T)0;
+                        wr = true;
+                    }
+                    const uint64_t m = __ballot(wr || (lane < 32 && st >= G.S)) & 0xFFFFFFFFull;
+                    const int k = __builtin_ctzll(~m);  // leading steps of the window with their value
+                    if (w + k > pub) {
+                        pub = min(w + k, G.S);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // after this wave's writes
+                        if (lane == 0) __hip_atomic_fetch_max(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        it = 0;
+                    } else {
+                        if (spun_out(it, true)) break;
+                        __builtin_amdgcn_s_sleep(HEC_GRID_POLL_SLEEP);
+                    }
+                    if (k > 0) {  // lane l takes over lane l + k's step
+                        const int from = lane + k;
+                        const int nw = __shfl((int)wr, from < 64 ? from : lane);
+                        wr = from < 32 && nw != 0;
+                        w += k;
+                    }
+                }
+            }
         } else if (wave <= kGridPollers) {
             // ---------------- face pollers: a window of 4R steps from w, step w + q + 4r in
             // lane 16q + i for r < R; i < 8: a-face entry i (lane (0, i)), i >= 8:
@@ -1059,13 +1106,13 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
             // with all their values is published as it grows.
             constexpr int R = HEC_GRID_POLL_R;
             const int q = lane >> 4, i = lane & 15, j = i & 7;
-            const bool on_a = i < GT;
+            const bool on_a = i < 8;
             const bool has = on_a ? mta > 0 && col_b(j) < G.NB : mtb > 0 && col_a(j) < G.NA;
             // a-face entry j: a-face of the tile before along a; b-face entry j: b-face of the
             // tile below, its corner (j = 7) on that tile's a-face
             const T *const fsrc = !has              ? io.face  // (not read)
                                   : on_a            ? io.face + ((int64_t)(c - 1) * 2 + 0) * G.S * 8 + j
-                                  : j == GT - 1     ? io.face + ((int64_t)(c - G.PA) * 2 + 0) * G.S * 8 + j
+                                  : j == TA - 1     ? io.face + ((int64_t)(c - G.PA) * 2 + 0) * G.S * 8 + j
                                                     : io.face + ((int64_t)(c - G.PA) * 2 + 1) * G.S * 8 + j;
             // a-face: left slot of lane (0, j)'s cell; b-face: below slot of lane (j, 0)'s cell
             const int gpos = on_a ? j * GG * 2 : j * 2 + 1;
@@ -1278,14 +1325,22 @@ void launch_grid(const hec_grid &g, uint32_t *sync, uint32_t *err, const GridIO<
     else
         coef = g.coef32.get();
     const int grid = std::min(nclaims, 1024);
-    constexpr size_t lds = grid_lds_bytes<T, UPPER>();
-    static bool attr_set = false;  // one per instantiation
-    if (!attr_set) {
-        HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_grid<T, UPPER>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-        attr_set = true;
-    }
-    k_trsv_grid<T, UPPER><<<grid, 64 * kGridWaves, lds, s>>>(G, coef, io, sync, skip);
+    auto go = [&](auto ta) {
+        constexpr int TA = decltype(ta)::value;
+        constexpr size_t lds = grid_lds_bytes<T, UPPER, TA>();
+        static_assert(lds <= 160 * 1024, "LDS");
+        static bool attr_set = false;  // one per instantiation
+        if (!attr_set) {
+            HEC_HIP(hipFuncSetAttribute((const void *)k_trsv_grid<T, UPPER, TA>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_set = true;
+        }
+        k_trsv_grid<T, UPPER, TA><<<grid, 64 * kGridWaves, lds, s>>>(G, coef, io, sync, skip);
+    };
+    if (g.TA == plan::kGT)
+        go(std::integral_constant<int, plan::kGT>());
+    else
+        go(std::integral_constant<int, plan::kGT2>());
     HEC_CHECK_LAUNCH();
 }
 
@@ -1400,6 +1455,7 @@ void build_grid(const hec_ilu_s &M, bool upper, hec_grid &g, hipStream_t s) {
     plan::GridPlan P;
     if (!plan::make_grid_plan(M.n, M.hLUp.data(), M.hLUj.data(), M.hdiag.data(), M.gnx, M.gny, M.gnz, upper, P))
         return;
+    g.TA = P.TA;
     g.NA = P.NA;
     g.NB = P.NB;
     g.NC = P.NC;

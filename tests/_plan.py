@@ -87,7 +87,7 @@ def make_plan(F, upper, grid=(0, 0, 0), has_f32=True, lds_max=LDS_MAX, flat=Fals
     return P
 
 
-GRID_META = ("NA", "NB", "NC", "sa", "sb", "sc", "PA", "PB", "S", "ncoef")
+GRID_META = ("NA", "NB", "NC", "sa", "sb", "sc", "PA", "PB", "S", "ncoef", "TA", "TB")
 
 
 def make_grid_plan(F, upper, grid):
@@ -99,7 +99,7 @@ def make_grid_plan(F, upper, grid):
     if not h:
         return None
     try:
-        meta = np.zeros(10, np.int64)
+        meta = np.zeros(12, np.int64)
         L.hecplan_grid_meta(h, meta)
         G = {k: int(v) for k, v in zip(GRID_META, meta)}
         m = L.hecplan_grid_src(h, None)

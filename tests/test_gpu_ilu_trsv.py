@@ -16,6 +16,7 @@ U32 = 2.0 ** -24
 
 def _cases():
     yield "poisson2d_64_k0", synth.poisson2d(64), 0
+    yield "poisson2d_64_k0_blocked", synth.poisson2d(64), 0
     yield "tpfa3d_k0", synth.lognormal_tpfa((17, 13, 11), 2.0, np.random.default_rng(2)), 0
     yield "tpfa3d_k1", synth.lognormal_tpfa((17, 13, 11), 2.0, np.random.default_rng(2)), 1
     yield "tpfa3d_k2", synth.lognormal_tpfa((9, 8, 7), 1.0, np.random.default_rng(3)), 2
@@ -45,7 +46,7 @@ def built():
             lv = hec.level_schedule(M)
         finally:
             hec.set_trsv_grid(True)
-        assert hec.levels_grid(lv) == (name in ("tpfa3d_k0", "tpfa3d_41x37x23_k0"))
+        assert hec.levels_grid(lv) == (name in ("poisson2d_64_k0", "tpfa3d_k0", "tpfa3d_41x37x23_k0"))
         out[name] = (A, k, F, M, lv)
     return out
 

@@ -24,11 +24,13 @@ def _oracle_lu(A, k, b):
     return O.trsv_upper(Fo, O.trsv_lower(Fo, b))
 
 
-@pytest.mark.parametrize("case", ["grid_f64", "grid_f32", "blocked_f64", "blocked_f32", "fallback"])
+@pytest.mark.parametrize("case", ["grid_f64", "grid_f32", "grid2d_f64", "blocked_f64", "blocked_f32", "fallback"])
 def test_zero_spin_limit_gives_up_and_recovers(case):
     import torch
     if case == "fallback":  # ILU(3) rows carry more than 32 entries: the per-row polling kernel
         A, k = synth.poisson3d(14), 3
+    elif case == "grid2d_f64":  # the wavefront solve with 64 x 1 tiles
+        A, k = synth.lognormal_tpfa((150, 120, 1), 2.0, np.random.default_rng(5)), 0
     else:
         A, k = synth.workload_diffusion3d(40, sigma=2.0, seed=5)[0], 0
     f32 = case.endswith("f32")

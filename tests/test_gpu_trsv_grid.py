@@ -1,8 +1,9 @@
-"""GPU parity of the wavefront triangular solve (7-point ILU(0) factors on 3D grids,
-Sec. 2.6, Eq. (11)) against the oracle's substitution: lone lower and upper solves and
-the L-then-U chain, FP64 within 1e-12 and with a componentwise backward-error bound,
-FP32 within the FP32 bound, ragged tiles along both tile axes, columns along x, y or z,
-and the level-blocked kernel on the same schedule for comparison. Calls in any order
+"""GPU parity of the wavefront triangular solve (ILU(0) factors of 7-point stencils on 3D
+grids and 5-point stencils on 2D grids, Sec. 2.6, Eq. (11)) against the oracle's
+substitution: lone lower and upper solves and the L-then-U chain, FP64 within 1e-12 and
+with a componentwise backward-error bound, FP32 within the FP32 bound, ragged tiles along
+both tile axes, columns along x, y or z, and the level-blocked kernel on the same
+schedule for comparison. Calls in any order
 reuse the face buffers and counters correctly (bit-identical repeats)."""
 import numpy as np
 import pytest
@@ -17,10 +18,13 @@ pytestmark = pytest.mark.gpu
 U64 = 2.0 ** -53
 
 # (shape, seed): columns along z (cubic, ragged 19 x 13), along x (41 longest), along y,
-# one tile with a ragged second one, the smallest grid with a plan, and long columns (many
-# steps at which every lane of a whole tile has a row, next to ragged tiles)
+# one tile with a ragged second one, the smallest grid with a plan, long columns (many
+# steps at which every lane of a whole tile has a row, next to ragged tiles); 2D grids
+# (64 x 1 tiles): one tile, three along x with a ragged last (columns along y), two
+# along y (columns along x), and one tile with 20 of its 64 lanes in the grid
 SHAPES = [((24, 24, 24), 1), ((19, 13, 30), 2), ((41, 37, 23), 3), ((13, 45, 16), 4), ((9, 8, 10), 5),
-          ((8, 8, 8), 6), ((19, 13, 70), 7)]
+          ((8, 8, 8), 6), ((19, 13, 70), 7), ((64, 64, 1), 8), ((130, 200, 1), 9), ((150, 70, 1), 10),
+          ((20, 33, 1), 11)]
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +70,7 @@ def test_wavefront_fp64_matches_oracle(built, shape):
         assert (np.abs(y_o - U @ z) <= gam * (np.abs(U) @ np.abs(z)) + 1e-300).all()
 
 
-@pytest.mark.parametrize("shape", [(24, 24, 24), (41, 37, 23)])
+@pytest.mark.parametrize("shape", [(24, 24, 24), (41, 37, 23), (130, 200, 1)])
 def test_wavefront_agrees_with_blocked_kernel(built, shape):
     """The switch is read when a schedule is built: a second schedule of the same factor
     built with it off has level-blocked plans and gives the same results within rounding."""
@@ -90,7 +94,7 @@ def test_wavefront_agrees_with_blocked_kernel(built, shape):
     assert np.linalg.norm(xg - xb) <= 1e-13 * np.linalg.norm(xb)
 
 
-@pytest.mark.parametrize("shape", [(24, 24, 24), (19, 13, 30)])
+@pytest.mark.parametrize("shape", [(24, 24, 24), (19, 13, 30), (150, 70, 1)])
 def test_wavefront_fp32(built, shape):
     import torch
     A, F, M, lv = built[shape]
@@ -122,7 +126,8 @@ def test_calls_in_any_order_repeat_bit_for_bit(built):
 
 
 def test_no_plan_where_it_does_not_apply():
-    for A, k in ((synth.poisson3d(16), 1), (synth.poisson2d(64), 0),
-                 (synth.lognormal_tpfa((7, 30, 30), 1.0, np.random.default_rng(3)), 0)):
+    for A, k in ((synth.poisson3d(16), 1), (synth.poisson2d(64), 1),
+                 (synth.lognormal_tpfa((7, 30, 30), 1.0, np.random.default_rng(3)), 0),
+                 (synth.lognormal_tpfa((12, 90, 1), 1.0, np.random.default_rng(3)), 0)):
         lv = hec.level_schedule(hec.ilu_factor(A, k=k))
         assert not hec.levels_grid(lv)

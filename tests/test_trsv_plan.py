@@ -483,24 +483,25 @@ def replay_grid(G, F, rhs, upper):
     upper: left, below, back, then the pivot, here a division as in the oracle)."""
     NA, NB, NC, PA, PB, S, nco = (G[k] for k in ("NA", "NB", "NC", "PA", "PB", "S", "ncoef"))
     sa, sb, sc = G["sa"], G["sb"], G["sc"]
+    TA, TB = G["TA"], G["TB"]
     lanes = np.arange(64)
-    ma, mb = lanes % 8, lanes // 8
+    ma, mb = lanes % TA, lanes // TA
     src = G["src"].reshape(PA * PB, S, nco, 64)
     vals = np.where(src >= 0, F.LUx[np.maximum(src, 0)], 0.0)
     x = np.full(F.n, np.nan)
     written = np.zeros(F.n, np.int32)
-    faces = np.full((PA * PB, 2, S, 8), np.nan)
-    la, lb = (7 - ma, 7 - mb) if upper else (ma, mb)
+    faces = np.full((PA * PB, 2, S, max(TA, TB)), np.nan)
+    la, lb = (TA - 1 - ma, TB - 1 - mb) if upper else (ma, mb)
     for c in range(PA * PB):
         mta, mtb = c % PA, c // PA
         ta, tb = (PA - 1 - mta, PB - 1 - mtb) if upper else (mta, mtb)
-        ga, gb = ta * 8 + la, tb * 8 + lb
+        ga, gb = ta * TA + la, tb * TB + lb
         act = (ga < NA) & (gb < NB)
         base = ga * sa + gb * sb
         xp = np.zeros(64)
         for s in range(S):
             left_l = np.concatenate(([0.0], xp[:-1]))
-            below_l = np.concatenate((np.zeros(8), xp[:-8]))
+            below_l = np.concatenate((np.zeros(TA), xp[:-TA]))
             mc = s - ma - mb
             valid = act & (mc >= 0) & (mc < NC)
             fa, fb = np.zeros(64), np.zeros(64)
@@ -508,9 +509,9 @@ def replay_grid(G, F, rhs, upper):
                 need = (ma == 0) & valid
                 fa[need] = faces[c - 1, 0, s, mb[need]]
                 assert not np.isnan(fa[need]).any(), (c, s)
-            if mtb > 0:  # b-face of the tile below; its corner (ma = 7) on that tile's a-face
+            if mtb > 0:  # b-face of the tile below; its corner (ma = TA - 1) on that tile's a-face
                 need = (mb == 0) & valid
-                fb[need] = np.where(ma[need] == 7, faces[c - PA, 0, s, 7], faces[c - PA, 1, s, ma[need]])
+                fb[need] = np.where(ma[need] == TA - 1, faces[c - PA, 0, s, TB - 1], faces[c - PA, 1, s, ma[need]])
                 assert not np.isnan(fb[need]).any(), (c, s)
             left = np.where(ma == 0, fa, left_l)
             below = np.where(mb == 0, fb, below_l)
@@ -531,24 +532,26 @@ def replay_grid(G, F, rhs, upper):
             xn = np.where(valid, acc, 0.0)
             x[row[valid]] = xn[valid]
             written[row[valid]] += 1
-            sel = (ma == 7) & valid  # the a-face, corner included, whether or not a tile reads it
-            faces[c, 0, s - 7, mb[sel]] = xn[sel]
+            sel = (ma == TA - 1) & valid  # the a-face, corner included, whether or not a tile reads it
+            faces[c, 0, s - (TA - 1), mb[sel]] = xn[sel]
             if mtb < PB - 1:
-                sel = (mb == 7) & (ma < 7) & valid
-                faces[c, 1, s - 7, ma[sel]] = xn[sel]
+                sel = (mb == TB - 1) & (ma < TA - 1) & valid
+                faces[c, 1, s - (TB - 1), ma[sel]] = xn[sel]
             xp = xn
     assert (written == 1).all()  # every row solved exactly once
     return x
 
 
 @pytest.mark.parametrize("shape,exact", [((24, 24, 24), True), ((19, 13, 30), True), ((41, 37, 23), False),
-                                         ((8, 9, 8), False), ((9, 8, 10), True)])
+                                         ((8, 9, 8), False), ((9, 8, 10), True), ((64, 64, 1), True),
+                                         ((40, 100, 1), True), ((130, 200, 1), True), ((150, 70, 1), False)])
 def test_grid_plan_replay(shape, exact):
-    """Wavefront plans of ILU(0) triangles of 7-point grids, tiles ragged along both tile
-    axes where the extents are not multiples of 8, replayed on the host in kernel order:
-    every row solved once, every face value read after it is stored, and the result equal
-    to the oracle's substitution -- bit for bit where the columns run along z (the
-    kernel's subtraction order is then the oracle's), within rounding otherwise."""
+    """Wavefront plans of ILU(0) triangles of 7-point grids (8 x 8 tiles) and 5-point 2D
+    grids (64 x 1 tiles), tiles ragged where the extents are not multiples of the tile
+    sides, replayed on the host in kernel order: every row solved once, every face value
+    read after it is stored, and the result equal to the oracle's substitution -- bit for
+    bit where the columns run along the axis of largest stride (the kernel's subtraction
+    order is then the oracle's), within rounding otherwise."""
     A = synth.lognormal_tpfa(shape, 2.0, np.random.default_rng(21))
     F = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
     grid = _plan.detect_grid(A)
@@ -560,7 +563,8 @@ def test_grid_plan_replay(shape, exact):
         G = _plan.make_grid_plan(F, upper, grid)
         assert G is not None
         longest = int(np.argmax(np.array(shape) + np.array([0, 1e-3, 2e-3])))  # ties: the largest stride
-        assert G["NC"] == shape[longest] and G["S"] == G["NC"] + 14
+        assert G["NC"] == shape[longest] and G["S"] == G["NC"] + G["TA"] + G["TB"] - 2
+        assert (G["TA"], G["TB"]) == ((64, 1) if shape[2] == 1 else (8, 8))
         assert G["ncoef"] == (4 if upper else 3)
         x = replay_grid(G, F, rhs, upper)
         if exact:
@@ -571,8 +575,9 @@ def test_grid_plan_replay(shape, exact):
 
 def test_grid_plan_refusals():
     """Wavefront plans only where they apply: ILU(1) fill (an entry off the three
-    neighbours behind a row), a 2D grid, fewer than 8 columns along a tile axis, and a
-    matrix that is no grid all get none."""
+    neighbours behind a row), fewer than 8 columns along a tile axis of a 3D grid or
+    fewer than 16 along the tile axis of a 2D one, and a matrix that is no grid all get
+    none; a 2D grid with enough columns gets one."""
     A = synth.poisson3d(16)
     F1 = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 1)
     assert _plan.make_grid_plan(F1, False, (16, 16, 16)) is None
@@ -581,7 +586,10 @@ def test_grid_plan_refusals():
     assert _plan.make_grid_plan(F0, False, (16, 16, 16)) is not None
     A2 = synth.poisson2d(64)
     F2 = O.iluk(A2.n, A2.Ap, A2.Aj, A2.Ax, 0)
-    assert _plan.make_grid_plan(F2, False, (64, 64, 1)) is None
+    assert _plan.make_grid_plan(F2, False, (64, 64, 1)) is not None
+    A4 = synth.lognormal_tpfa((12, 90, 1), 1.0, np.random.default_rng(4))
+    F4 = O.iluk(A4.n, A4.Ap, A4.Aj, A4.Ax, 0)
+    assert _plan.make_grid_plan(F4, False, (12, 90, 1)) is None
     A3 = synth.lognormal_tpfa((7, 30, 30), 1.0, np.random.default_rng(3))
     F3 = O.iluk(A3.n, A3.Ap, A3.Aj, A3.Ax, 0)
     assert _plan.make_grid_plan(F3, False, (7, 30, 30)) is None
