@@ -7,7 +7,10 @@
   bit-exact, preconditioner solve within 1e-12 of the oracle (1e-4 from the FP32
   factor copy; these plans take two solver wavefronts per part), and the FP64 and
   mixed-precision GMRES solutions checked by their FP64 true residual (1e-10)
-  computed with the oracle's SpMV.
+  computed with the oracle's SpMV;
+* 2D lognormal diffusion 1000 x 1000 (n = 1,000,000), ILU(0): the wavefront
+  preconditioner solve with 64 x 1 tiles within 1e-12 of the oracle's substitution,
+  componentwise on sampled rows, and within 1e-4 from the FP32 factor copy.
 """
 import numpy as np
 import pytest
@@ -103,3 +106,46 @@ def test_aniso_gmres_reaches_1e10(aniso, precision):
           f"rel_res {rr:.3e} |x-x_true|/|x_true| {np.linalg.norm(xh - xt) / np.linalg.norm(xt):.3e} "
           f"{info['seconds']:.2f}s")
     assert info["status"] == hec.OK and rr <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def plane():
+    A = synth.lognormal_tpfa((1000, 1000, 1), 2.0, np.random.default_rng(12))
+    M = hec.ilu_factor(A, k=0, keep_f32=True)
+    lv = hec.level_schedule(M)
+    return A, O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0), M, lv
+
+
+def test_plane_1000_wavefront_trsv(plane):
+    """The largest 2D requests of the serving trace (1000 x 1000, ILU(0)): the wavefront
+    solve with 64 x 1 tiles (16 along x, the last one ragged) against the oracle's
+    substitution, lone triangles and the L-then-U chain, FP64 within 1e-12 (and
+    componentwise on sampled rows: the residual of row i against the exact products of
+    its own entries) and from the FP32 copy within 1e-4."""
+    import torch
+    A, Fo, M, lv = plane
+    assert hec.levels_grid(lv)
+    g = hec.levels_export(lv)
+    assert (g["nlev_lower"], g["nlev_upper"]) == (1999, 1999)
+    r = np.random.default_rng(13).uniform(-1, 1, A.n)
+    y_o = O.trsv_lower(Fo, r)
+    x_o = O.trsv_upper(Fo, y_o)
+    y, x, x1 = empty(A.n), empty(A.n), empty(A.n)
+    hec.trsv_levels(M, lv, dev(r), y, hec.LOWER)
+    hec.trsv_levels(M, lv, dev(r), x, hec.LU)
+    hec.trsv_levels(M, lv, dev(y_o), x1, hec.UPPER)
+    hec.levels_check(lv)
+    y, x, x1 = host(y), host(x), host(x1)
+    for got, ref in ((y, y_o), (x, x_o), (x1, x_o)):
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    rows = np.random.default_rng(14).choice(A.n, 2000, replace=False)
+    for i in rows:  # row i of L y = r (unit diagonal): |r_i - y_i - sum l_ij y_j| within the rounding of its terms
+        lo, hi = Fo.LUp[i], Fo.LUp[i + 1]
+        cols, vals = Fo.LUj[lo:hi], Fo.LUx[lo:hi]
+        low = cols < i
+        res = r[i] - y[i] - np.dot(vals[low], y[cols[low]])
+        assert abs(res) <= 2 * 4 * U64 * (abs(r[i]) + abs(y[i]) + np.dot(np.abs(vals[low]), np.abs(y[cols[low]])))
+    x32 = empty(A.n, "f32")
+    hec.trsv_levels(M, lv, dev(r, torch.float32), x32, hec.LU)
+    hec.levels_check(lv)
+    assert np.linalg.norm(host(x32).astype(np.float64) - x_o) <= 1e-4 * np.linalg.norm(x_o)
