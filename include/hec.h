@@ -236,12 +236,13 @@ hec_status hec_set_spin_limit(int64_t polls);
 
 /* Chooses the triangular-solve kernel of the schedules level_schedule builds after
  * the call (from any thread). With enable = 1 (the default), a factor on a
- * natural-order 3D grid (detected from A) whose strict triangles hold only the
- * three grid neighbours behind each row, as ILU(0) of a 7-point stencil does
- * (Sec. 2.6: the level of a row is then the sum of its coordinates, Eq. (11)),
- * gets wavefront plans for both triangles: tiles of 8 x 8 grid columns, one
- * wavefront each, whose lanes step through the levels together, passing results
- * between neighbouring lanes through LDS. Every other factor, and every factor
+ * natural-order 3D or 2D grid (detected from A) whose strict triangles hold only
+ * the grid neighbours behind each row, as ILU(0) of a 7-point or 5-point stencil
+ * does (Sec. 2.6: the level of a row is then the sum of its coordinates, Eq. (11)),
+ * gets wavefront plans for both triangles: tiles of 8 x 8 grid columns (3D) or
+ * 64 x 1 (2D, at least 16 columns across), one wavefront each, whose lanes step
+ * through the levels together, passing results between neighbouring lanes through
+ * LDS. Every other factor, and every factor
  * with enable = 0, gets the level-blocked plans. A schedule keeps the kind it was
  * built with (levels_grid reports it). Both kernels perform each row's
  * subtractions (fused multiply-adds) and may differ in rounding only where their
