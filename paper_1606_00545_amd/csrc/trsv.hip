@@ -686,9 +686,10 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront solve of a grid triangle (plan.hpp's GridPlan): one tile of 8 x 8
-// columns per workgroup, tiles claimed in order from a ticket counter (a tile
-// only waits for tiles claimed before it, held by running workgroups).
+// Wavefront solve of a grid triangle (plan.hpp's GridPlan): one tile of TA x TB
+// columns per workgroup (8 x 8 on a 3D grid, which the description below follows;
+// 64 x 1 on a 2D grid), tiles claimed in order from a ticket counter (a tile only
+// waits for tiles claimed before it, held by running workgroups).
 //  * Wavefront 0 solves. At step s lane (ma, mb) solves the row at c-index
 //    s - ma - mb of its column; that row's dependencies were solved at step s - 1:
 //    the one behind it along c by the lane itself (a register), the ones along a
@@ -705,7 +706,7 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
 //    multiply-adds. Steps run as unrolled blocks of 8 with ring offsets fixed at
 //    compile time and one release per block: about 20 instructions a step where a
 //    whole tile's 64 rows are all valid for the 8 steps (the bulk of a long column),
-//    a few more with validity masks elsewhere (0.12 us a step against 0.19 us for
+//    a few more with validity masks elsewhere (0.13 us a step against 0.19 us for
 //    the general step, which only a column's last, partial block takes).
 //  * Wavefronts 1..kGridPollers poll the tile's incoming face values (8 on the
 //    a-face, 8 on the b-face per step) for a window of the next 4 * HEC_GRID_POLL_R
@@ -713,12 +714,14 @@ __global__ __launch_bounds__(256) void k_trsv_sf(int32_t nchunks, const int32_t 
 //    not the sentinel, write each into its step's grid, and raise the count of
 //    leading steps that have all of theirs. (Several pollers would poll the same
 //    window independently; a wider window or more pollers send more device-coherent
-//    loads, which slowed the 128^3 solve: 209 us for the lower triangle with 16
-//    steps and 3 pollers, 157 us with 4 steps and 1.)
+//    loads, and a poll takes longer the more lines it reads: at 128^3 every wider
+//    window or second poller measured slower.) A 2D tile's poller polls its one
+//    face value per step, 32 steps at a time.
 //  * The other wavefronts load the coefficients (packed by claim, step and lane, so
 //    every load is a whole line) and the right-hand side of runs of steps into a
 //    ring of LDS slots. They depend on nothing but the ring, so they run ahead.
-//  * The solver stores each result to the output by row and, on the tile's high
+//  * The solver stores each result to the output (by row, or in padded tile-step
+//    order for the intermediate of an L-then-U chain) and, on the tile's high
 //    faces, to the face buffer with a device-coherent store, at the index of the
 //    step at which the next tile needs it (the corner lane's value only on the
 //    a-face, where the tile above also reads it).
