@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes moved by one preconditioner solve (lower + upper launch) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
-TRSV_PAIR_TRAFFIC = 233961692  # k_trsv_grid lower + upper (profiles/gmres_ilu0_tpfa128_hbm_counters.md)
+TRSV_PAIR_TRAFFIC = 235111904  # k_trsv_grid lower + upper (profiles/gmres_ilu0_tpfa128_hbm_counters.md)
 
 
 def parse():
@@ -303,7 +303,7 @@ def main():
     trsv_share = t_trsv_lu * it_per_solve / (ms_per_step / 1e3)
 
     grid = hec.levels_grid(lv)  # the wavefront kernel (7-point ILU(0) on a grid) or the level-blocked one
-    kname = ("k_trsv_grid<double,false> + k_trsv_grid<double,true>" if grid else
+    kname = ("k_trsv_grid<double,false,8> + k_trsv_grid<double,true,8>" if grid else
              "k_trsv_blk<double,false,4> + k_trsv_blk<double,true,4>")
     roof = {"kernel": kname + " (one preconditioner solve: the lower and the upper launch)",
             "bound": "hbm", "achieved": round(trsv_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
