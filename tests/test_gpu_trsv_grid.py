@@ -21,10 +21,11 @@ U64 = 2.0 ** -53
 # one tile with a ragged second one, the smallest grid with a plan, long columns (many
 # steps at which every lane of a whole tile has a row, next to ragged tiles); 2D grids
 # (64 x 1 tiles): one tile, three along x with a ragged last (columns along y), two
-# along y (columns along x), and one tile with 20 of its 64 lanes in the grid
+# along y (columns along x), and single tiles with 20 and with 16 (the fewest) of their
+# 64 lanes in the grid
 SHAPES = [((24, 24, 24), 1), ((19, 13, 30), 2), ((41, 37, 23), 3), ((13, 45, 16), 4), ((9, 8, 10), 5),
           ((8, 8, 8), 6), ((19, 13, 70), 7), ((64, 64, 1), 8), ((130, 200, 1), 9), ((150, 70, 1), 10),
-          ((20, 33, 1), 11)]
+          ((20, 33, 1), 11), ((16, 300, 1), 12)]
 
 
 @pytest.fixture(scope="module")

@@ -544,7 +544,8 @@ def replay_grid(G, F, rhs, upper):
 
 @pytest.mark.parametrize("shape,exact", [((24, 24, 24), True), ((19, 13, 30), True), ((41, 37, 23), False),
                                          ((8, 9, 8), False), ((9, 8, 10), True), ((64, 64, 1), True),
-                                         ((40, 100, 1), True), ((130, 200, 1), True), ((150, 70, 1), False)])
+                                         ((40, 100, 1), True), ((130, 200, 1), True), ((150, 70, 1), False),
+                                         ((16, 300, 1), True)])
 def test_grid_plan_replay(shape, exact):
     """Wavefront plans of ILU(0) triangles of 7-point grids (8 x 8 tiles) and 5-point 2D
     grids (64 x 1 tiles), tiles ragged where the extents are not multiples of the tile
