@@ -598,3 +598,42 @@ def test_grid_plan_refusals():
     FR = O.iluk(R.n, R.Ap, R.Aj, R.Ax, 0)
     assert _plan.make_grid_plan(FR, False, (16, 16, 16)) is None  # wrong offsets for this "grid"
     assert _plan.make_grid_plan(FR, False, (0, 0, 0)) is None
+
+
+def _plan_rows(G, upper):
+    """Row of every padded position (claim, step, lane) of a wavefront plan, -1 where the
+    lane holds no row: the plan's own geometry (tiles claimed in order, mirrored for the
+    upper triangle), written out independently of the kernel."""
+    NA, NB, NC, PA, PB, S, TA, TB = (G[k] for k in ("NA", "NB", "NC", "PA", "PB", "S", "TA", "TB"))
+    lane = np.arange(64)
+    ma, mb = lane % TA, lane // TA
+    out = np.full((PA * PB, S, 64), -1, np.int64)
+    for c in range(PA * PB):
+        mta, mtb = c % PA, c // PA
+        ta, tb = (PA - 1 - mta, PB - 1 - mtb) if upper else (mta, mtb)
+        ga = ta * TA + ((TA - 1 - ma) if upper else ma)
+        gb = tb * TB + ((TB - 1 - mb) if upper else mb)
+        for s in range(S):
+            mc = s - ma - mb
+            gc = (NC - 1 - mc) if upper else mc
+            ok = (ga < NA) & (gb < NB) & (mc >= 0) & (mc < NC)
+            out[c, s, ok] = ga[ok] * G["sa"] + gb[ok] * G["sb"] + gc[ok] * G["sc"]
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [(19, 13, 30), (9, 8, 10), (130, 200, 1), (150, 70, 1)])
+def test_padded_tile_step_order_is_mirrored_between_triangles(shape):
+    """The L-then-U chain hands its intermediate over in the lower plan's padded order
+    (claim * S + step) * 64 + lane: the lower launch writes row r there, and the upper
+    launch reads the row it solves at its own (claim, step, lane) from position
+    total - 1 - ((claim * S + step) * 64 + lane). That is right only if both name the same
+    row, and every row has exactly one position."""
+    A = synth.lognormal_tpfa(shape, 2.0, np.random.default_rng(23))
+    F = O.iluk(A.n, A.Ap, A.Aj, A.Ax, 0)
+    grid = _plan.detect_grid(A)
+    GL, GU = _plan.make_grid_plan(F, False, grid), _plan.make_grid_plan(F, True, grid)
+    assert all(GL[k] == GU[k] for k in ("PA", "PB", "S", "TA", "TB"))
+    low, up = _plan_rows(GL, False), _plan_rows(GU, True)
+    assert np.array_equal(up, low[::-1])
+    held = low[low >= 0]
+    assert held.size == A.n and np.array_equal(np.sort(held), np.arange(A.n))
