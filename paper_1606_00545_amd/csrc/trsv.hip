@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                     if (w + k > pub) {
                         pub = min(w + k, G.S);
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // after this wave's writes
-                        if (lane == 0) __hip_atomic_fetch_max(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (lane == 0) __hip_atomic_store(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         it = 0;
                     } else {
                         if (spun_out(it, true)) break;
@@ -1144,18 +1144,33 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_trsv_grid(GridArgs G, const
                     okm[r] = __ballot(wr[r] || st >= G.S);
                 }
                 int k = 0;  // leading steps of the window with all their values
-                bool gap = false;
+                if constexpr (R == 1) {
+                    uint64_t t = okm[0];  // bit 16 q ends up set when all 16 lanes of step w + q are in
+                    t &= t >> 8;
+                    t &= t >> 4;
+                    t &= t >> 2;
+                    t &= t >> 1;
+                    const uint32_t g = (uint32_t)((t & 1) | ((t >> 15) & 2) | ((t >> 30) & 4) | ((t >> 45) & 8));
+                    k = __builtin_ctz(~g);
+                } else {
+                    bool gap = false;
 #pragma unroll
-                for (int r = 0; r < R; ++r)
+                    for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int qq = 0; qq < 4; ++qq) {
-                        gap = gap || ((okm[r] >> (16 * qq)) & 0xFFFFull) != 0xFFFFull;
-                        k += gap ? 0 : 1;
-                    }
+                        for (int qq = 0; qq < 4; ++qq) {
+                            gap = gap || ((okm[r] >> (16 * qq)) & 0xFFFFull) != 0xFFFFull;
+                            k += gap ? 0 : 1;
+                        }
+                }
                 if (w + k > pub) {
                     pub = min(w + k, G.S);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // after this wave's writes
-                    if (lane == 0) __hip_atomic_fetch_max(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (lane == 0) {  // one poller: its count only grows; several: the largest
+                        if constexpr (kGridPollers == 1)
+                            __hip_atomic_store(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        else
+                            __hip_atomic_fetch_max(s_faces, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                     it = 0;
                 } else {
                     if (spun_out(it, true)) break;
