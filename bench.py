@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes moved by one preconditioner solve (lower + upper launch) on the 128^3 system, measured with
 # rocprofv3 FETCH_SIZE and WRITE_SIZE and scaled by the counts of a plain 1 GiB copy; valid for the kernels
 # as they are -- reset to None whenever the solve kernels change until the counters are taken again.
-TRSV_PAIR_TRAFFIC = 235111904  # k_trsv_grid lower + upper (profiles/gmres_ilu0_tpfa128_hbm_counters.md)
+TRSV_PAIR_TRAFFIC = 234725554  # k_trsv_grid lower + upper (profiles/gmres_ilu0_tpfa128_hbm_counters.md)
 
 
 def parse():
